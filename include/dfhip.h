@@ -1,0 +1,284 @@
+/*
+ * dfhip.h - C ABI of the dynamic-data-rate actor library for AMD MI355X (gfx950).
+ *
+ * Implements batched firing of GPU-mapped actors whose token consumption and
+ * production per firing are fixed by control tokens (Boutellier & Hautala,
+ * "Executing Dynamic Data Rate Actor Networks on OpenCL Platforms", SiPS 2016,
+ * Sec. 2.2 and 3).  An application is a network of actors and FIFO channels
+ * (Sec. 2.2); it is built by calls to this API (Sec. 3.4: the network is
+ * described by a C function calling the framework's library).
+ *
+ * General conventions
+ *   - Every call returns df_status; DF_OK (0) on success, a negative code
+ *     otherwise.  No exception or signal crosses this boundary.  After an
+ *     error, df_last_error() gives a human-readable reason.
+ *   - All device work of a graph is ordered on the graph's HIP stream.
+ *   - Device-side FIFO read/write indices are authoritative; kernels read
+ *     them from device memory, so batches can be enqueued (and captured in
+ *     a HIP graph) without host round trips.
+ *   - A graph is used from one host thread at a time.  Distinct graphs are
+ *     independent.
+ *   - A HIP runtime failure poisons the graph: every later call on it
+ *     returns DF_EDEVICE.
+ *   - Pointers marked "device" must point to memory of the graph's device;
+ *     "host" pointers to ordinary host memory.  The caller keeps ownership
+ *     of every buffer it passes; the library owns FIFO storage and actor
+ *     state and frees them in df_graph_destroy.
+ */
+#ifndef DFHIP_H
+#define DFHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct df_graph df_graph;
+typedef int32_t df_status;
+
+enum {
+  DF_OK = 0,
+  DF_EINVAL = -1,    /* bad argument, handle, port, size or token value          */
+  DF_EAGAIN = -2,    /* not enough tokens or space for an all-or-nothing firing;
+                        nothing changed                                          */
+  DF_ENOMEM = -3,    /* device or host allocation failed                         */
+  DF_ESTATE = -4,    /* call not valid in the current wiring / state             */
+  DF_EDEVICE = -5,   /* HIP runtime error; the graph is poisoned                 */
+  DF_ECONTROL = -6   /* a control token read on the device was out of range
+                        (sticky; reported by df_sync / df_fifo_status)           */
+};
+
+typedef enum { DF_C64 = 1, DF_U8 = 2, DF_I32 = 3, DF_I64 = 4 } df_dtype;
+
+typedef enum { DF_ACTOR_DPD = 1, DF_ACTOR_MOTION = 2 } df_actor_kind;
+
+/* Ports of the predistortion actor. */
+enum { DF_DPD_CTRL = 0, DF_DPD_IN = 1, DF_DPD_OUT = 2 };
+/* Ports of the motion actor. */
+enum { DF_MD_CUR = 0, DF_MD_PREV = 1, DF_MD_MASK = 2, DF_MD_INDEX = 3 };
+
+/* FIR history of a predistortion branch across firings where it is inactive. */
+enum {
+  DF_HIST_BRANCH = 0, /* a branch's delay line advances only when the branch
+                         fires: after a gap its history is the tail of its own
+                         last active firing (the dataflow reading of Sec. 2.2
+                         for separate FIR actors selected per firing, Sec. 4.2) */
+  DF_HIST_SHARED = 1  /* every branch's history is the true input stream       */
+};
+
+/* df_fire flags */
+enum { DF_FIRE_PARTIAL = 1 };  /* fire as many firings as are admissible (<= n) */
+/* df_fire_many flags */
+enum { DF_FIRE_PERSISTENT = 1, DF_FIRE_GRAPH = 2 };
+
+/*
+ * Predistortion actor (Sec. 4.2).  One firing consumes one control token B
+ * (0 <= B <= n_branches_max) and firing_size samples, and produces
+ * firing_size samples:
+ *     y[t] = sum_{b<B} sum_{m<n_taps} h[b][m] * psi_b(s_b[t-m]),
+ *     psi_b(x) = |x|^(2b) x   (odd order 2b+1),
+ * where s_b is branch b's input sample stream under history_mode.  Branches
+ * b >= B have token rate 0 in this firing (Sec. 2.2: a dynamic actor's
+ * regular ports take rate 0 or r per firing, fixed by the control token).
+ * Constraint: firing_size >= n_taps - 1.
+ */
+typedef struct {
+  int32_t n_branches_max;   /* 1..16                                            */
+  int32_t n_taps;           /* 1..32                                            */
+  int64_t firing_size;      /* r: samples consumed and produced per firing      */
+  const void *coeffs;       /* complex64 [n_branches_max][n_taps], row-major,
+                               host or device (coeffs_on_device); copied        */
+  int32_t coeffs_on_device;
+  int32_t history_mode;     /* DF_HIST_BRANCH or DF_HIST_SHARED                 */
+} df_dpd_params;
+
+/*
+ * Motion actor (frame difference, threshold, 3x3 opening; Sec. 4.1 builds
+ * motion detection from consecutive-frame subtraction with a threshold, the
+ * previous frame arriving over a channel with one initial token).  One
+ * firing consumes one frame from CUR and one from PREV and computes
+ *     changed = |cur - prev| > diff_threshold,
+ *     o = dilate3x3(erode3x3(changed))  (out-of-frame neighbours ignored),
+ *     count = number of set pixels of o.
+ * It produces one MASK token (u8 frame, 255 where o is set) and one INDEX
+ * token (int64 frame number, counted from the actor's first firing) iff
+ * 1000*count >= min_changed_permille*width*height; otherwise it produces no
+ * output token (rate 0 on both output ports).
+ * With self_delay = 1 the PREV port is not used: the actor keeps the
+ * previous CUR frame as state (an all-zero frame before the first firing),
+ * which equals a PREV channel fed the same frames with one zero initial token.
+ */
+typedef struct {
+  int32_t width, height;            /* token = width*height bytes             */
+  int32_t diff_threshold;           /* 25 in the reference workload           */
+  int32_t min_changed_permille;     /* 1 => 0.1 % of the pixels               */
+  int32_t self_delay;               /* 0: PREV port wired; 1: internal delay  */
+} df_motion_params;
+
+/* ------------------------------------------------------------------ graph */
+
+/* Create an empty network on HIP device `hip_device`.  `hip_stream` is a
+ * hipStream_t to order all work on (e.g. torch's current stream), or NULL
+ * for a library-owned stream.  *g receives the handle. */
+df_status df_graph_create(df_graph **g, int hip_device, void *hip_stream);
+
+/* Synchronise, free all FIFO storage, actor state and the owned stream. */
+df_status df_graph_destroy(df_graph *g);
+
+/* Wait for all enqueued work; report sticky device errors (DF_ECONTROL). */
+df_status df_sync(df_graph *g);
+
+/* Reason for the last failing call on g (static storage, never NULL). */
+const char *df_last_error(const df_graph *g);
+
+/* Library version string, e.g. "dfhip 0.1 gfx950". */
+const char *df_version(void);
+
+/* ------------------------------------------------------------------ FIFOs */
+
+/* Create an order-preserving channel (Sec. 3.2) as a device ring of
+ * capacity_tokens tokens (rounded up to a power of two; 0 picks
+ * max(2*n_initial, 1024)) of elems_per_token elements of type dt.
+ * n_initial delay tokens are present before any firing (Sec. 2.2; the paper
+ * allows 0 or 1, any number is accepted here): their values are read from
+ * initial_host (host, n_initial tokens) or are zero when it is NULL.
+ * *fifo_out receives the channel id.
+ * Errors: DF_EINVAL (bad dtype/sizes, n_initial > capacity), DF_ENOMEM. */
+df_status df_fifo_create(df_graph *g, df_dtype dt, int64_t elems_per_token,
+                         int64_t capacity_tokens, int64_t n_initial,
+                         const void *initial_host, int32_t *fifo_out);
+
+/* Token counts of a channel.  Synchronises when the producer's rate is
+ * data-dependent (the device indices are read back).  read/write indices
+ * count tokens since creation; initial tokens occupy write indices
+ * 0..n_initial-1.  Any output pointer may be NULL. */
+df_status df_fifo_status(df_graph *g, int32_t fifo, int64_t *read_idx,
+                         int64_t *write_idx, int64_t *capacity);
+
+/* ------------------------------------------------------------------ actors */
+
+/* Create an actor of `kind` with a parameter struct (df_dpd_params or
+ * df_motion_params; params_size = sizeof that struct).  The actor's init
+ * (Sec. 3.1) runs here: coefficients are copied, state zeroed.
+ * Errors: DF_EINVAL (bad kind, size or parameter). */
+df_status df_actor_create(df_graph *g, df_actor_kind kind, const void *params,
+                          size_t params_size, int32_t *actor_out);
+
+/* Connect an actor port to a channel.  A channel connects exactly one output
+ * port to exactly one input port (Sec. 3.2); the host is the implicit writer
+ * of channels no actor writes and the implicit reader of channels no actor
+ * reads.  Token shape and dtype must match the port.  A channel with initial
+ * tokens cannot feed a control port (Sec. 2.2).
+ * Errors: DF_EINVAL (bad ids, port, dtype or token size), DF_ESTATE (port or
+ * channel end already connected, initial tokens on a control channel). */
+df_status df_connect(df_graph *g, int32_t actor, int32_t port, int32_t fifo);
+
+/* ------------------------------------------------------------------ tokens */
+
+/* Append n_tokens tokens from src (host, or device when src_on_device) to a
+ * channel the host writes.  A host push has finished reading src when the
+ * call returns; a device push is stream-ordered (keep src alive until
+ * df_sync).  Tokens written to a DPD control channel are checked to lie in
+ * 0..n_branches_max (host pushes only).
+ * Errors: DF_EAGAIN (not enough space; nothing written), DF_EINVAL (bad
+ * token value, n_tokens < 0), DF_ESTATE (an actor writes this channel). */
+df_status df_push(df_graph *g, int32_t fifo, const void *src, int64_t n_tokens,
+                  int src_on_device);
+
+/* Remove up to max_tokens tokens from a channel the host reads into dst
+ * (host, or device when dst_on_device); *n_popped receives the number
+ * moved.  A host pop has completed when the call returns; a device pop is
+ * stream-ordered.  Errors: DF_ESTATE (an actor reads this channel). */
+df_status df_pop(df_graph *g, int32_t fifo, void *dst, int64_t max_tokens,
+                 int dst_on_device, int64_t *n_popped);
+
+/* ------------------------------------------------------------------ firing */
+
+/* Fire `actor` n_firings times, in order, as one batch (Sec. 2.2 firing rule
+ * applied to every firing; the batch is a schedule of the same firings, so
+ * results equal firing them one by one).  The batch runs as device kernels:
+ * control intake and rate resolution, an offset scan over the per-firing
+ * rates, the actor body, and a commit of the channel indices.
+ * Reads and writes of the paper are blocking (Sec. 2.2); here admission is
+ * all-or-nothing: if the statically known token counts (control tokens,
+ * input tokens, worst-case output space) do not allow n_firings firings the
+ * call returns DF_EAGAIN and changes nothing, unless flags has
+ * DF_FIRE_PARTIAL, which fires the admissible prefix.  *n_fired (may be
+ * NULL) receives the number fired.  Out-of-range control tokens found on the
+ * device raise the sticky DF_ECONTROL and are treated as 0.
+ * Errors: DF_EINVAL, DF_ESTATE (ports not all connected), DF_EAGAIN. */
+df_status df_fire(df_graph *g, int32_t actor, int64_t n_firings, int flags,
+                  int64_t *n_fired);
+
+/* Fire many predistortion actors, actor[i] n_firings[i] times each (host
+ * arrays of n_actors entries), as one batch of independent instances.
+ * flags = 0: one df_fire per actor.  DF_FIRE_PERSISTENT: one persistent
+ * kernel whose workgroups pull (instance, firing, tile) work items from a
+ * device queue built by a segmented offset scan.  DF_FIRE_GRAPH (with
+ * PERSISTENT): the scan -> persistent kernel -> commit chain is captured
+ * once in a HIP graph for this actor list and replayed on later calls.
+ * Admission is all-or-nothing over all instances (DF_EAGAIN).
+ * Errors: DF_EINVAL (not DPD actors, duplicates, mixed n_taps), DF_ESTATE. */
+df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *actors,
+                       const int64_t *n_firings, int flags);
+
+/* Tile configuration of the DPD body kernels: tile_outputs samples per
+ * workgroup work item (a multiple of 64*outputs_per_thread, at most
+ * 512*outputs_per_thread), outputs_per_thread (4 or 8), and the persistent
+ * kernel's workgroups per compute unit (1..16).  0 keeps the current value.
+ * Used by the autotuner.  Errors: DF_EINVAL. */
+df_status df_set_tile(df_graph *g, int32_t tile_outputs, int32_t outputs_per_thread,
+                      int32_t blocks_per_cu);
+
+/* Test hook: per-firing tables of the last batch of a DPD actor (device
+ * results copied to host arrays of at least cap entries per row):
+ * rates [n_branches_max][n], offsets [n_branches_max][n] (token offset of
+ * the firing's block on branch b's channel), prev [n_branches_max][n] (the
+ * firing whose tail is branch b's FIR history, -1: carried state);
+ * *n_out receives n.  Any array pointer may be NULL. */
+df_status df_debug_last_batch(df_graph *g, int32_t actor, int32_t *rates,
+                              int64_t *offsets, int64_t *prev, int64_t cap,
+                              int64_t *n_out);
+
+/* ------------------------------------------------------- stateless kernels */
+/* Device-pointer entry points used by the autograd binding.  All run on
+ * `stream` (a hipStream_t, NULL = default stream) and do not synchronise.
+ * Each of the n_streams rows of length len is an independent predistortion
+ * actor fired len/r times from zero state with no delay tokens.  ctrl is
+ * int32 [n_streams][len/r] control tokens, or NULL for all branches active
+ * in every firing.  x, y, G: complex64 [n_streams][len]; h, grad_h:
+ * complex64 [B_max][M].  len must be a multiple of r, r >= M-1.
+ * Errors: DF_EINVAL (sizes), DF_EDEVICE (launch failure). */
+
+/* y = DPD_h(x) (the predistortion actor body above). */
+df_status df_dpd_forward(void *stream, const void *x, const int32_t *ctrl,
+                         const void *h, void *y, int64_t n_streams, int64_t len,
+                         int64_t r, int32_t B_max, int32_t M, int32_t hist);
+
+/* Coefficient adjoint: grad_h[b][m] = sum over rows and samples n of
+ * G[n] * conj(d y[n] / d h[b][m]), i.e. dL/dRe h + i dL/dIm h given
+ * G[n] = dL/dRe y[n] + i dL/dIm y[n].  Deterministic (fixed reduction
+ * order, no floating-point atomics).  grad_h is overwritten.
+ * `work` is a device buffer of df_dpd_coeff_adjoint_work_bytes() bytes. */
+df_status df_dpd_coeff_adjoint(void *stream, const void *x, const int32_t *ctrl,
+                               const void *G, void *grad_h, int64_t n_streams,
+                               int64_t len, int64_t r, int32_t B_max, int32_t M,
+                               int32_t hist, void *work, int64_t work_bytes);
+int64_t df_dpd_coeff_adjoint_work_bytes(int64_t n_streams, int64_t len, int64_t r,
+                                        int32_t B_max, int32_t M);
+
+/* Memory-polynomial input adjoint.  For v[n] = sum_k sum_q a[k][q]
+ * |u[n-q]|^(2k) u[n-q] (a: complex64 [K][Q], orders 1,3,..,2K-1) and an
+ * upstream gradient g = dL/dRe v + i dL/dIm v, writes
+ * Gu = dL/dRe u + i dL/dIm u (Wirtinger chain rule).  u, g, Gu: complex64
+ * [n_streams][len]; samples past a row's end contribute nothing. */
+df_status df_mp_input_adjoint(void *stream, const void *u, const void *a,
+                              const void *g, void *Gu, int64_t n_streams,
+                              int64_t len, int32_t K, int32_t Q);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFHIP_H */

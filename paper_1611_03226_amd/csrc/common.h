@@ -1,0 +1,143 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dfh {
+
+constexpr int kMaxBranches = 16;
+constexpr int kMaxTaps = 32;
+
+// Sticky device error bits (an int32 in device memory per graph).
+enum : int32_t { kErrControl = 1, kErrIndex = 2 };
+
+// ---------------------------------------------------------------- DPD
+//
+// One batch of predistortion firings.  Firing g (0 <= g < n_firings) reads
+// r input samples starting at sample position xpos(g) and writes r output
+// samples at ypos(g):
+//   actor mode:      xpos(g) = R_x + g*r (ring, masked), ypos(g) = W_y + g*r
+//   stateless mode:  xpos(g) = g*r, ypos(g) = g*r (rows of length
+//                    seg_firings*r concatenated; no wrap: mask = -1)
+// B[g] is the firing's validated branch count (nullptr: B_const).
+// prev[b*prev_stride + g] is the firing whose tail is branch b's FIR history
+// (-1: carried state `hist` [b][M-1], nullptr history = zeros).  With
+// prev == nullptr the history firing is g-1 inside its segment of
+// seg_firings firings and -1 at a segment start.
+struct DpdArgs {
+  const float2 *x;
+  const int64_t *x_idx;   // device [read, write] or nullptr (position 0)
+  int64_t x_mask;
+  float2 *y;
+  const int64_t *y_idx;   // device [read, write] or nullptr
+  int64_t y_mask;
+  const float2 *h;        // [B_max][M]
+  const float2 *hist;     // [B_max][M-1] or nullptr
+  const int32_t *B;       // [n_firings] or nullptr
+  int32_t B_const;
+  const int64_t *prev;    // [B_max][prev_stride] or nullptr
+  int64_t prev_stride;
+  int64_t seg_firings;
+  int64_t n_firings;
+  int64_t r;
+  int32_t B_max;
+  int32_t M;
+  int32_t tile;           // outputs per workgroup (tiled kernel)
+  int32_t tiles_per_firing;
+};
+
+// Control intake + offset scan over segments of firings (one workgroup per
+// segment, one wavefront per branch).
+struct ScanArgs {
+  const int32_t *ctrl;    // control tokens (ring or linear)
+  const int64_t *ctrl_idx;// device [read, write] or nullptr (position 0)
+  int64_t ctrl_mask;      // ring mask, -1 for linear
+  int64_t seg_firings;    // firings per segment
+  int32_t n_segs;
+  int32_t B_max;
+  int32_t hist_mode;      // 0 branch, 1 shared
+  int32_t *B_out;         // [n_segs*seg_firings]
+  int64_t *prev_out;      // [B_max][stride]
+  int64_t *off_out;       // [B_max][stride] (may be nullptr)
+  int64_t *last_out;      // [n_segs][B_max] (may be nullptr)
+  int64_t stride;
+  int64_t r;
+  int32_t *err;           // sticky error word (may be nullptr)
+};
+
+struct DpdCommitArgs {
+  const float2 *x;
+  int64_t *x_idx;
+  int64_t x_mask;
+  int64_t *ctrl_idx;
+  int64_t *y_idx;
+  float2 *hist;           // [B_max][M-1]
+  const int64_t *last;    // [B_max]
+  int64_t n_firings;
+  int64_t r;
+  int32_t B_max;
+  int32_t M;
+};
+
+// ---------------------------------------------------------------- motion
+struct MotionArgs {
+  const uint8_t *cur;     // ring of frames
+  const int64_t *cur_idx;
+  int64_t cur_mask;
+  const uint8_t *prev;    // ring of frames (two-channel form) or nullptr
+  const int64_t *prev_idx;
+  int64_t prev_mask;
+  const uint8_t *state;   // previous frame (self-delay form)
+  uint8_t *out;           // mask ring
+  const int64_t *out_idx;
+  int64_t out_mask;
+  int64_t *index_out;     // index ring
+  const int64_t *index_idx;
+  int64_t index_mask;
+  int32_t *count;         // [n] opened-mask counts
+  const int64_t *emit_off;// [n+1] exclusive scan of emit flags (emit pass)
+  uint32_t *bits;         // bit-packed opened masks [n][H][W/32] (count pass)
+  int64_t n;
+  int64_t frame_base;     // global index of firing 0
+  int32_t W, H, thr;
+  int32_t permille;
+  int32_t words_per_row;  // W/32 rounded up
+};
+
+// ---------------------------------------------------------------- adjoint
+// Coefficient adjoint over firings laid out as in DpdArgs' stateless mode.
+struct AdjArgs {
+  const float2 *x;        // [n_firings * r]
+  const float2 *G;        // [n_firings * r]
+  const int32_t *B;       // [n_firings] or nullptr (all B_max branches)
+  const int64_t *prev;    // [B_max][prev_stride] or nullptr
+  int64_t prev_stride;
+  int64_t seg_firings;
+  int64_t n_firings;
+  int64_t r;
+  int32_t B_max;
+  int32_t M;
+  int32_t chunk;          // outputs per workgroup
+  int32_t chunks_per_firing;
+  float2 *partial;        // [n_firings*chunks_per_firing][B_max][M]
+  float2 *grad;           // [B_max][M]
+};
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
+hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread);
+hipError_t launch_dpd_commit(const DpdCommitArgs &a, hipStream_t s);
+hipError_t launch_advance(int64_t *idx, int64_t delta, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_motion_count(const MotionArgs &a, hipStream_t s);
+hipError_t launch_motion_emit_scan(const int32_t *count, int64_t n, int64_t emit_threshold,
+                                   int64_t *emit_off, hipStream_t s);
+hipError_t launch_motion_emit(const MotionArgs &a, hipStream_t s);
+hipError_t launch_adj(const AdjArgs &a, hipStream_t s);
+hipError_t launch_mp_adj(const float2 *u, const float2 *a, const float2 *g, float2 *Gu, int64_t n_streams,
+                         int64_t len, int K, int Q, hipStream_t s);
+hipError_t launch_motion_commit(const int64_t *emit_off, int64_t n, int64_t *cur_idx, int64_t *prev_idx,
+                                int64_t *out_idx, int64_t *index_idx, hipStream_t s);
+
+}  // namespace dfh

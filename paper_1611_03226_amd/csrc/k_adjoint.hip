@@ -1,0 +1,196 @@
+// Adjoints for coefficient adaptation through a memory-polynomial PA.
+//
+// Gradients use the real-pair convention: for complex z, dL/dRe z + i dL/dIm z.
+//
+// Coefficient adjoint of the predistortion actor (y linear in h):
+//   grad_h[b][m] = sum_n G[n] conj(psi_b(s_b[n-m])),  b < B of n's firing.
+// Inside a firing the source sample is branch independent, so with
+// z = G[n] conj(x[n-m]) and p = |x[n-m]|^2 each (n, m) pair feeds all
+// branches through the running power z p^b.  Taps reaching before a firing
+// start read branch b's own history and are added per branch.
+// Reduction: fp32 partial sums per workgroup in a fixed order, then an fp64
+// sum over workgroups in a fixed order (deterministic, no float atomics).
+//
+// Input adjoint of v[n] = sum_k sum_q a[k][q] phi_k(u[n-q]),
+// phi_k(u) = |u|^(2k) u: with d phi/du = (k+1) p^k and
+// d phi/du* = k p^(k-1) u^2 (p = |u|^2),
+//   Gu[n] = sum_q g[n+q] conj(A_q) + conj(g[n+q]) Bw_q u^2,
+//   A_q = sum_k a[k][q] (k+1) p^k,  Bw_q = sum_{k>=1} a[k][q] k p^(k-1).
+#include "common.h"
+
+namespace dfh {
+
+constexpr int ADJ_NT = 256;
+
+__device__ __forceinline__ int64_t adj_prev(const AdjArgs &a, int b, int64_t g) {
+  if (a.prev) return a.prev[(int64_t)b * a.prev_stride + g];
+  return (g % a.seg_firings) ? g - 1 : -1;
+}
+
+template <int BM>
+__global__ __launch_bounds__(ADJ_NT) void k_adj_partial(AdjArgs a) {
+  extern __shared__ float2 lds[];
+  const int M = a.M;
+  const int64_t g = blockIdx.x / a.chunks_per_firing;
+  const int64_t c = blockIdx.x - g * a.chunks_per_firing;
+  const int64_t n0 = c * a.chunk;
+  const int nout = (int)min((int64_t)a.chunk, a.r - n0);
+  const int B = a.B ? a.B[g] : BM;
+  const int64_t xb = g * a.r;
+  float2 *sx = lds;                       // nout + M - 1
+  float2 *sg = lds + a.chunk + M - 1;     // nout
+  float2 *red = sg + a.chunk;             // [groups][BM][M]
+  for (int i = threadIdx.x; i < nout + M - 1; i += ADJ_NT) {
+    const int64_t pos = n0 - (M - 1) + i;
+    sx[i] = pos >= 0 ? a.x[xb + pos] : make_float2(0.f, 0.f);
+  }
+  for (int i = threadIdx.x; i < nout; i += ADJ_NT) sg[i] = a.G[xb + n0 + i];
+  __syncthreads();
+  const int groups = ADJ_NT / M;
+  const int m = threadIdx.x % M;
+  const int grp = threadIdx.x / M;
+  float accr[BM], acci[BM];
+#pragma unroll
+  for (int b = 0; b < BM; ++b) accr[b] = acci[b] = 0.f;
+  if (grp < groups) {
+    for (int i = grp; i < nout; i += groups) {
+      const float2 xv = sx[i + M - 1 - m];
+      const float2 gv = sg[i];
+      const float p = xv.x * xv.x + xv.y * xv.y;
+      float wr = gv.x * xv.x + gv.y * xv.y;          // G conj(x)
+      float wi = gv.y * xv.x - gv.x * xv.y;
+#pragma unroll
+      for (int b = 0; b < BM; ++b) {
+        if (b >= B) break;
+        accr[b] += wr;
+        acci[b] += wi;
+        wr *= p;
+        wi *= p;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < BM; ++b) red[(grp * BM + b) * M + m] = make_float2(accr[b], acci[b]);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < BM * M; t += ADJ_NT) {
+    const int b = t / M, mm = t - b * M;
+    float sr = 0.f, si = 0.f;
+    if (b < B) {
+      for (int q = 0; q < groups; ++q) {
+        const float2 v = red[(q * BM + b) * M + mm];
+        sr += v.x;
+        si += v.y;
+      }
+      if (n0 == 0 && mm > 0) {
+        // taps before the firing start: branch b's history source
+        const int64_t pf = adj_prev(a, b, g);
+        for (int i = 0; i < mm && i < nout; ++i) {
+          const int64_t ii = i - mm;
+          float2 xv = make_float2(0.f, 0.f);
+          if (pf >= 0) xv = a.x[pf * a.r + a.r + ii];
+          const float pp = xv.x * xv.x + xv.y * xv.y;
+          float pb = 1.f;
+          for (int e = 0; e < b; ++e) pb *= pp;
+          const float2 gv = sg[i];
+          const float xr = pb * xv.x, xi = pb * xv.y;
+          sr += gv.x * xr + gv.y * xi;
+          si += gv.y * xr - gv.x * xi;
+        }
+      }
+    }
+    a.partial[(int64_t)blockIdx.x * a.B_max * M + b * M + mm] = make_float2(sr, si);
+  }
+}
+
+// grad_h[b][m] = fp64 sum of the workgroup partials, fixed order.
+__global__ __launch_bounds__(256) void k_adj_reduce(const float2 *partial, int64_t n_blocks, int BM_stride,
+                                                    float2 *grad) {
+  __shared__ double sr[256], si[256];
+  const int e = blockIdx.x;               // b * M + m
+  double ar = 0.0, ai = 0.0;
+  for (int64_t k = threadIdx.x; k < n_blocks; k += 256) {
+    const float2 v = partial[k * BM_stride + e];
+    ar += v.x;
+    ai += v.y;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[e] = make_float2((float)sr[0], (float)si[0]);
+}
+
+hipError_t launch_adj(const AdjArgs &a, hipStream_t s) {
+  const int64_t blocks = a.n_firings * a.chunks_per_firing;
+  if (blocks > 0) {
+    const int groups = ADJ_NT / a.M;
+    const size_t lds = sizeof(float2) * ((size_t)2 * a.chunk + a.M - 1 + (size_t)groups * kMaxBranches * a.M);
+    switch (a.B_max) {
+#define DF_CASE(n) \
+  case n: hipLaunchKernelGGL(k_adj_partial<n>, dim3((unsigned)blocks), dim3(ADJ_NT), lds, s, a); break;
+      DF_CASE(1) DF_CASE(2) DF_CASE(3) DF_CASE(4) DF_CASE(5) DF_CASE(6) DF_CASE(7) DF_CASE(8)
+      DF_CASE(9) DF_CASE(10) DF_CASE(11) DF_CASE(12) DF_CASE(13) DF_CASE(14) DF_CASE(15) DF_CASE(16)
+#undef DF_CASE
+      default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_adj_reduce, dim3(a.B_max * a.M), dim3(256), 0, s, a.partial, blocks, a.B_max * a.M,
+                     a.grad);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ PA input adjoint
+__global__ __launch_bounds__(256) void k_mp_adj(const float2 *u, const float2 *a, const float2 *gin, float2 *Gu,
+                                                int64_t n_streams, int64_t len, int K, int Q) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_streams * len) return;
+  const int64_t s = t / len, n = t - s * len;
+  const float2 uv = u[t];
+  const float p = uv.x * uv.x + uv.y * uv.y;
+  const float u2r = uv.x * uv.x - uv.y * uv.y, u2i = 2.f * uv.x * uv.y;
+  float Gr = 0.f, Gi = 0.f;
+  for (int q = 0; q < Q; ++q) {
+    if (n + q >= len) break;
+    const float2 gq = gin[s * len + n + q];
+    float Ar = 0.f, Ai = 0.f, Br = 0.f, Bi = 0.f;
+    float pk = 1.f, pkm1 = 1.f;                    // p^k, p^(k-1)
+    for (int k = 0; k < K; ++k) {
+      const float2 c = a[k * Q + q];
+      Ar += c.x * (k + 1) * pk;
+      Ai += c.y * (k + 1) * pk;
+      if (k >= 1) {
+        Br += c.x * k * pkm1;
+        Bi += c.y * k * pkm1;
+        pkm1 *= p;
+      }
+      pk *= p;
+    }
+    // gq conj(A)
+    Gr += gq.x * Ar + gq.y * Ai;
+    Gi += gq.y * Ar - gq.x * Ai;
+    // conj(gq) Bw u^2
+    const float wr = Br * u2r - Bi * u2i, wi = Br * u2i + Bi * u2r;
+    Gr += gq.x * wr + gq.y * wi;
+    Gi += gq.x * wi - gq.y * wr;
+  }
+  Gu[t] = make_float2(Gr, Gi);
+}
+
+hipError_t launch_mp_adj(const float2 *u, const float2 *a, const float2 *g, float2 *Gu, int64_t n_streams,
+                         int64_t len, int K, int Q, hipStream_t s) {
+  const int64_t total = n_streams * len;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mp_adj, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, u, a, g, Gu, n_streams,
+                     len, K, Q);
+  return hipGetLastError();
+}
+
+}  // namespace dfh

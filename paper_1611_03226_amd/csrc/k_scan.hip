@@ -1,0 +1,63 @@
+// Control intake, rate resolution and offset scan for a batch of firings.
+//
+// Sec. 2.2: a dynamic actor first consumes one control token, which fixes
+// the rate (0 or r) of each regular port for that firing.  For the
+// predistortion actor the token B activates branches b < B.  From the
+// per-firing rates this pass derives, for every branch b:
+//   off_b(j)  = r * #{i < j : firing i feeds branch b}   (exclusive sum)
+//   prev_b(j) = max{i < j : firing i feeds branch b}     (exclusive max, -1 none)
+//   last_b    = max{i < n : firing i feeds branch b}
+// where "feeds" is B_i > b (branch history) or always (shared history).
+//
+// One workgroup per segment of firings, one wavefront per branch.  A
+// 0/1 feed flag per lane makes both scans a ballot: the exclusive count is
+// the popcount of the ballot bits below the lane, the exclusive max is the
+// highest such bit, carried across 64-firing chunks.
+#include "common.h"
+
+namespace dfh {
+
+__global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
+  const int seg = blockIdx.x;
+  const int b = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t R = a.ctrl_idx ? a.ctrl_idx[0] : 0;
+  const int64_t g0 = (int64_t)seg * a.seg_firings;
+  const uint64_t below_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int64_t count = 0;
+  int64_t lastw = -1;
+  for (int64_t c = 0; c < a.seg_firings; c += 64) {
+    const int64_t j = c + lane;
+    const bool in = j < a.seg_firings;
+    int32_t B = 0;
+    if (in) {
+      int32_t v = a.ctrl[(R + g0 + j) & a.ctrl_mask];
+      if (v < 0 || v > a.B_max) {
+        if (b == 0 && a.err) atomicOr(a.err, (int32_t)kErrControl);
+        v = 0;
+      }
+      B = v;
+      if (b == 0) a.B_out[g0 + j] = B;
+    }
+    const bool fed = in && (a.hist_mode == 1 || B > b);
+    const uint64_t bal = __ballot(fed);
+    const uint64_t below = bal & below_mask;
+    if (in) {
+      const int64_t pv = below ? (c + 63 - __clzll((long long)below)) : lastw;
+      a.prev_out[(int64_t)b * a.stride + g0 + j] = pv >= 0 ? g0 + pv : -1;
+      if (a.off_out)
+        a.off_out[(int64_t)b * a.stride + g0 + j] = a.r * (count + __popcll(below));
+    }
+    count += __popcll(bal);
+    if (bal) lastw = c + 63 - __clzll((long long)bal);
+  }
+  if (lane == 0 && a.last_out) a.last_out[(int64_t)seg * a.B_max + b] = lastw >= 0 ? g0 + lastw : -1;
+}
+
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s) {
+  if (a.n_segs <= 0 || a.seg_firings <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan, dim3(a.n_segs), dim3(64 * a.B_max), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace dfh

@@ -1,0 +1,671 @@
+// Host runtime behind the dfhip.h C ABI: network registry (actors and FIFO
+// channels, Sec. 2.2 / 3.2), all-or-nothing batch admission (the blocking
+// reads and writes of Sec. 2.2), host push/pop, and the kernel chains that
+// fire a batch.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "dfhip.h"
+#include "runtime.h"
+
+using namespace dfh;
+
+static thread_local std::string g_tls_error;
+
+// ------------------------------------------------------------------ errors
+
+df_status dfh::fail(df_graph *g, df_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (g) g->last_error = buf;
+  g_tls_error = buf;
+  return st;
+}
+
+df_status dfh::fail_hip(df_graph *g, hipError_t e, const char *what) {
+  if (g) g->poisoned = true;
+  return fail(g, DF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(g, expr)                                  \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return fail_hip((g), e_, #expr); \
+  } while (0)
+
+#define ENTER(g)                                                          \
+  do {                                                                    \
+    if (!(g)) return fail(nullptr, DF_EINVAL, "null graph");              \
+    if ((g)->poisoned) return fail((g), DF_EDEVICE, "graph poisoned by an earlier HIP error"); \
+    hipError_t e0_ = hipSetDevice((g)->device);                           \
+    if (e0_ != hipSuccess) return fail_hip((g), e0_, "hipSetDevice");     \
+  } while (0)
+
+static int64_t next_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+static int64_t dtype_bytes(int dt) {
+  switch (dt) {
+    case DF_C64: return 8;
+    case DF_U8: return 1;
+    case DF_I32: return 4;
+    case DF_I64: return 8;
+    default: return 0;
+  }
+}
+
+// ------------------------------------------------------------------ graph
+
+extern "C" const char *df_version(void) { return "dfhip 0.1 gfx950"; }
+
+extern "C" const char *df_last_error(const df_graph *g) {
+  if (g) return g->last_error.c_str();
+  return g_tls_error.c_str();
+}
+
+extern "C" df_status df_graph_create(df_graph **out, int device, void *stream) {
+  if (!out) return fail(nullptr, DF_EINVAL, "df_graph_create: null output pointer");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return fail(nullptr, DF_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= n) return fail(nullptr, DF_EINVAL, "device %d out of range (have %d)", device, n);
+  df_graph *g = new (std::nothrow) df_graph();
+  if (!g) return fail(nullptr, DF_ENOMEM, "host allocation failed");
+  g->device = device;
+  if ((e = hipSetDevice(device)) != hipSuccess) {
+    delete g;
+    return fail(nullptr, DF_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  }
+  if (stream) {
+    g->stream = (hipStream_t)stream;
+    g->own_stream = false;
+  } else {
+    if ((e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) != hipSuccess) {
+      delete g;
+      return fail(nullptr, DF_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    g->own_stream = true;
+  }
+  const size_t idx_bytes = sizeof(int64_t) * 2 * kMaxFifos;
+  if ((e = hipMalloc(&g->idx_pool, idx_bytes)) != hipSuccess ||
+      (e = hipMalloc(&g->err_dev, sizeof(int32_t) * 4)) != hipSuccess ||
+      (e = hipMemset(g->idx_pool, 0, idx_bytes)) != hipSuccess ||
+      (e = hipMemset(g->err_dev, 0, sizeof(int32_t) * 4)) != hipSuccess) {
+    df_graph_destroy(g);
+    return fail(nullptr, DF_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return DF_OK;
+}
+
+static void free_actor(Actor &a) {
+  hipFree(a.h);
+  hipFree(a.hist);
+  hipFree(a.B);
+  hipFree(a.prev);
+  hipFree(a.off);
+  hipFree(a.last);
+  hipFree(a.state);
+  hipFree(a.count);
+  hipFree(a.emit_off);
+  a = Actor();
+}
+
+extern "C" df_status df_graph_destroy(df_graph *g) {
+  if (!g) return fail(nullptr, DF_EINVAL, "null graph");
+  hipSetDevice(g->device);
+  if (g->stream) hipStreamSynchronize(g->stream);
+  destroy_persistent(g);
+  for (auto &f : g->fifos) hipFree(f.ring);
+  for (auto &a : g->actors) free_actor(a);
+  hipFree(g->idx_pool);
+  hipFree(g->err_dev);
+  if (g->own_stream && g->stream) hipStreamDestroy(g->stream);
+  delete g;
+  return DF_OK;
+}
+
+extern "C" df_status df_sync(df_graph *g) {
+  ENTER(g);
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  int32_t err = 0;
+  HIPCHK(g, hipMemcpy(&err, g->err_dev, sizeof err, hipMemcpyDeviceToHost));
+  if (err & kErrControl) return fail(g, DF_ECONTROL, "a control token outside 0..n_branches_max was read on the device");
+  return DF_OK;
+}
+
+// ------------------------------------------------------------------ FIFOs
+
+extern "C" df_status df_fifo_create(df_graph *g, df_dtype dt, int64_t elems_per_token, int64_t capacity_tokens,
+                                    int64_t n_initial, const void *initial_host, int32_t *fifo_out) {
+  ENTER(g);
+  if (!fifo_out) return fail(g, DF_EINVAL, "df_fifo_create: null output pointer");
+  const int64_t eb = dtype_bytes(dt);
+  if (!eb) return fail(g, DF_EINVAL, "df_fifo_create: bad dtype %d", (int)dt);
+  if (elems_per_token < 1) return fail(g, DF_EINVAL, "df_fifo_create: elems_per_token must be >= 1");
+  if (n_initial < 0 || capacity_tokens < 0) return fail(g, DF_EINVAL, "df_fifo_create: negative size");
+  if ((int)g->fifos.size() >= kMaxFifos) return fail(g, DF_ENOMEM, "too many FIFOs (max %d)", kMaxFifos);
+  int64_t cap = capacity_tokens ? capacity_tokens : std::max<int64_t>(2 * n_initial, 1024);
+  cap = next_pow2(cap);
+  if (n_initial > cap) return fail(g, DF_EINVAL, "df_fifo_create: n_initial %lld exceeds capacity %lld",
+                                   (long long)n_initial, (long long)cap);
+  Fifo f;
+  f.dt = dt;
+  f.elem_bytes = eb;
+  f.elems_per_token = elems_per_token;
+  f.token_bytes = eb * elems_per_token;
+  f.cap = cap;
+  f.mask = cap - 1;
+  f.n_initial = n_initial;
+  const int id = (int)g->fifos.size();
+  f.idx = g->idx_pool + 2 * id;
+  hipError_t e = hipMalloc(&f.ring, (size_t)(cap * f.token_bytes));
+  if (e != hipSuccess) return fail(g, DF_ENOMEM, "ring allocation of %lld bytes failed",
+                                   (long long)(cap * f.token_bytes));
+  if (n_initial) {
+    if (initial_host)
+      e = hipMemcpy(f.ring, initial_host, (size_t)(n_initial * f.token_bytes), hipMemcpyHostToDevice);
+    else
+      e = hipMemset(f.ring, 0, (size_t)(n_initial * f.token_bytes));
+    if (e != hipSuccess) {
+      hipFree(f.ring);
+      return fail_hip(g, e, "initial tokens");
+    }
+  }
+  const int64_t init_idx[2] = {0, n_initial};
+  e = hipMemcpy(f.idx, init_idx, sizeof init_idx, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(f.ring);
+    return fail_hip(g, e, "index init");
+  }
+  f.read_h = 0;
+  f.write_lo = f.write_hi = n_initial;
+  g->fifos.push_back(f);
+  *fifo_out = id;
+  return DF_OK;
+}
+
+df_status dfh::refresh_fifo(df_graph *g, Fifo &f) {
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  int64_t idx[2];
+  HIPCHK(g, hipMemcpy(idx, f.idx, sizeof idx, hipMemcpyDeviceToHost));
+  f.read_h = idx[0];
+  f.write_lo = f.write_hi = idx[1];
+  return DF_OK;
+}
+
+extern "C" df_status df_fifo_status(df_graph *g, int32_t fifo, int64_t *read_idx, int64_t *write_idx,
+                                    int64_t *capacity) {
+  ENTER(g);
+  if (fifo < 0 || fifo >= (int)g->fifos.size()) return fail(g, DF_EINVAL, "bad fifo id %d", fifo);
+  Fifo &f = g->fifos[fifo];
+  if (f.write_lo != f.write_hi) {
+    df_status st = refresh_fifo(g, f);
+    if (st) return st;
+  }
+  if (read_idx) *read_idx = f.read_h;
+  if (write_idx) *write_idx = f.write_lo;
+  if (capacity) *capacity = f.cap;
+  return DF_OK;
+}
+
+// ------------------------------------------------------------------ actors
+
+extern "C" df_status df_actor_create(df_graph *g, df_actor_kind kind, const void *params, size_t params_size,
+                                     int32_t *actor_out) {
+  ENTER(g);
+  if (!params || !actor_out) return fail(g, DF_EINVAL, "df_actor_create: null pointer");
+  Actor a;
+  a.kind = kind;
+  hipError_t e;
+  if (kind == DF_ACTOR_DPD) {
+    if (params_size != sizeof(df_dpd_params)) return fail(g, DF_EINVAL, "df_actor_create: params_size mismatch");
+    const df_dpd_params &p = *(const df_dpd_params *)params;
+    if (p.n_branches_max < 1 || p.n_branches_max > kMaxBranches)
+      return fail(g, DF_EINVAL, "n_branches_max %d outside 1..%d", p.n_branches_max, kMaxBranches);
+    if (p.n_taps < 1 || p.n_taps > kMaxTaps) return fail(g, DF_EINVAL, "n_taps %d outside 1..%d", p.n_taps, kMaxTaps);
+    if (p.firing_size < 1 || p.firing_size < p.n_taps - 1)
+      return fail(g, DF_EINVAL, "firing_size %lld must be >= max(1, n_taps-1)", (long long)p.firing_size);
+    if (p.history_mode != DF_HIST_BRANCH && p.history_mode != DF_HIST_SHARED)
+      return fail(g, DF_EINVAL, "bad history_mode %d", p.history_mode);
+    if (!p.coeffs) return fail(g, DF_EINVAL, "null coefficients");
+    a.dp = p;
+    a.dp.coeffs = nullptr;
+    const size_t hb = sizeof(float2) * p.n_branches_max * p.n_taps;
+    const size_t sb = sizeof(float2) * p.n_branches_max * std::max(p.n_taps - 1, 1);
+    if ((e = hipMalloc(&a.h, hb)) != hipSuccess || (e = hipMalloc(&a.hist, sb)) != hipSuccess ||
+        (e = hipMalloc(&a.last, sizeof(int64_t) * p.n_branches_max)) != hipSuccess) {
+      free_actor(a);
+      return fail(g, DF_ENOMEM, "actor allocation failed");
+    }
+    e = hipMemcpy(a.h, p.coeffs, hb, p.coeffs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(a.hist, 0, sb);
+    if (e != hipSuccess) {
+      free_actor(a);
+      return fail_hip(g, e, "actor init");
+    }
+  } else if (kind == DF_ACTOR_MOTION) {
+    if (params_size != sizeof(df_motion_params)) return fail(g, DF_EINVAL, "df_actor_create: params_size mismatch");
+    const df_motion_params &p = *(const df_motion_params *)params;
+    if (p.width < 1 || p.height < 1 || p.width > 65536 || p.height > 65536)
+      return fail(g, DF_EINVAL, "bad frame size %dx%d", p.width, p.height);
+    if (p.diff_threshold < 0 || p.diff_threshold > 255) return fail(g, DF_EINVAL, "diff_threshold outside 0..255");
+    if (p.min_changed_permille < 0 || p.min_changed_permille > 1000)
+      return fail(g, DF_EINVAL, "min_changed_permille outside 0..1000");
+    if (p.self_delay != 0 && p.self_delay != 1) return fail(g, DF_EINVAL, "self_delay must be 0 or 1");
+    a.mp = p;
+    if (p.self_delay) {
+      const size_t wh = (size_t)p.width * p.height;
+      if ((e = hipMalloc(&a.state, wh)) != hipSuccess) return fail(g, DF_ENOMEM, "state allocation failed");
+      if ((e = hipMemset(a.state, 0, wh)) != hipSuccess) {
+        free_actor(a);
+        return fail_hip(g, e, "state init");
+      }
+    }
+  } else {
+    return fail(g, DF_EINVAL, "unknown actor kind %d", (int)kind);
+  }
+  *actor_out = (int32_t)g->actors.size();
+  g->actors.push_back(a);
+  return DF_OK;
+}
+
+// Port table: (dtype, elems per token, is_input); elems 0 = frame size.
+struct PortSpec {
+  df_dtype dt;
+  bool frame;
+  bool input;
+  bool control;
+};
+
+static bool port_spec(const Actor &a, int port, PortSpec *ps) {
+  if (a.kind == DF_ACTOR_DPD) {
+    switch (port) {
+      case DF_DPD_CTRL: *ps = {DF_I32, false, true, true}; return true;
+      case DF_DPD_IN: *ps = {DF_C64, false, true, false}; return true;
+      case DF_DPD_OUT: *ps = {DF_C64, false, false, false}; return true;
+    }
+  } else if (a.kind == DF_ACTOR_MOTION) {
+    switch (port) {
+      case DF_MD_CUR: *ps = {DF_U8, true, true, false}; return true;
+      case DF_MD_PREV: *ps = {DF_U8, true, true, false}; return a.mp.self_delay == 0;
+      case DF_MD_MASK: *ps = {DF_U8, true, false, false}; return true;
+      case DF_MD_INDEX: *ps = {DF_I64, false, false, false}; return true;
+    }
+  }
+  return false;
+}
+
+extern "C" df_status df_connect(df_graph *g, int32_t actor, int32_t port, int32_t fifo) {
+  ENTER(g);
+  if (actor < 0 || actor >= (int)g->actors.size()) return fail(g, DF_EINVAL, "bad actor id %d", actor);
+  if (fifo < 0 || fifo >= (int)g->fifos.size()) return fail(g, DF_EINVAL, "bad fifo id %d", fifo);
+  Actor &a = g->actors[actor];
+  Fifo &f = g->fifos[fifo];
+  PortSpec ps;
+  if (!port_spec(a, port, &ps)) return fail(g, DF_EINVAL, "actor %d has no port %d", actor, port);
+  const int64_t want_elems = ps.frame ? (int64_t)a.mp.width * a.mp.height : 1;
+  if (f.dt != ps.dt || f.elems_per_token != want_elems)
+    return fail(g, DF_EINVAL, "fifo %d token type does not match port %d", fifo, port);
+  if (a.ports[port] >= 0) return fail(g, DF_ESTATE, "port %d of actor %d already connected", port, actor);
+  if (ps.input) {
+    if (f.reader >= 0) return fail(g, DF_ESTATE, "fifo %d already has a reader", fifo);
+    if (f.writer == actor) return fail(g, DF_ESTATE, "an actor cannot read its own output channel");
+    if (ps.control && f.n_initial)
+      return fail(g, DF_ESTATE, "initial tokens are not allowed on a control channel");
+    f.reader = actor;
+    f.reader_port = port;
+  } else {
+    if (f.writer >= 0) return fail(g, DF_ESTATE, "fifo %d already has a writer", fifo);
+    if (f.reader == actor) return fail(g, DF_ESTATE, "an actor cannot write its own input channel");
+    f.writer = actor;
+    f.writer_port = port;
+  }
+  a.ports[port] = fifo;
+  return DF_OK;
+}
+
+// ------------------------------------------------------------------ push / pop
+
+// Copy n tokens between a ring (starting at token position pos) and a flat buffer.
+static hipError_t ring_copy(df_graph *g, Fifo &f, int64_t pos, void *flat, int64_t n, bool to_ring,
+                            bool flat_on_device) {
+  const int64_t slot = pos & f.mask;
+  const int64_t first = std::min(n, f.cap - slot);
+  const size_t tb = (size_t)f.token_bytes;
+  char *ring = f.ring;
+  char *p = (char *)flat;
+  hipMemcpyKind kind = to_ring ? (flat_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)
+                               : (flat_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+  hipError_t e;
+  if (to_ring) {
+    e = hipMemcpyAsync(ring + slot * tb, p, first * tb, kind, g->stream);
+    if (e == hipSuccess && n > first) e = hipMemcpyAsync(ring, p + first * tb, (n - first) * tb, kind, g->stream);
+  } else {
+    e = hipMemcpyAsync(p, ring + slot * tb, first * tb, kind, g->stream);
+    if (e == hipSuccess && n > first) e = hipMemcpyAsync(p + first * tb, ring, (n - first) * tb, kind, g->stream);
+  }
+  return e;
+}
+
+extern "C" df_status df_push(df_graph *g, int32_t fifo, const void *src, int64_t n, int src_on_device) {
+  ENTER(g);
+  if (fifo < 0 || fifo >= (int)g->fifos.size()) return fail(g, DF_EINVAL, "bad fifo id %d", fifo);
+  if (n < 0) return fail(g, DF_EINVAL, "negative token count");
+  Fifo &f = g->fifos[fifo];
+  if (f.writer >= 0) return fail(g, DF_ESTATE, "fifo %d is written by actor %d", fifo, f.writer);
+  if (n == 0) return DF_OK;
+  if (!src) return fail(g, DF_EINVAL, "null source");
+  if (f.cap - (f.write_hi - f.read_h) < n)
+    return fail(g, DF_EAGAIN, "fifo %d: %lld tokens do not fit (%lld free)", fifo, (long long)n,
+                (long long)(f.cap - (f.write_hi - f.read_h)));
+  if (f.reader >= 0 && f.reader_port == DF_DPD_CTRL && g->actors[f.reader].kind == DF_ACTOR_DPD &&
+      !src_on_device) {
+    const int32_t *v = (const int32_t *)src;
+    const int32_t bm = g->actors[f.reader].dp.n_branches_max;
+    for (int64_t i = 0; i < n; ++i)
+      if (v[i] < 0 || v[i] > bm)
+        return fail(g, DF_EINVAL, "control token %d at %lld outside 0..%d", v[i], (long long)i, bm);
+  }
+  HIPCHK(g, ring_copy(g, f, f.write_hi, (void *)src, n, true, src_on_device != 0));
+  HIPCHK(g, launch_advance(f.idx + 1, n, g->stream));
+  f.write_lo += n;
+  f.write_hi += n;
+  if (!src_on_device) HIPCHK(g, hipStreamSynchronize(g->stream));
+  return DF_OK;
+}
+
+extern "C" df_status df_pop(df_graph *g, int32_t fifo, void *dst, int64_t max_tokens, int dst_on_device,
+                            int64_t *n_popped) {
+  ENTER(g);
+  if (n_popped) *n_popped = 0;
+  if (fifo < 0 || fifo >= (int)g->fifos.size()) return fail(g, DF_EINVAL, "bad fifo id %d", fifo);
+  if (max_tokens < 0) return fail(g, DF_EINVAL, "negative token count");
+  Fifo &f = g->fifos[fifo];
+  if (f.reader >= 0) return fail(g, DF_ESTATE, "fifo %d is read by actor %d", fifo, f.reader);
+  if (f.write_lo != f.write_hi) {
+    df_status st = refresh_fifo(g, f);
+    if (st) return st;
+  }
+  const int64_t k = std::min(max_tokens, f.write_lo - f.read_h);
+  if (k > 0) {
+    if (!dst) return fail(g, DF_EINVAL, "null destination");
+    HIPCHK(g, ring_copy(g, f, f.read_h, dst, k, false, dst_on_device != 0));
+    HIPCHK(g, launch_advance(f.idx + 0, k, g->stream));
+    f.read_h += k;
+    if (!dst_on_device) HIPCHK(g, hipStreamSynchronize(g->stream));
+  }
+  if (n_popped) *n_popped = k;
+  return DF_OK;
+}
+
+// ------------------------------------------------------------------ firing
+
+// Tokens available to the reader, refreshing a data-dependent producer's
+// count from the device only when the guaranteed count is too small.
+static df_status available(df_graph *g, Fifo &f, int64_t need, int64_t *avail) {
+  *avail = f.write_lo - f.read_h;
+  if (*avail < need && f.write_lo != f.write_hi) {
+    df_status st = refresh_fifo(g, f);
+    if (st) return st;
+    *avail = f.write_lo - f.read_h;
+  }
+  return DF_OK;
+}
+
+static int64_t space_of(const Fifo &f) { return f.cap - (f.write_hi - f.read_h); }
+
+static hipError_t grow(void **p, size_t bytes) {
+  hipFree(*p);
+  *p = nullptr;
+  return hipMalloc(p, bytes);
+}
+
+df_status dfh::ensure_dpd_scratch(df_graph *g, Actor &a, int64_t n) {
+  if (n <= a.scratch_n) return DF_OK;
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  const int64_t cap = std::max<int64_t>(next_pow2(n), 64);
+  const int bm = a.dp.n_branches_max;
+  if (grow((void **)&a.B, sizeof(int32_t) * cap) != hipSuccess ||
+      grow((void **)&a.prev, sizeof(int64_t) * bm * cap) != hipSuccess ||
+      grow((void **)&a.off, sizeof(int64_t) * bm * cap) != hipSuccess)
+    return fail(g, DF_ENOMEM, "scratch allocation failed");
+  a.scratch_n = cap;
+  return DF_OK;
+}
+
+df_status dfh::dpd_admit(df_graph *g, Actor &a, int64_t n, int64_t *n_adm) {
+  if (a.ports[DF_DPD_CTRL] < 0 || a.ports[DF_DPD_IN] < 0 || a.ports[DF_DPD_OUT] < 0)
+    return fail(g, DF_ESTATE, "predistortion actor has unconnected ports");
+  Fifo &fc = g->fifos[a.ports[DF_DPD_CTRL]];
+  Fifo &fx = g->fifos[a.ports[DF_DPD_IN]];
+  Fifo &fy = g->fifos[a.ports[DF_DPD_OUT]];
+  const int64_t r = a.dp.firing_size;
+  int64_t ac, ax;
+  df_status st = available(g, fc, n, &ac);
+  if (st) return st;
+  st = available(g, fx, n * r, &ax);
+  if (st) return st;
+  *n_adm = std::min({n, ac, ax / r, space_of(fy) / r});
+  return DF_OK;
+}
+
+df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
+  Fifo &fc = g->fifos[a.ports[DF_DPD_CTRL]];
+  Fifo &fx = g->fifos[a.ports[DF_DPD_IN]];
+  Fifo &fy = g->fifos[a.ports[DF_DPD_OUT]];
+  const int64_t r = a.dp.firing_size;
+  const int bm = a.dp.n_branches_max, M = a.dp.n_taps;
+
+  ScanArgs sa{};
+  sa.ctrl = (const int32_t *)fc.ring;
+  sa.ctrl_idx = fc.idx;
+  sa.ctrl_mask = fc.mask;
+  sa.seg_firings = n;
+  sa.n_segs = 1;
+  sa.B_max = bm;
+  sa.hist_mode = a.dp.history_mode;
+  sa.B_out = a.B;
+  sa.prev_out = a.prev;
+  sa.off_out = a.off;
+  sa.last_out = a.last;
+  sa.stride = a.scratch_n;
+  sa.r = r;
+  sa.err = g->err_dev;
+  HIPCHK(g, launch_scan(sa, g->stream));
+
+  DpdArgs da{};
+  da.x = (const float2 *)fx.ring;
+  da.x_idx = fx.idx;
+  da.x_mask = fx.mask;
+  da.y = (float2 *)fy.ring;
+  da.y_idx = fy.idx;
+  da.y_mask = fy.mask;
+  da.h = a.h;
+  da.hist = a.hist;
+  da.B = a.B;
+  da.prev = a.prev;
+  da.prev_stride = a.scratch_n;
+  da.seg_firings = n;
+  da.n_firings = n;
+  da.r = r;
+  da.B_max = bm;
+  da.M = M;
+  HIPCHK(g, launch_dpd_body(da, g->stream, g->tile, g->outputs_per_thread));
+
+  DpdCommitArgs ca{};
+  ca.x = (const float2 *)fx.ring;
+  ca.x_idx = fx.idx;
+  ca.x_mask = fx.mask;
+  ca.ctrl_idx = fc.idx;
+  ca.y_idx = fy.idx;
+  ca.hist = a.hist;
+  ca.last = a.last;
+  ca.n_firings = n;
+  ca.r = r;
+  ca.B_max = bm;
+  ca.M = M;
+  HIPCHK(g, launch_dpd_commit(ca, g->stream));
+
+  fc.read_h += n;
+  fx.read_h += n * r;
+  fy.write_lo += n * r;
+  fy.write_hi += n * r;
+  a.last_n = n;
+  a.fired += n;
+  return DF_OK;
+}
+
+static df_status fire_dpd(df_graph *g, Actor &a, int64_t n, int flags, int64_t *n_fired) {
+  int64_t adm;
+  df_status st = dpd_admit(g, a, n, &adm);
+  if (st) return st;
+  if (adm < n && !(flags & DF_FIRE_PARTIAL))
+    return fail(g, DF_EAGAIN, "only %lld of %lld firings admissible", (long long)adm, (long long)n);
+  n = adm;
+  if (n_fired) *n_fired = n;
+  if (n == 0) return DF_OK;
+  st = ensure_dpd_scratch(g, a, n);
+  if (st) return st;
+  return dpd_enqueue(g, a, n);
+}
+
+static df_status fire_motion(df_graph *g, Actor &a, int64_t n, int flags, int64_t *n_fired) {
+  const df_motion_params &p = a.mp;
+  if (a.ports[DF_MD_CUR] < 0 || a.ports[DF_MD_MASK] < 0 || a.ports[DF_MD_INDEX] < 0 ||
+      (!p.self_delay && a.ports[DF_MD_PREV] < 0))
+    return fail(g, DF_ESTATE, "motion actor has unconnected ports");
+  Fifo &fc = g->fifos[a.ports[DF_MD_CUR]];
+  Fifo *fp = p.self_delay ? nullptr : &g->fifos[a.ports[DF_MD_PREV]];
+  Fifo &fm = g->fifos[a.ports[DF_MD_MASK]];
+  Fifo &fi = g->fifos[a.ports[DF_MD_INDEX]];
+  int64_t ac, ap = n;
+  df_status st = available(g, fc, n, &ac);
+  if (st) return st;
+  if (fp && (st = available(g, *fp, n, &ap))) return st;
+  const int64_t adm = std::min({n, ac, ap, space_of(fm), space_of(fi)});
+  if (adm < n && !(flags & DF_FIRE_PARTIAL))
+    return fail(g, DF_EAGAIN, "only %lld of %lld firings admissible", (long long)adm, (long long)n);
+  n = adm;
+  if (n_fired) *n_fired = n;
+  if (n == 0) return DF_OK;
+  const int64_t wh = (int64_t)p.width * p.height;
+  const int64_t chunk_max = 65535;                     // grid z limit of one launch
+  const int64_t want = std::min(n, chunk_max);
+  if (want > a.cnt_cap) {
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    const int64_t cap = next_pow2(want);
+    if (grow((void **)&a.count, sizeof(int32_t) * cap) != hipSuccess ||
+        grow((void **)&a.emit_off, sizeof(int64_t) * (cap + 1)) != hipSuccess)
+      return fail(g, DF_ENOMEM, "scratch allocation failed");
+    a.cnt_cap = cap;
+  }
+  for (int64_t done = 0; done < n; done += chunk_max) {
+    const int64_t k = std::min(chunk_max, n - done);
+    MotionArgs ma{};
+    ma.cur = (const uint8_t *)fc.ring;
+    ma.cur_idx = fc.idx;
+    ma.cur_mask = fc.mask;
+    ma.prev = fp ? (const uint8_t *)fp->ring : nullptr;
+    ma.prev_idx = fp ? fp->idx : nullptr;
+    ma.prev_mask = fp ? fp->mask : 0;
+    ma.state = a.state;
+    ma.out = (uint8_t *)fm.ring;
+    ma.out_idx = fm.idx;
+    ma.out_mask = fm.mask;
+    ma.index_out = (int64_t *)fi.ring;
+    ma.index_idx = fi.idx;
+    ma.index_mask = fi.mask;
+    ma.count = a.count;
+    ma.emit_off = a.emit_off;
+    ma.n = k;
+    ma.frame_base = a.fired;
+    ma.W = p.width;
+    ma.H = p.height;
+    ma.thr = p.diff_threshold;
+    ma.permille = p.min_changed_permille;
+    HIPCHK(g, launch_fill_i32(a.count, 0, k, g->stream));
+    HIPCHK(g, launch_motion_count(ma, g->stream));
+    HIPCHK(g, launch_motion_emit_scan(a.count, k, (int64_t)p.min_changed_permille * wh, a.emit_off, g->stream));
+    HIPCHK(g, launch_motion_emit(ma, g->stream));
+    if (p.self_delay) {
+      const int64_t last = (fc.read_h + k - 1) & fc.mask;
+      HIPCHK(g, hipMemcpyAsync(a.state, fc.ring + last * wh, (size_t)wh, hipMemcpyDeviceToDevice, g->stream));
+    }
+    HIPCHK(g, launch_motion_commit(a.emit_off, k, fc.idx, fp ? fp->idx : nullptr, fm.idx, fi.idx, g->stream));
+    fc.read_h += k;
+    if (fp) fp->read_h += k;
+    fm.write_hi += k;
+    fi.write_hi += k;
+    a.fired += k;
+  }
+  a.last_n = n;
+  return DF_OK;
+}
+
+extern "C" df_status df_fire(df_graph *g, int32_t actor, int64_t n, int flags, int64_t *n_fired) {
+  ENTER(g);
+  if (n_fired) *n_fired = 0;
+  if (actor < 0 || actor >= (int)g->actors.size()) return fail(g, DF_EINVAL, "bad actor id %d", actor);
+  if (n < 0) return fail(g, DF_EINVAL, "negative firing count");
+  if (flags & ~DF_FIRE_PARTIAL) return fail(g, DF_EINVAL, "bad flags 0x%x", flags);
+  Actor &a = g->actors[actor];
+  if (a.kind == DF_ACTOR_DPD) return fire_dpd(g, a, n, flags, n_fired);
+  return fire_motion(g, a, n, flags, n_fired);
+}
+
+extern "C" df_status df_set_tile(df_graph *g, int32_t tile_outputs, int32_t outputs_per_thread,
+                                 int32_t blocks_per_cu) {
+  ENTER(g);
+  if (outputs_per_thread != 0 && outputs_per_thread != 4 && outputs_per_thread != 8)
+    return fail(g, DF_EINVAL, "outputs_per_thread must be 4 or 8");
+  const int k = outputs_per_thread ? outputs_per_thread : g->outputs_per_thread;
+  if (tile_outputs != 0 && (tile_outputs < 64 * k || tile_outputs > 512 * k || tile_outputs % (64 * k)))
+    return fail(g, DF_EINVAL, "tile_outputs must be a multiple of %d in %d..%d", 64 * k, 64 * k, 512 * k);
+  if (blocks_per_cu < 0 || blocks_per_cu > 16) return fail(g, DF_EINVAL, "blocks_per_cu outside 0..16");
+  if (outputs_per_thread) g->outputs_per_thread = outputs_per_thread;
+  if (tile_outputs) g->tile = tile_outputs;
+  if (blocks_per_cu) g->blocks_per_cu = blocks_per_cu;
+  return DF_OK;
+}
+
+extern "C" df_status df_debug_last_batch(df_graph *g, int32_t actor, int32_t *rates, int64_t *offsets,
+                                         int64_t *prev, int64_t cap, int64_t *n_out) {
+  ENTER(g);
+  if (actor < 0 || actor >= (int)g->actors.size()) return fail(g, DF_EINVAL, "bad actor id %d", actor);
+  Actor &a = g->actors[actor];
+  if (a.kind != DF_ACTOR_DPD) return fail(g, DF_EINVAL, "not a predistortion actor");
+  const int64_t n = a.last_n;
+  if (n_out) *n_out = n;
+  if (n > cap) return fail(g, DF_EINVAL, "cap %lld < batch size %lld", (long long)cap, (long long)n);
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  const int bm = a.dp.n_branches_max;
+  if (n == 0) return DF_OK;
+  if (rates) {
+    std::vector<int32_t> B(n);
+    HIPCHK(g, hipMemcpy(B.data(), a.B, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    for (int b = 0; b < bm; ++b)
+      for (int64_t j = 0; j < n; ++j) rates[b * cap + j] = b < B[j] ? (int32_t)a.dp.firing_size : 0;
+  }
+  for (int b = 0; b < bm; ++b) {
+    if (offsets)
+      HIPCHK(g, hipMemcpy(offsets + b * cap, a.off + b * a.scratch_n, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
+    if (prev)
+      HIPCHK(g, hipMemcpy(prev + b * cap, a.prev + b * a.scratch_n, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
+  }
+  return DF_OK;
+}

@@ -1,0 +1,83 @@
+// Host-side state of a network (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "dfhip.h"
+
+namespace dfh {
+
+constexpr int kMaxFifos = 16384;
+
+// A FIFO channel as a device ring of `cap` tokens (power of two).  The
+// device pair idx[0..1] = (read, write) token counters is authoritative;
+// the host mirror read_h is exact (every reader has a statically known rate)
+// and [write_lo, write_hi] brackets the write counter (equal unless the
+// writer's production rate is data-dependent and not yet read back).
+struct Fifo {
+  df_dtype dt = DF_C64;
+  int64_t elem_bytes = 0, elems_per_token = 0, token_bytes = 0;
+  int64_t cap = 0, mask = 0;
+  char *ring = nullptr;
+  int64_t *idx = nullptr;
+  int64_t read_h = 0, write_lo = 0, write_hi = 0;
+  int64_t n_initial = 0;
+  int writer = -1, writer_port = -1;  // -1: the host
+  int reader = -1, reader_port = -1;
+};
+
+struct Actor {
+  df_actor_kind kind = DF_ACTOR_DPD;
+  int ports[4] = {-1, -1, -1, -1};
+  int64_t fired = 0;     // firings so far
+  int64_t last_n = 0;    // size of the last batch
+  // predistortion
+  df_dpd_params dp{};
+  float2 *h = nullptr;       // [B_max][M]
+  float2 *hist = nullptr;    // [B_max][M-1] carried branch histories
+  int64_t scratch_n = 0;
+  int32_t *B = nullptr;      // [scratch_n]
+  int64_t *prev = nullptr;   // [B_max][scratch_n]
+  int64_t *off = nullptr;    // [B_max][scratch_n]
+  int64_t *last = nullptr;   // [B_max]
+  // motion
+  df_motion_params mp{};
+  uint8_t *state = nullptr;  // previous frame (self-delay form)
+  int32_t *count = nullptr;
+  int64_t *emit_off = nullptr;
+  int64_t cnt_cap = 0;
+};
+
+struct Persistent;  // multi-instance batching state
+
+}  // namespace dfh
+
+struct df_graph {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool poisoned = false;
+  std::string last_error;
+  std::vector<dfh::Fifo> fifos;
+  std::vector<dfh::Actor> actors;
+  int64_t *idx_pool = nullptr;   // device [kMaxFifos][2]
+  int32_t *err_dev = nullptr;    // sticky device error word
+  int tile = 0;                  // 0 = default
+  int outputs_per_thread = 4;
+  int blocks_per_cu = 0;          // persistent grid; 0 = default
+  dfh::Persistent *pers = nullptr;
+};
+
+namespace dfh {
+df_status fail(df_graph *g, df_status st, const char *fmt, ...);
+df_status fail_hip(df_graph *g, hipError_t e, const char *what);
+df_status refresh_fifo(df_graph *g, Fifo &f);
+df_status ensure_dpd_scratch(df_graph *g, Actor &a, int64_t n);
+df_status dpd_admit(df_graph *g, Actor &a, int64_t n, int64_t *n_adm);
+df_status dpd_enqueue(df_graph *g, Actor &a, int64_t n);
+void destroy_persistent(df_graph *g);
+}  // namespace dfh

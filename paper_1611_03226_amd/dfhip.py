@@ -1,0 +1,250 @@
+"""Thin Python binding of libdfhip.so: one function per C entry point, same
+names, argument marshalling only (numpy arrays for host buffers, torch
+tensors for device buffers, torch streams for HIP streams).  Every call
+raises DFError on a non-zero status.  All computation happens in the HIP
+library; if it is not built, importing this module fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdfhip.so")
+
+DF_OK, DF_EINVAL, DF_EAGAIN, DF_ENOMEM, DF_ESTATE, DF_EDEVICE, DF_ECONTROL = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "DF_OK", -1: "DF_EINVAL", -2: "DF_EAGAIN", -3: "DF_ENOMEM", -4: "DF_ESTATE",
+                -5: "DF_EDEVICE", -6: "DF_ECONTROL"}
+DF_C64, DF_U8, DF_I32, DF_I64 = 1, 2, 3, 4
+DF_ACTOR_DPD, DF_ACTOR_MOTION = 1, 2
+DF_DPD_CTRL, DF_DPD_IN, DF_DPD_OUT = 0, 1, 2
+DF_MD_CUR, DF_MD_PREV, DF_MD_MASK, DF_MD_INDEX = 0, 1, 2, 3
+DF_HIST_BRANCH, DF_HIST_SHARED = 0, 1
+DF_FIRE_PARTIAL = 1
+DF_FIRE_PERSISTENT, DF_FIRE_GRAPH = 1, 2
+
+_NP_DTYPE = {DF_C64: np.complex64, DF_U8: np.uint8, DF_I32: np.int32, DF_I64: np.int64}
+
+
+class DFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class DpdParams(C.Structure):
+    _fields_ = [("n_branches_max", C.c_int32), ("n_taps", C.c_int32), ("firing_size", C.c_int64),
+                ("coeffs", C.c_void_p), ("coeffs_on_device", C.c_int32), ("history_mode", C.c_int32)]
+
+
+class MotionParams(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("diff_threshold", C.c_int32),
+                ("min_changed_permille", C.c_int32), ("self_delay", C.c_int32)]
+
+
+_P = C.c_void_p
+_I32, _I64 = C.c_int32, C.c_int64
+_SIGS = {
+    "df_graph_create": ([C.POINTER(_P), C.c_int, _P], _I32),
+    "df_graph_destroy": ([_P], _I32),
+    "df_sync": ([_P], _I32),
+    "df_last_error": ([_P], C.c_char_p),
+    "df_version": ([], C.c_char_p),
+    "df_fifo_create": ([_P, C.c_int, _I64, _I64, _I64, _P, C.POINTER(_I32)], _I32),
+    "df_fifo_status": ([_P, _I32, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)], _I32),
+    "df_actor_create": ([_P, C.c_int, _P, C.c_size_t, C.POINTER(_I32)], _I32),
+    "df_connect": ([_P, _I32, _I32, _I32], _I32),
+    "df_push": ([_P, _I32, _P, _I64, C.c_int], _I32),
+    "df_pop": ([_P, _I32, _P, _I64, C.c_int, C.POINTER(_I64)], _I32),
+    "df_fire": ([_P, _I32, _I64, C.c_int, C.POINTER(_I64)], _I32),
+    "df_fire_many": ([_P, _I32, _P, _P, C.c_int], _I32),
+    "df_set_tile": ([_P, _I32, _I32, _I32], _I32),
+    "df_debug_last_batch": ([_P, _I32, _P, _P, _P, _I64, C.POINTER(_I64)], _I32),
+    "df_dpd_forward": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
+    "df_dpd_coeff_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32, _P, _I64], _I32),
+    "df_dpd_coeff_adjoint_work_bytes": ([_I64, _I64, _I64, _I32, _I32], _I64),
+    "df_mp_input_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I32, _I32], _I32),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_1611_03226_amd.build` "
+                          "(the HIP library is required, there is no fallback)")
+    lib = C.CDLL(path)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(status: int, g=None) -> None:
+    if status != DF_OK:
+        msg = _lib.df_last_error(g)
+        raise DFError(status, msg.decode() if msg else "")
+
+
+# ------------------------------------------------------------------ marshalling
+
+def _is_tensor(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _host_ptr(a: np.ndarray):
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("host buffers must be C-contiguous")
+    return a.ctypes.data
+
+
+def _dev_ptr(t):
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("device tensors must be contiguous")
+    return t.data_ptr()
+
+
+# ------------------------------------------------------------------ graph
+
+def df_version() -> str:
+    return _lib.df_version().decode()
+
+
+def df_graph_create(device: int = 0, stream=None) -> int:
+    g = C.c_void_p()
+    _check(_lib.df_graph_create(C.byref(g), device, _stream_ptr(stream)))
+    return g.value
+
+
+def df_graph_destroy(g) -> None:
+    _check(_lib.df_graph_destroy(g))
+
+
+def df_sync(g) -> None:
+    _check(_lib.df_sync(g), g)
+
+
+def df_last_error(g=None) -> str:
+    return _lib.df_last_error(g).decode()
+
+
+def df_fifo_create(g, dtype: int, elems_per_token: int = 1, capacity: int = 0, n_initial: int = 0,
+                   initial: np.ndarray | None = None) -> int:
+    out = C.c_int32()
+    ptr = None
+    if initial is not None:
+        initial = np.ascontiguousarray(initial, dtype=_NP_DTYPE[dtype])
+        if initial.size != n_initial * elems_per_token:
+            raise ValueError("initial has the wrong number of elements")
+        ptr = _host_ptr(initial)
+    _check(_lib.df_fifo_create(g, dtype, elems_per_token, capacity, n_initial, ptr, C.byref(out)), g)
+    return out.value
+
+
+def df_fifo_status(g, fifo: int):
+    r, w, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(_lib.df_fifo_status(g, fifo, C.byref(r), C.byref(w), C.byref(c)), g)
+    return r.value, w.value, c.value
+
+
+def df_actor_create(g, kind: int, params) -> int:
+    out = C.c_int32()
+    _check(_lib.df_actor_create(g, kind, C.byref(params), C.sizeof(params), C.byref(out)), g)
+    return out.value
+
+
+def df_connect(g, actor: int, port: int, fifo: int) -> None:
+    _check(_lib.df_connect(g, actor, port, fifo), g)
+
+
+def df_push(g, fifo: int, data, n_tokens: int | None = None) -> None:
+    """Push host (numpy) or device (torch) data; n_tokens defaults to len(data)."""
+    n = len(data) if n_tokens is None else n_tokens
+    if _is_tensor(data):
+        _check(_lib.df_push(g, fifo, _dev_ptr(data), n, 1), g)
+    else:
+        _check(_lib.df_push(g, fifo, _host_ptr(np.ascontiguousarray(data)), n, 0), g)
+
+
+def df_pop(g, fifo: int, dst, max_tokens: int | None = None) -> int:
+    """Pop into host (numpy) or device (torch) dst; returns tokens moved."""
+    n = len(dst) if max_tokens is None else max_tokens
+    out = C.c_int64()
+    if _is_tensor(dst):
+        _check(_lib.df_pop(g, fifo, _dev_ptr(dst), n, 1, C.byref(out)), g)
+    else:
+        _check(_lib.df_pop(g, fifo, _host_ptr(dst), n, 0, C.byref(out)), g)
+    return out.value
+
+
+def df_fire(g, actor: int, n_firings: int, flags: int = 0) -> int:
+    out = C.c_int64()
+    _check(_lib.df_fire(g, actor, n_firings, flags, C.byref(out)), g)
+    return out.value
+
+
+def df_fire_many(g, actors, n_firings, flags: int = 0) -> None:
+    a = np.ascontiguousarray(actors, dtype=np.int32)
+    n = np.ascontiguousarray(n_firings, dtype=np.int64)
+    if a.shape != n.shape:
+        raise ValueError("actors and n_firings differ in length")
+    _check(_lib.df_fire_many(g, len(a), _host_ptr(a), _host_ptr(n), flags), g)
+
+
+def df_set_tile(g, tile_outputs: int = 0, outputs_per_thread: int = 0, blocks_per_cu: int = 0) -> None:
+    _check(_lib.df_set_tile(g, tile_outputs, outputs_per_thread, blocks_per_cu), g)
+
+
+def df_debug_last_batch(g, actor: int, n_branches_max: int, cap: int):
+    rates = np.zeros((n_branches_max, cap), np.int32)
+    offs = np.zeros((n_branches_max, cap), np.int64)
+    prev = np.zeros((n_branches_max, cap), np.int64)
+    n = C.c_int64()
+    _check(_lib.df_debug_last_batch(g, actor, _host_ptr(rates), _host_ptr(offs), _host_ptr(prev), cap,
+                                    C.byref(n)), g)
+    k = n.value
+    return rates[:, :k], offs[:, :k], prev[:, :k]
+
+
+# ------------------------------------------------------------------ stateless
+
+def df_dpd_forward(x, ctrl, h, y, r: int, hist: int = DF_HIST_BRANCH, stream=None) -> None:
+    """x, y: complex64 device tensors [S, L]; ctrl int32 [S, L/r] or None; h complex64 [B, M]."""
+    S, L = x.shape
+    B, M = h.shape
+    _check(_lib.df_dpd_forward(_stream_ptr(stream), _dev_ptr(x), None if ctrl is None else _dev_ptr(ctrl),
+                               _dev_ptr(h), _dev_ptr(y), S, L, r, B, M, hist))
+
+
+def df_dpd_coeff_adjoint_work_bytes(S: int, L: int, r: int, B: int, M: int) -> int:
+    return int(_lib.df_dpd_coeff_adjoint_work_bytes(S, L, r, B, M))
+
+
+def df_dpd_coeff_adjoint(x, ctrl, G, grad_h, r: int, work, hist: int = DF_HIST_BRANCH, stream=None) -> None:
+    S, L = x.shape
+    B, M = grad_h.shape
+    _check(_lib.df_dpd_coeff_adjoint(_stream_ptr(stream), _dev_ptr(x), None if ctrl is None else _dev_ptr(ctrl),
+                                     _dev_ptr(G), _dev_ptr(grad_h), S, L, r, B, M, hist, _dev_ptr(work),
+                                     work.numel() * work.element_size()))
+
+
+def df_mp_input_adjoint(u, a, g, Gu, stream=None) -> None:
+    S, L = u.shape
+    K, Q = a.shape
+    _check(_lib.df_mp_input_adjoint(_stream_ptr(stream), _dev_ptr(u), _dev_ptr(a), _dev_ptr(g), _dev_ptr(Gu),
+                                    S, L, K, Q))

@@ -1,0 +1,83 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/dfhip.h declares, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dfhip.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"^\s*(?:df_status|const char \*|int64_t)\s*(df_\w+)\s*\(", text, flags=re.M))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1611_03226_amd import dfhip as D
+    names = _declared()
+    assert len(names) >= 18
+    lib = C.CDLL(D.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert names == set(D.EXPORTED)          # the binding covers exactly the header
+
+
+def test_version_and_error_string():
+    from paper_1611_03226_amd import dfhip as D
+    assert D.df_version().startswith("dfhip")
+    assert isinstance(D.df_last_error(None), str)
+
+
+def _have_gpu():
+    import torch
+    return torch.cuda.is_available()
+
+
+@pytest.mark.skipif(_have_gpu(), reason="checks the no-device error path")
+def test_graph_create_without_device_reports_edevice():
+    from paper_1611_03226_amd import dfhip as D
+    with pytest.raises(D.DFError) as e:
+        D.df_graph_create(0)
+    assert e.value.code == D.DF_EDEVICE
+
+
+def test_null_graph_is_rejected():
+    from paper_1611_03226_amd import dfhip as D
+    lib = D._lib
+    n = C.c_int64()
+    assert lib.df_fire(None, 0, 1, 0, C.byref(n)) == D.DF_EINVAL
+    assert lib.df_push(None, 0, None, 1, 0) == D.DF_EINVAL
+    assert lib.df_sync(None) == D.DF_EINVAL
+    assert lib.df_graph_create(None, 0, None) == D.DF_EINVAL
+
+
+@pytest.mark.parametrize("args,ok", [
+    ((1, 100, 7, 4, 4, 0), False),      # len not a multiple of r
+    ((1, 64, 8, 17, 4, 0), False),      # too many branches
+    ((1, 64, 8, 4, 33, 0), False),      # too many taps
+    ((1, 64, 4, 4, 8, 0), False),       # r < M - 1
+    ((1, 64, 8, 4, 4, 2), False),       # bad history mode
+    ((0, 64, 8, 4, 4, 0), True),        # empty: nothing to do
+])
+def test_stateless_argument_validation(args, ok):
+    from paper_1611_03226_amd import dfhip as D
+    st = D._lib.df_dpd_forward(None, None, None, None, None, *args)
+    assert (st == D.DF_OK) if ok else (st == D.DF_EINVAL)
+
+
+def test_stateless_null_pointers_and_work_size():
+    from paper_1611_03226_amd import dfhip as D
+    lib = D._lib
+    assert lib.df_dpd_forward(None, None, None, None, None, 2, 64, 8, 4, 4, 0) == D.DF_EINVAL
+    assert lib.df_mp_input_adjoint(None, None, None, None, None, 2, 64, 4, 4) == D.DF_EINVAL
+    assert lib.df_mp_input_adjoint(None, None, None, None, None, 2, 64, 0, 4) == D.DF_EINVAL
+    # work: one fp32 complex partial per (workgroup, branch, tap); 1024-sample chunks
+    wb = D.df_dpd_coeff_adjoint_work_bytes(64, 65536, 65536, 10, 16)
+    assert wb == 64 * 64 * 10 * 16 * 8
+    wb2 = D.df_dpd_coeff_adjoint_work_bytes(2, 4096, 256, 4, 8)
+    assert wb2 == 2 * 16 * 1 * 4 * 8 * 8
+    assert lib.df_dpd_coeff_adjoint(None, None, None, None, None, 2, 4096, 256, 4, 8, 0, None, 0) == D.DF_EINVAL
