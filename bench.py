@@ -1,0 +1,391 @@
+#!/usr/bin/env python3
+"""Throughput of the dynamic-rate actor hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+
+One step = one batch of the predistortion actor at scale: 2**24 complex64
+samples (OFDM-like input), 4096 firings of 4096 samples, per-firing control
+tokens uniform in 1..10 active odd-order branches, 16-tap complex FIR per
+branch.  Inputs (all W+K batches) are resident in the actor's HBM channels
+before the timed region; a step is control intake + offset scan + actor
+body + commit (one df_fire of 4096 firings).  The JSON line also carries,
+as extras, motion detection (300 x 1920x1080 frames), the 64-firing chain
+(batched vs per-firing), 1024 uneven instances (persistent HIP-graph launch
+vs per-actor and per-firing launches) and one coefficient-adaptation step,
+plus the oracle timed on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DPD Msamples/s + motion frames/s at 1 GPU; % HBM roofline; batched vs per-firing"
+HBM_PEAK = 8.0e12                 # B/s, MI355X HBM3E
+# FP32 FMA issue: 256 CUs x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz.  Packed FP32
+# (two FMAs per lane per cycle, 157.3 TFLOP/s) is disabled at compile time.
+VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
+VALU_PEAK_PACKED = 2 * VALU_PEAK
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pow2(n):
+    p = 1
+    while p < n:
+        p <<= 1
+    return p
+
+
+def dpd_flops(ctrl, r, M):
+    """Algorithmic FLOPs of one batch, Horner form: per sample of a firing
+    with B > 0 active branches, 3 (p = re^2 + im^2) + M * (4B + 4)."""
+    B = np.asarray(ctrl, np.int64)
+    return float(np.sum(np.where(B > 0, r * (3 + M * (4 * B + 4)), 0)))
+
+
+# ----------------------------------------------------------------------- main line
+
+def bench_dpd_scale(args, D, Graph, torch):
+    from workloads import dpd_scale
+    w = dpd_scale()
+    N, r, nf, M = len(w.x), w.r, w.n_firings, w.n_taps
+    nb = args.warmup + args.steps
+    G = Graph(0)
+    ch = G.dpd_chain(w.h, r, cap_x=pow2(nb * N), cap_ctrl=pow2(nb * nf), cap_y=pow2(nb * N))
+    x_dev = torch.from_numpy(w.x).cuda()
+    c_dev = torch.from_numpy(w.ctrl).cuda()
+    torch.cuda.synchronize()
+    for _ in range(nb):
+        G.push(ch.x, x_dev)
+        G.push(ch.ctrl, c_dev)
+    G.sync()
+    for _ in range(args.warmup):
+        G.fire(ch.actor, nf)
+    G.sync()
+    D.df_profile_enable(G.g, True)
+    D.df_profile_read(G.g)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        G.fire(ch.actor, nf)
+    G.sync()
+    t1 = time.perf_counter()
+    body_ms, n_body = D.df_profile_read(G.g)
+    D.df_profile_enable(G.g, False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    body = body_ms / max(n_body, 1)
+    # sampled check of the last batch against the oracle, one output at a time
+    from oracle import dpd as odpd
+    y_dev = torch.empty(nb * N, dtype=torch.complex64, device="cuda")
+    G.pop(ch.y, y_dev)
+    G.sync()
+    rng = np.random.default_rng(1)
+    idx = (nb - 1) * N + rng.integers(0, N, 200)
+
+    class Repeated:                       # the input stream: the batch pushed nb times
+        def __getitem__(self, i):
+            return w.x[int(i) % N]
+    ref = odpd.output_at(Repeated(), np.tile(w.ctrl, nb), w.h, r, idx)
+    y_last = y_dev[(nb - 1) * N:].cpu().numpy().astype(np.complex128)
+    rms = np.sqrt(np.mean(np.abs(y_last) ** 2))
+    err = float(np.max(np.abs(y_dev[idx].cpu().numpy() - ref)) / rms)
+    G.close()
+    flops = dpd_flops(w.ctrl, r, M)
+    res = dict(ms=ms, body_ms=body, flops=flops, bytes=16.0 * N, N=N, err=err,
+               papr_db=w.notes["papr_db"])
+    # per-firing launches on the same workload (one batch of 4096 df_fire(1))
+    G = Graph(0)
+    ch = G.dpd_chain(w.h, r, cap_x=pow2(2 * N), cap_ctrl=pow2(2 * nf), cap_y=pow2(2 * N))
+    G.push(ch.x, x_dev)
+    G.push(ch.ctrl, c_dev)
+    G.push(ch.x, x_dev)
+    G.push(ch.ctrl, c_dev)
+    G.fire(ch.actor, nf)                     # warm
+    G.sync()
+    t0 = time.perf_counter()
+    for _ in range(nf):
+        G.fire(ch.actor, 1)
+    G.sync()
+    res["per_firing_ms"] = (time.perf_counter() - t0) * 1e3
+    G.close()
+    return res
+
+
+# ----------------------------------------------------------------------- extras
+
+def bench_chain(D, Graph, torch, reps=50):
+    from workloads import dpd_chain
+    w = dpd_chain()
+    n, r = w.n_firings, w.r
+    G = Graph(0)
+    tot = 2 * reps + 2
+    ch = G.dpd_chain(w.h, r, w.n_delay, cap_x=pow2(tot * n * r + 8), cap_ctrl=pow2(tot * n),
+                     cap_y=pow2(tot * n * r))
+    x_dev = torch.from_numpy(w.x).cuda()
+    c_dev = torch.from_numpy(w.ctrl).cuda()
+    torch.cuda.synchronize()
+    for _ in range(tot):
+        G.push(ch.x, x_dev)
+        G.push(ch.ctrl, c_dev)
+    G.fire(ch.actor, n)
+    G.fire(ch.actor, n)
+    G.sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G.fire(ch.actor, n)
+    G.sync()
+    batched = (time.perf_counter() - t0) * 1e6 / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for _ in range(n):
+            G.fire(ch.actor, 1)
+    G.sync()
+    per = (time.perf_counter() - t0) * 1e6 / reps
+    G.close()
+    return dict(workload="dpd chain 16384 samples, 64 firings of 256, B<=5, M=8, d=4",
+                us_per_batch_batched=round(batched, 2), us_per_batch_per_firing=round(per, 2),
+                speedup=round(per / batched, 2))
+
+
+def bench_motion(D, Graph, torch, steps=3, warmup=1):
+    from workloads import motion
+    log("generating 300 frames of 1920x1080")
+    m = motion()
+    n, H, W = m.frames.shape
+    nb = steps + warmup + 2
+    G = Graph(0)
+    mc = G.motion_chain(W, H, cap_in=pow2(nb * n), cap_out=pow2(nb * n))
+    f_dev = torch.from_numpy(m.frames).cuda()
+    torch.cuda.synchronize()
+    for _ in range(nb):
+        G.push(mc.cur, f_dev)
+    for _ in range(warmup):
+        G.fire(mc.actor, n)
+    G.sync()
+    e0 = G.status(mc.index)[1]
+    D.df_profile_enable(G.g, True)
+    D.df_profile_read(G.g)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        G.fire(mc.actor, n)
+    G.sync()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    body_ms, nl = D.df_profile_read(G.g)
+    D.df_profile_enable(G.g, False)
+    body = body_ms / max(nl, 1)
+    emitted = (G.status(mc.index)[1] - e0) / steps
+    t0 = time.perf_counter()
+    for _ in range(n):
+        G.fire(mc.actor, 1)
+    G.sync()
+    per_ms = (time.perf_counter() - t0) * 1e3
+    G.close()
+    wh = W * H
+    bytes_alg = n * wh + emitted * (wh + 8)
+    return dict(workload="motion 300 frames 1920x1080 u8, threshold 25, 3x3 opening, emit at 0.1%",
+                fps=round(n / (ms * 1e-3), 1), ms_per_batch=round(ms, 4), body_ms=round(body, 4),
+                emit_fraction=round(emitted / n, 4),
+                hbm_frac_alg=round(bytes_alg / (body * 1e-3) / HBM_PEAK, 4),
+                achieved_GBps=round(bytes_alg / (body * 1e-3) / 1e9, 1),
+                per_frame_fps=round(n / (per_ms * 1e-3), 1), speedup_vs_per_frame=round(per_ms / ms, 2))
+
+
+def bench_instances(D, Graph, torch, steps=2):
+    from paper_1611_03226_amd import tune
+    from workloads import dpd_instances
+    w = dpd_instances()
+    r, M = w.r, w.n_taps
+    L = w.lengths.astype(np.int64)
+    nfs = (L // r).tolist()
+    tile = tune.tune_instances(w, log=log)
+    modes = ("many", "persistent", "graph")
+    nb = len(modes) * (steps + 1) + 1
+    G = Graph(0)
+    G.set_tile(*tile)
+    xall = torch.from_numpy(np.concatenate(w.x)).cuda()
+    offs = np.concatenate([[0], np.cumsum(L)])
+    chains = []
+    for i in range(len(L)):
+        ch = G.dpd_chain(w.h[i], r, cap_x=pow2(nb * int(L[i])), cap_ctrl=pow2(nb * nfs[i]),
+                         cap_y=pow2(nb * int(L[i])))
+        c_dev = torch.from_numpy(w.ctrl(i)).cuda()
+        for _ in range(nb):
+            G.push(ch.x, xall[offs[i]:offs[i + 1]])
+            G.push(ch.ctrl, c_dev)
+        chains.append(ch)
+    actors = [c.actor for c in chains]
+    G.sync()
+    res = {}
+    for mode in modes:
+        kw = dict(persistent=mode != "many", graph=mode == "graph")
+        G.fire_many(actors, nfs, **kw)
+        G.sync()
+        D.df_profile_enable(G.g, True)
+        D.df_profile_read(G.g)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            G.fire_many(actors, nfs, **kw)
+        G.sync()
+        res[mode] = (time.perf_counter() - t0) * 1e3 / steps
+        kms, kn = D.df_profile_read(G.g)
+        D.df_profile_enable(G.g, False)
+        res[mode + "_body_ms"] = kms / max(kn, 1) if mode != "many" else kms / steps
+    t0 = time.perf_counter()
+    for a, nf in zip(actors, nfs):
+        for _ in range(nf):
+            G.fire(a, 1)
+    G.sync()
+    res["per_firing"] = (time.perf_counter() - t0) * 1e3
+    G.close()
+    total = float(L.sum())
+    flops = sum(dpd_flops(np.full(nf, b), r, M) for nf, b in zip(nfs, w.n_branches))
+    body = res["persistent_body_ms"]
+    return dict(workload=f"1024 DPD instances, lognormal lengths 1024..262144 (sum {int(total)}), r=1024, "
+                         f"B in 1..10 per instance, M=16",
+                tile=dict(tile_outputs=tile[0], outputs_per_thread=tile[1], blocks_per_cu=tile[2]),
+                msps_graph=round(total / (res["graph"] * 1e-3) / 1e6, 1),
+                msps_persistent=round(total / (res["persistent"] * 1e-3) / 1e6, 1),
+                msps_per_actor=round(total / (res["many"] * 1e-3) / 1e6, 1),
+                msps_per_firing=round(total / (res["per_firing"] * 1e-3) / 1e6, 1),
+                ms=dict((k, round(v, 4)) for k, v in res.items()),
+                persistent_valu_frac=round(flops / (body * 1e-3) / VALU_PEAK, 4),
+                persistent_hbm_frac=round(16 * total / (body * 1e-3) / HBM_PEAK, 4),
+                speedup_graph_vs_per_firing=round(res["per_firing"] / res["graph"], 1))
+
+
+def bench_adaptation(D, torch, steps=10, warmup=2):
+    from paper_1611_03226_amd.autograd import adaptation_loss
+    from workloads import adaptation
+    w = adaptation()
+    x = torch.from_numpy(w.x).cuda()
+    a = torch.from_numpy(w.a).cuda()
+    h = torch.from_numpy(w.h0).cuda().requires_grad_(True)
+    S, L = w.x.shape
+    opt = torch.optim.SGD([h], lr=6.5 / (S * L))
+    losses = []
+
+    def step():
+        opt.zero_grad()
+        loss = adaptation_loss(x, h, a, L)
+        loss.backward()
+        opt.step()
+        return loss
+
+    for _ in range(warmup):
+        losses.append(step().item())
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        loss = step()
+    ev1.record()
+    torch.cuda.synchronize()
+    step_ms = ev0.elapsed_time(ev1) / steps
+    losses.append(loss.item())
+    # the coefficient adjoint alone
+    G = torch.randn(S, L, dtype=torch.complex64, device="cuda")
+    grad = torch.empty_like(h)
+    nb = D.df_dpd_coeff_adjoint_work_bytes(S, L, L, 10, 16)
+    work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    D.df_dpd_coeff_adjoint(x, None, G, grad, L, work, stream=torch.cuda.current_stream())
+    ev0.record()
+    for _ in range(steps):
+        D.df_dpd_coeff_adjoint(x, None, G, grad, L, work, stream=torch.cuda.current_stream())
+    ev1.record()
+    torch.cuda.synchronize()
+    adj_ms = ev0.elapsed_time(ev1) / steps
+    adj_flops = S * L * 16 * (8 + 4 * 10)
+    return dict(workload="adaptation 64 streams x 65536, DPD 10x16 learnable, PA orders 1..7 x 4 taps",
+                step_ms=round(step_ms, 4), loss_first=losses[0], loss_after=losses[-1],
+                coeff_adjoint_ms=round(adj_ms, 4),
+                coeff_adjoint_valu_frac=round(adj_flops / (adj_ms * 1e-3) / VALU_PEAK, 4))
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle network on a prefix of the same workload, one host core."""
+    from oracle import dpd as odpd
+    from workloads import dpd_scale
+    w = dpd_scale()
+    r = w.r
+    n = 16
+    t0 = time.perf_counter()
+    odpd.run_dpd(w.x[:n * r], w.ctrl[:n], w.h, r)
+    dt = time.perf_counter() - t0
+    n = int(min(w.n_firings, max(16, n * budget_s / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    odpd.run_dpd(w.x[:n * r], w.ctrl[:n], w.h, r)
+    dt = time.perf_counter() - t0
+    return dict(value=round(n * r / dt / 1e6, 4), unit="Msamples/s", cores=1, kind="oracle",
+                sample=f"first {n} firings ({n * r} samples) of the 2^24-sample workload, "
+                       f"FP64 sequential dataflow scheduler, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on one "
+              f"MI355X; sharding across GPUs is described, not implemented)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1611_03226_amd import dfhip as D
+    from paper_1611_03226_amd.graph import Graph
+    torch.cuda.set_device(0)
+
+    log("dpd at scale")
+    m = bench_dpd_scale(args, D, Graph, torch)
+    value = m["N"] / (m["ms"] * 1e-3) / 1e6
+    body_s = m["body_ms"] * 1e-3
+    achieved = m["flops"] / body_s / 1e12
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Msamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(m["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "dpd at scale: 2^24 complex64 OFDM-like samples, 4096 firings of 4096, "
+                               "control uniform 1..10 branches (odd orders to 19), 16 taps",
+                   "n_samples": m["N"], "firing_size": 4096, "n_branches_max": 10, "n_taps": 16},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK / 1e12, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved * 1e12 / VALU_PEAK, 4), "traffic": None,
+                     "kernel": "k_dpd_tiled<16,4>", "kernel_ms": round(m["body_ms"], 4),
+                     "algorithmic_flops_per_launch": m["flops"],
+                     "frac_of_packed_peak": round(achieved * 1e12 / VALU_PEAK_PACKED, 4),
+                     "hbm_frac": round(m["bytes"] / body_s / HBM_PEAK, 4)},
+        "per_firing": {"ms_per_batch": round(m["per_firing_ms"], 3),
+                       "msps": round(m["N"] / (m["per_firing_ms"] * 1e-3) / 1e6, 1),
+                       "batched_speedup": round(m["per_firing_ms"] / m["ms"], 1)},
+        "sampled_error_vs_oracle": m["err"],
+    }
+    if not args.no_extras:
+        log("dpd chain")
+        out["chain"] = bench_chain(D, Graph, torch)
+        log("motion")
+        out["motion"] = bench_motion(D, Graph, torch)
+        log("instances")
+        out["instances"] = bench_instances(D, Graph, torch)
+        log("adaptation")
+        out["adaptation"] = bench_adaptation(D, torch)
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

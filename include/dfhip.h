@@ -232,6 +232,15 @@ df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *actors,
 df_status df_set_tile(df_graph *g, int32_t tile_outputs, int32_t outputs_per_thread,
                       int32_t blocks_per_cu);
 
+/* Kernel timing.  While enabled, every batch records HIP events on the
+ * graph's stream around its actor-body kernels (predistortion body; motion
+ * count + emit passes; the persistent body kernel, or the whole replayed
+ * graph when captured).  df_profile_read synchronises, returns the summed
+ * time and number of timed launches since the last read, and resets them.
+ * Errors: DF_EINVAL, DF_EDEVICE. */
+df_status df_profile_enable(df_graph *g, int32_t enable);
+df_status df_profile_read(df_graph *g, double *total_ms, int64_t *n_launches);
+
 /* Test hook: per-firing tables of the last batch of a DPD actor (device
  * results copied to host arrays of at least cap entries per row):
  * rates [n_branches_max][n], offsets [n_branches_max][n] (token offset of

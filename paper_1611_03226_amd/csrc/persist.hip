@@ -231,7 +231,7 @@ static hipError_t launch_pers_body(const PersArgs &a, int threads, int blocks, h
   return hipGetLastError();
 }
 
-static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s) {
+static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s, df_graph *prof_g) {
   hipLaunchKernelGGL(k_pers_prep, dim3(1), dim3(64), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -239,6 +239,7 @@ static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s)
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int threads = p->tile / p->K;
   const int blocks = p->bpc * p->ncu;
+  if (prof_g && (e = prof_begin(prof_g)) != hipSuccess) return e;
   if (p->M == 16 && p->K == 4) e = launch_pers_body<16, 4>(a, threads, blocks, s);
   else if (p->M == 16 && p->K == 8) e = launch_pers_body<16, 8>(a, threads, blocks, s);
   else if (p->M == 8 && p->K == 4) e = launch_pers_body<8, 4>(a, threads, blocks, s);
@@ -247,6 +248,7 @@ static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s)
   else if (p->M == 4 && p->K == 8) e = launch_pers_body<4, 8>(a, threads, blocks, s);
   else return hipErrorInvalidValue;
   if (e != hipSuccess) return e;
+  if (prof_g && (e = prof_end(prof_g)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_pers_commit, dim3(a.n_inst), dim3(256), 0, s, a, p->M);
   return hipGetLastError();
 }
@@ -401,7 +403,7 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
   if (flags & DF_FIRE_GRAPH) {
     if (!p->exec) {
       HIPCHK(g, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e = enqueue_chain(p, pa, p->cap_stream);
+      hipError_t e = enqueue_chain(p, pa, p->cap_stream, nullptr);
       hipGraph_t graph = nullptr;
       hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
       if (e != hipSuccess) return fail_hip(g, e, "capture of the persistent chain");
@@ -409,9 +411,11 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
       p->graph = graph;
       HIPCHK(g, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
     }
+    HIPCHK(g, prof_begin(g));
     HIPCHK(g, hipGraphLaunch(p->exec, g->stream));
+    HIPCHK(g, prof_end(g));
   } else {
-    HIPCHK(g, enqueue_chain(p, pa, g->stream));
+    HIPCHK(g, enqueue_chain(p, pa, g->stream, g));
   }
   for (int i = 0; i < n_actors; ++i) {
     Actor &a = g->actors[actors[i]];

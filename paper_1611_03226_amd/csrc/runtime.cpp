@@ -130,6 +130,11 @@ extern "C" df_status df_graph_destroy(df_graph *g) {
   hipSetDevice(g->device);
   if (g->stream) hipStreamSynchronize(g->stream);
   destroy_persistent(g);
+  for (auto &pe : g->prof_pending) {
+    hipEventDestroy(pe.first);
+    hipEventDestroy(pe.second);
+  }
+  for (auto ev : g->prof_pool) hipEventDestroy(ev);
   for (auto &f : g->fifos) hipFree(f.ring);
   for (auto &a : g->actors) free_actor(a);
   hipFree(g->idx_pool);
@@ -505,7 +510,9 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   da.r = r;
   da.B_max = bm;
   da.M = M;
+  HIPCHK(g, prof_begin(g));
   HIPCHK(g, launch_dpd_body(da, g->stream, g->tile, g->outputs_per_thread));
+  HIPCHK(g, prof_end(g));
 
   DpdCommitArgs ca{};
   ca.x = (const float2 *)fx.ring;
@@ -599,9 +606,11 @@ static df_status fire_motion(df_graph *g, Actor &a, int64_t n, int flags, int64_
     ma.thr = p.diff_threshold;
     ma.permille = p.min_changed_permille;
     HIPCHK(g, launch_fill_i32(a.count, 0, k, g->stream));
+    HIPCHK(g, prof_begin(g));
     HIPCHK(g, launch_motion_count(ma, g->stream));
     HIPCHK(g, launch_motion_emit_scan(a.count, k, (int64_t)p.min_changed_permille * wh, a.emit_off, g->stream));
     HIPCHK(g, launch_motion_emit(ma, g->stream));
+    HIPCHK(g, prof_end(g));
     if (p.self_delay) {
       const int64_t last = (fc.read_h + k - 1) & fc.mask;
       HIPCHK(g, hipMemcpyAsync(a.state, fc.ring + last * wh, (size_t)wh, hipMemcpyDeviceToDevice, g->stream));
@@ -667,5 +676,54 @@ extern "C" df_status df_debug_last_batch(df_graph *g, int32_t actor, int32_t *ra
     if (prev)
       HIPCHK(g, hipMemcpy(prev + b * cap, a.prev + b * a.scratch_n, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
   }
+  return DF_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+
+static hipError_t take_event(df_graph *g, hipEvent_t *ev) {
+  if (!g->prof_pool.empty()) {
+    *ev = g->prof_pool.back();
+    g->prof_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(ev);
+}
+
+hipError_t dfh::prof_begin(df_graph *g) {
+  if (!g->prof) return hipSuccess;
+  hipEvent_t a, b;
+  hipError_t e = take_event(g, &a);
+  if (e == hipSuccess) e = take_event(g, &b);
+  if (e != hipSuccess) return e;
+  g->prof_pending.push_back({a, b});
+  return hipEventRecord(a, g->stream);
+}
+
+hipError_t dfh::prof_end(df_graph *g) {
+  if (!g->prof || g->prof_pending.empty()) return hipSuccess;
+  return hipEventRecord(g->prof_pending.back().second, g->stream);
+}
+
+extern "C" df_status df_profile_enable(df_graph *g, int32_t enable) {
+  ENTER(g);
+  g->prof = enable != 0;
+  return DF_OK;
+}
+
+extern "C" df_status df_profile_read(df_graph *g, double *total_ms, int64_t *n_launches) {
+  ENTER(g);
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  double t = 0.0;
+  for (auto &pe : g->prof_pending) {
+    float ms = 0.f;
+    HIPCHK(g, hipEventElapsedTime(&ms, pe.first, pe.second));
+    t += ms;
+    g->prof_pool.push_back(pe.first);
+    g->prof_pool.push_back(pe.second);
+  }
+  if (total_ms) *total_ms = t;
+  if (n_launches) *n_launches = (int64_t)g->prof_pending.size();
+  g->prof_pending.clear();
   return DF_OK;
 }

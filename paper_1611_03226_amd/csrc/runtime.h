@@ -70,6 +70,9 @@ struct df_graph {
   int outputs_per_thread = 4;
   int blocks_per_cu = 0;          // persistent grid; 0 = default
   dfh::Persistent *pers = nullptr;
+  bool prof = false;                                   // record body-kernel events
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
 };
 
 namespace dfh {
@@ -80,4 +83,7 @@ df_status ensure_dpd_scratch(df_graph *g, Actor &a, int64_t n);
 df_status dpd_admit(df_graph *g, Actor &a, int64_t n, int64_t *n_adm);
 df_status dpd_enqueue(df_graph *g, Actor &a, int64_t n);
 void destroy_persistent(df_graph *g);
+// Event pair around body kernels when profiling is enabled (no-op otherwise).
+hipError_t prof_begin(df_graph *g);
+hipError_t prof_end(df_graph *g);
 }  // namespace dfh

@@ -61,6 +61,8 @@ _SIGS = {
     "df_fire": ([_P, _I32, _I64, C.c_int, C.POINTER(_I64)], _I32),
     "df_fire_many": ([_P, _I32, _P, _P, C.c_int], _I32),
     "df_set_tile": ([_P, _I32, _I32, _I32], _I32),
+    "df_profile_enable": ([_P, _I32], _I32),
+    "df_profile_read": ([_P, C.POINTER(C.c_double), C.POINTER(_I64)], _I32),
     "df_debug_last_batch": ([_P, _I32, _P, _P, _P, _I64, C.POINTER(_I64)], _I32),
     "df_dpd_forward": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
     "df_dpd_coeff_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32, _P, _I64], _I32),
@@ -208,6 +210,17 @@ def df_fire_many(g, actors, n_firings, flags: int = 0) -> None:
 
 def df_set_tile(g, tile_outputs: int = 0, outputs_per_thread: int = 0, blocks_per_cu: int = 0) -> None:
     _check(_lib.df_set_tile(g, tile_outputs, outputs_per_thread, blocks_per_cu), g)
+
+
+def df_profile_enable(g, enable: bool = True) -> None:
+    _check(_lib.df_profile_enable(g, 1 if enable else 0), g)
+
+
+def df_profile_read(g):
+    """(summed body-kernel milliseconds, launches) since the last read."""
+    t, n = C.c_double(), C.c_int64()
+    _check(_lib.df_profile_read(g, C.byref(t), C.byref(n)), g)
+    return t.value, n.value
 
 
 def df_debug_last_batch(g, actor: int, n_branches_max: int, cap: int):
