@@ -20,15 +20,19 @@
 
 namespace dfh {
 
-constexpr int ADJ_NT = 256;
 
 __device__ __forceinline__ int64_t adj_prev(const AdjArgs &a, int b, int64_t g) {
   if (a.prev) return a.prev[(int64_t)b * a.prev_stride + g];
   return (g % a.seg_firings) ? g - 1 : -1;
 }
 
+// One workgroup per (firing, chunk of outputs); one wavefront per group of 4
+// taps; lane l of a wavefront takes input samples s = l, l+64, ... of the
+// chunk's window.  For its sample a lane forms p^b once and accumulates
+// G[s+m] conj(x_s) p^b into 4 taps x BM branches of independent registers;
+// the wavefront then reduces over lanes (fixed shuffle order).
 template <int BM>
-__global__ __launch_bounds__(ADJ_NT) void k_adj_partial(AdjArgs a) {
+__global__ __launch_bounds__(512) void k_adj_partial(AdjArgs a) {
   extern __shared__ float2 lds[];
   const int M = a.M;
   const int64_t g = blockIdx.x / a.chunks_per_firing;
@@ -37,50 +41,65 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj_partial(AdjArgs a) {
   const int nout = (int)min((int64_t)a.chunk, a.r - n0);
   const int B = a.B ? a.B[g] : BM;
   const int64_t xb = g * a.r;
-  float2 *sx = lds;                       // nout + M - 1
-  float2 *sg = lds + a.chunk + M - 1;     // nout
-  float2 *red = sg + a.chunk;             // [groups][BM][M]
-  for (int i = threadIdx.x; i < nout + M - 1; i += ADJ_NT) {
+  float2 *sx = lds;                       // window: nout + M - 1 samples
+  float2 *sg = lds + a.chunk + M - 1;     // G of the chunk's outputs
+  float2 *red = sg + a.chunk;             // [BM][M] reduced sums
+  for (int i = threadIdx.x; i < nout + M - 1; i += blockDim.x) {
     const int64_t pos = n0 - (M - 1) + i;
     sx[i] = pos >= 0 ? a.x[xb + pos] : make_float2(0.f, 0.f);
   }
-  for (int i = threadIdx.x; i < nout; i += ADJ_NT) sg[i] = a.G[xb + n0 + i];
+  for (int i = threadIdx.x; i < nout; i += blockDim.x) sg[i] = a.G[xb + n0 + i];
   __syncthreads();
-  const int groups = ADJ_NT / M;
-  const int m = threadIdx.x % M;
-  const int grp = threadIdx.x / M;
-  float accr[BM], acci[BM];
+  const int lane = threadIdx.x & 63;
+  const int m0 = (threadIdx.x >> 6) * 4;  // first tap of this wavefront
+  float accr[4][BM], acci[4][BM];
 #pragma unroll
-  for (int b = 0; b < BM; ++b) accr[b] = acci[b] = 0.f;
-  if (grp < groups) {
-    for (int i = grp; i < nout; i += groups) {
-      const float2 xv = sx[i + M - 1 - m];
-      const float2 gv = sg[i];
-      const float p = xv.x * xv.x + xv.y * xv.y;
-      float wr = gv.x * xv.x + gv.y * xv.y;          // G conj(x)
-      float wi = gv.y * xv.x - gv.x * xv.y;
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int b = 0; b < BM; ++b) {
-        if (b >= B) break;
-        accr[b] += wr;
-        acci[b] += wi;
-        wr *= p;
-        wi *= p;
+    for (int b = 0; b < BM; ++b) accr[q][b] = acci[q][b] = 0.f;
+  // window index i <-> input sample n0-(M-1)+i; output n = sample + m
+  for (int i = lane; i < nout + M - 1; i += 64) {
+    const float2 xv = sx[i];
+    const float p = fmaf(xv.x, xv.x, xv.y * xv.y);
+    float pw[BM];
+    pw[0] = 1.f;
+#pragma unroll
+    for (int b = 1; b < BM; ++b) pw[b] = pw[b - 1] * p;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + q;
+      const int o = i - (M - 1) + m;      // output index within the chunk
+      if (m < M && o >= 0 && o < nout) {
+        const float2 gv = sg[o];
+        const float zr = fmaf(gv.x, xv.x, gv.y * xv.y);   // G conj(x)
+        const float zi = fmaf(gv.y, xv.x, -(gv.x * xv.y));
+#pragma unroll
+        for (int b = 0; b < BM; ++b) {
+          accr[q][b] = fmaf(zr, pw[b], accr[q][b]);
+          acci[q][b] = fmaf(zi, pw[b], acci[q][b]);
+        }
       }
     }
-#pragma unroll
-    for (int b = 0; b < BM; ++b) red[(grp * BM + b) * M + m] = make_float2(accr[b], acci[b]);
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int b = 0; b < BM; ++b) {
+      float vr = accr[q][b], vi = acci[q][b];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        vr += __shfl_xor(vr, off);
+        vi += __shfl_xor(vi, off);
+      }
+      if (lane == 0 && m0 + q < M) red[b * M + m0 + q] = make_float2(vr, vi);
+    }
   __syncthreads();
-  for (int t = threadIdx.x; t < BM * M; t += ADJ_NT) {
+  for (int t = threadIdx.x; t < BM * M; t += blockDim.x) {
     const int b = t / M, mm = t - b * M;
     float sr = 0.f, si = 0.f;
     if (b < B) {
-      for (int q = 0; q < groups; ++q) {
-        const float2 v = red[(q * BM + b) * M + mm];
-        sr += v.x;
-        si += v.y;
-      }
+      sr = red[t].x;
+      si = red[t].y;
       if (n0 == 0 && mm > 0) {
         // taps before the firing start: branch b's history source
         const int64_t pf = adj_prev(a, b, g);
@@ -88,7 +107,7 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj_partial(AdjArgs a) {
           const int64_t ii = i - mm;
           float2 xv = make_float2(0.f, 0.f);
           if (pf >= 0) xv = a.x[pf * a.r + a.r + ii];
-          const float pp = xv.x * xv.x + xv.y * xv.y;
+          const float pp = fmaf(xv.x, xv.x, xv.y * xv.y);
           float pb = 1.f;
           for (int e = 0; e < b; ++e) pb *= pp;
           const float2 gv = sg[i];
@@ -98,7 +117,7 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj_partial(AdjArgs a) {
         }
       }
     }
-    a.partial[(int64_t)blockIdx.x * a.B_max * M + b * M + mm] = make_float2(sr, si);
+    a.partial[(int64_t)blockIdx.x * a.B_max * M + t] = make_float2(sr, si);
   }
 }
 
@@ -129,11 +148,11 @@ __global__ __launch_bounds__(256) void k_adj_reduce(const float2 *partial, int64
 hipError_t launch_adj(const AdjArgs &a, hipStream_t s) {
   const int64_t blocks = a.n_firings * a.chunks_per_firing;
   if (blocks > 0) {
-    const int groups = ADJ_NT / a.M;
-    const size_t lds = sizeof(float2) * ((size_t)2 * a.chunk + a.M - 1 + (size_t)groups * kMaxBranches * a.M);
+    const int threads = 64 * ((a.M + 3) / 4);          // one wavefront per 4 taps
+    const size_t lds = sizeof(float2) * ((size_t)2 * a.chunk + a.M - 1 + (size_t)a.B_max * a.M);
     switch (a.B_max) {
 #define DF_CASE(n) \
-  case n: hipLaunchKernelGGL(k_adj_partial<n>, dim3((unsigned)blocks), dim3(ADJ_NT), lds, s, a); break;
+  case n: hipLaunchKernelGGL(k_adj_partial<n>, dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
       DF_CASE(1) DF_CASE(2) DF_CASE(3) DF_CASE(4) DF_CASE(5) DF_CASE(6) DF_CASE(7) DF_CASE(8)
       DF_CASE(9) DF_CASE(10) DF_CASE(11) DF_CASE(12) DF_CASE(13) DF_CASE(14) DF_CASE(15) DF_CASE(16)
 #undef DF_CASE

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_dpd_generic(DpdArgs a) {
 // window of K+M-1 samples staged through LDS.
 template <int M, int K>
 __global__ __launch_bounds__(512) void k_dpd_tiled(DpdArgs a) {
-  extern __shared__ float2 sx[];                       // tile + M - 1 samples
+  extern __shared__ float2 lds[];                      // [B_max*M] coefficients, [tile+M-1] samples
   const int64_t g = blockIdx.x / a.tiles_per_firing;
   const int64_t tk = blockIdx.x - g * a.tiles_per_firing;
   const int64_t t0 = tk * a.tile;
@@ -73,7 +73,8 @@ __global__ __launch_bounds__(512) void k_dpd_tiled(DpdArgs a) {
   const int64_t Rx = a.x_idx ? a.x_idx[0] : 0;
   const int64_t Wy = a.y_idx ? a.y_idx[1] : 0;
   auto hist = [&](int b, int64_t ii) { return hist_sample(a, Rx, b, g, prev_of(a, b, g), ii); };
-  dpd_tile<M, K>(sx, a.x, Rx + g * a.r, a.x_mask, a.y, Wy + g * a.r, a.y_mask, t0, nout, B, a.h, hist);
+  dpd_tile<M, K>(lds + a.B_max * M, lds, a.x, Rx + g * a.r, a.x_mask, a.y, Wy + g * a.r, a.y_mask, t0, nout, B,
+                 a.h, hist);
 }
 
 template <int M, int K>
@@ -82,7 +83,7 @@ static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile) {
   a.tile = tile;
   a.tiles_per_firing = (int32_t)((a.r + tile - 1) / tile);
   const int threads = tile / K;
-  const size_t lds = (size_t)(tile + M - 1) * sizeof(float2);
+  const size_t lds = (size_t)(tile + M - 1 + a.B_max * M) * sizeof(float2);
   const int64_t blocks = a.n_firings * a.tiles_per_firing;
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_dpd_tiled<M, K>), dim3((unsigned)blocks), dim3(threads), lds, s, a);

@@ -8,114 +8,207 @@
 //   e  = AND of m0 over the in-frame 3x3 neighbourhood   (erosion)
 //   o  = OR  of e  over the in-frame 3x3 neighbourhood   (dilation)
 //   count_j = sum o;  emit_j = 1000*count_j >= permille*W*H
-// Emission depends on the whole frame, so the batch runs as
-//   count pass -> scan of emit flags -> emit pass (recompute, write emitted
-//   masks at their scanned output slots) -> commit of channel indices.
+// Emission depends on the whole frame, so a batch runs
+//   bits pass:   opened masks, bit-packed (32 pixels per word), and counts
+//   emit scan:   output slots of the emitted frames
+//   expand pass: emitted masks as 0/255 bytes at their output slots
+//   commit:      channel indices.
+//
+// Bits pass layout: a wavefront owns a band of rows of one frame chunk and
+// one chunk of 62 consecutive 32-pixel words (lane l <-> word chunk*62+l-1;
+// lanes 0 and 63 are halo words).  It sweeps the rows of the band (plus two
+// above and below) keeping, per frame, the last horizontal-AND rows and
+// horizontal-OR rows in registers:
+//   hm(y)   = m0(y) & m0(y)<<1 & m0(y)>>1        (carries from neighbour lanes)
+//   e(y-1)  = hm(y-2) & hm(y-1) & hm(y)
+//   he(y-1) = e(y-1) | e(y-1)<<1 | e(y-1)>>1
+//   o(y-2)  = he(y-3) | he(y-2) | he(y-1)
+// Outside the frame m0 counts as set (erosion ignores it) and e as clear
+// (dilation ignores it).  Erosion and dilation over a square are separable,
+// so this equals the 3x3 definitions exactly.  In the self-delay form a
+// wavefront handles F consecutive frames per row, so each input row is
+// loaded once for F frames (F+1 row loads per F outputs).
 #include "common.h"
 
 namespace dfh {
 
-constexpr int TX = 64;   // tile width (outputs)
-constexpr int TY = 16;   // tile height
-constexpr int NTH = 256;
+constexpr int MW_CHUNK = 62;   // output words per wavefront
 
-__device__ __forceinline__ const uint8_t *frame_ptr(const uint8_t *ring, int64_t pos, int64_t mask,
-                                                    int64_t wh) {
-  return ring + (pos & mask) * wh;
+// 32 pixels of row y starting at pixel x0 (x0 < W); bytes past the row end
+// read as 0.  `fast`: 16-byte loads (row starts and the word are aligned and
+// the word lies inside the row).
+__device__ __forceinline__ void load_word(const uint8_t *frame, int y, int x0, int W, bool fast, uint32_t (&v)[8]) {
+  const uint8_t *p = frame + (int64_t)y * W + x0;
+  if (fast) {
+    const uint4 a = *reinterpret_cast<const uint4 *>(p);
+    const uint4 b = *reinterpret_cast<const uint4 *>(p + 16);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int x = x0 + 4 * k + i;
+        if (x < W) w |= (uint32_t)p[4 * k + i] << (8 * i);
+      }
+      v[k] = w;
+    }
+  }
 }
 
-// Opened mask of the tile at (x0, y0) of firing j, left in o[TY][TX].
-__device__ __forceinline__ void opened_tile(const MotionArgs &a, int64_t j, int x0, int y0,
-                                            uint8_t (&m0)[TY + 4][TX + 4],
-                                            uint8_t (&e)[TY + 2][TX + 2],
-                                            uint8_t (&o)[TY][TX]) {
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Bit i of the result: |cur_i - prev_i| > thr for the 32 pixels of a word.
+__device__ __forceinline__ uint32_t thresh_bits(const uint32_t (&c)[8], const uint32_t (&p)[8], u16x2 thr) {
+  uint32_t bits = 0;
+  const u16x2 one = {1, 1};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    // even bytes (pixels 0, 2) and odd bytes (pixels 1, 3) as u16 pairs
+    const u16x2 ce = __builtin_bit_cast(u16x2, c[k] & 0x00FF00FFu);
+    const u16x2 co = __builtin_bit_cast(u16x2, (c[k] >> 8) & 0x00FF00FFu);
+    const u16x2 pe = __builtin_bit_cast(u16x2, p[k] & 0x00FF00FFu);
+    const u16x2 po = __builtin_bit_cast(u16x2, (p[k] >> 8) & 0x00FF00FFu);
+    const u16x2 de = __builtin_elementwise_max(ce, pe) - __builtin_elementwise_min(ce, pe);
+    const u16x2 dd = __builtin_elementwise_max(co, po) - __builtin_elementwise_min(co, po);
+    // 1 where the difference exceeds the threshold, else 0
+    const u16x2 ge = __builtin_elementwise_min(__builtin_elementwise_sub_sat(de, thr), one);
+    const u16x2 go = __builtin_elementwise_min(__builtin_elementwise_sub_sat(dd, thr), one);
+    const uint32_t t = __builtin_bit_cast(uint32_t, ge) | (__builtin_bit_cast(uint32_t, go) << 1);
+    bits |= ((t | (t >> 14)) & 0xFu) << (4 * k);   // pixels 0,1 from bits 0,1; 2,3 from bits 16,17
+  }
+  return bits;
+}
+
+// Row y of the F+1 frames a wavefront needs: buf[f] is the previous frame of
+// frame f and buf[f+1] its current frame (self-delay form: frames j0-1 ..
+// j0+F-1 of the input channel, the first from the state for j0 = 0; the
+// two-channel form has F = 1: buf[0] from the PREV channel, buf[1] from CUR).
+template <int F>
+__device__ __forceinline__ void load_rows(const MotionArgs &a, int64_t j0, int nfr, int y, int x0, bool fast,
+                                          bool active, uint32_t (&buf)[F + 1][8]) {
+  if (!active || y < 0 || y >= a.H) return;
   const int64_t wh = (int64_t)a.W * a.H;
   const int64_t Rc = a.cur_idx[0];
-  const uint8_t *cur = frame_ptr(a.cur, Rc + j, a.cur_mask, wh);
-  const uint8_t *prev;
-  if (a.prev) {
-    prev = frame_ptr(a.prev, a.prev_idx[0] + j, a.prev_mask, wh);
-  } else {
-    prev = j == 0 ? a.state : frame_ptr(a.cur, Rc + j - 1, a.cur_mask, wh);
-  }
-  for (int idx = threadIdx.x; idx < (TY + 4) * (TX + 4); idx += NTH) {
-    const int ly = idx / (TX + 4), lx = idx - ly * (TX + 4);
-    const int y = y0 - 2 + ly, x = x0 - 2 + lx;
-    uint8_t v = 1;                                   // outside: ignored by erosion
-    if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
-      const int64_t off = (int64_t)y * a.W + x;
-      const int d = abs((int)cur[off] - (int)prev[off]);
-      v = d > a.thr;
+#pragma unroll
+  for (int f = 0; f <= F; ++f) {
+    if (f > nfr) break;
+    const uint8_t *fr;
+    if (a.prev) {
+      fr = f == 0 ? a.prev + ((a.prev_idx[0] + j0) & a.prev_mask) * wh
+                  : a.cur + ((Rc + j0) & a.cur_mask) * wh;
+    } else {
+      const int64_t j = j0 + f - 1;
+      fr = j < 0 ? a.state : a.cur + ((Rc + j) & a.cur_mask) * wh;
     }
-    m0[ly][lx] = v;
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < (TY + 2) * (TX + 2); idx += NTH) {
-    const int ly = idx / (TX + 2), lx = idx - ly * (TX + 2);
-    const int y = y0 - 1 + ly, x = x0 - 1 + lx;
-    uint8_t v = 0;                                   // outside: ignored by dilation
-    if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
-      v = 1;
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) v &= m0[ly + dy][lx + dx];
-    }
-    e[ly][lx] = v;
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < TY * TX; idx += NTH) {
-    const int ly = idx / TX, lx = idx - ly * TX;
-    uint8_t v = 0;
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) v |= e[ly + dy][lx + dx];
-    const int y = y0 + ly, x = x0 + lx;
-    o[ly][lx] = (y < a.H && x < a.W) ? v : 0;
-  }
-  __syncthreads();
-}
-
-__global__ __launch_bounds__(NTH) void k_motion_count(MotionArgs a) {
-  __shared__ uint8_t m0[TY + 4][TX + 4];
-  __shared__ uint8_t e[TY + 2][TX + 2];
-  __shared__ uint8_t o[TY][TX];
-  __shared__ int wsum[NTH / 64];
-  const int64_t j = blockIdx.z;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  opened_tile(a, j, x0, y0, m0, e, o);
-  int c = 0;
-  for (int idx = threadIdx.x; idx < TY * TX; idx += NTH) c += o[idx / TX][idx % TX];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int t = 0;
-    for (int w = 0; w < NTH / 64; ++w) t += wsum[w];
-    if (t) atomicAdd(&a.count[j], t);
+    load_word(fr, y, x0, a.W, fast, buf[f]);
   }
 }
 
-__global__ __launch_bounds__(NTH) void k_motion_emit(MotionArgs a) {
-  __shared__ uint8_t m0[TY + 4][TX + 4];
-  __shared__ uint8_t e[TY + 2][TX + 2];
-  __shared__ uint8_t o[TY][TX];
-  const int64_t j = blockIdx.z;
+template <int F>
+__global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int n_bands, int n_chunks) {
+  const int lane = threadIdx.x;
+  const int blk = blockIdx.x;
+  const int chunk = blk % n_chunks;
+  const int band = (blk / n_chunks) % n_bands;
+  const int64_t j0 = (int64_t)(blk / (n_chunks * n_bands)) * F;
+  const int nfr = (int)min((int64_t)F, a.n - j0);
+  const int H = a.H, wpr = a.words_per_row;
+  const int c = chunk * MW_CHUNK + lane - 1;
+  const bool word_in = c >= 0 && c < wpr;
+  const bool out_lane = lane >= 1 && lane <= MW_CHUNK && word_in;
+  const int x0 = c * 32;
+  const uint32_t valid = (c == wpr - 1 && (a.W & 31)) ? ((1u << (a.W & 31)) - 1u) : 0xFFFFFFFFu;
+  const int64_t wh = (int64_t)a.W * H;
+  const bool fast = (a.W % 32) == 0 && (wh % 16) == 0 && word_in;
+  const u16x2 thr = {(unsigned short)a.thr, (unsigned short)a.thr};
+  const int y0 = band * rows, y1 = min(H, y0 + rows);
+  uint32_t *__restrict__ bits = a.bits;
+
+  uint32_t hm2[F], hm1[F], he3[F], he2[F];
+  int cnt[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) hm2[f] = hm1[f] = he3[f] = he2[f] = 0, cnt[f] = 0;
+
+  auto process = [&](const uint32_t (&buf)[F + 1][8], int y) {
+    const bool row_in = y >= 0 && y < H;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      if (f >= nfr) break;                                  // uniform
+      uint32_t m0 = 0xFFFFFFFFu;                            // outside the frame: set
+      if (row_in && word_in) m0 = thresh_bits(buf[f + 1], buf[f], thr) | ~valid;
+      // horizontal AND with the neighbour words' edge bits
+      const uint32_t lw = __shfl_up(m0, 1), rw = __shfl_down(m0, 1);
+      const uint32_t hm = m0 & ((m0 << 1) | (lw >> 31)) & ((m0 >> 1) | (rw << 31));
+      uint32_t e = hm2[f] & hm1[f] & hm;                    // e(y-1)
+      if (!(y - 1 >= 0 && y - 1 < H) || !word_in) e = 0;    // outside the frame: clear
+      e &= valid;
+      const uint32_t le = __shfl_up(e, 1), re = __shfl_down(e, 1);
+      const uint32_t he = e | ((e << 1) | (le >> 31)) | ((e >> 1) | (re << 31));
+      const uint32_t o = (he3[f] | he2[f] | he) & valid;    // o(y-2)
+      const int yo = y - 2;
+      if (yo >= y0 && yo < y1 && out_lane) {
+        cnt[f] += __popc(o);
+        bits[(j0 + f) * (int64_t)H * wpr + (int64_t)yo * wpr + c] = o;
+      }
+      hm2[f] = hm1[f];
+      hm1[f] = hm;
+      he3[f] = he2[f];
+      he2[f] = he;
+    }
+  };
+
+  // two register row buffers: the loads of the next row are in flight while
+  // the current row is processed
+  uint32_t A[F + 1][8], Bf[F + 1][8];
+  const int ylast = y1 + 1;
+  load_rows<F>(a, j0, nfr, y0 - 2, x0, fast, word_in, A);
+  for (int y = y0 - 2; y <= ylast; y += 2) {
+    if (y + 1 <= ylast) load_rows<F>(a, j0, nfr, y + 1, x0, fast, word_in, Bf);
+    process(A, y);
+    if (y + 1 > ylast) break;
+    if (y + 2 <= ylast) load_rows<F>(a, j0, nfr, y + 2, x0, fast, word_in, A);
+    process(Bf, y + 1);
+  }
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    int t = cnt[f];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane == 0 && f < nfr && t) atomicAdd(&a.count[j0 + f], t);
+  }
+}
+
+// Expand the bit-packed mask of every emitted frame to 0/255 bytes at the
+// frame's output slot; one thread per 32-pixel word.
+__global__ __launch_bounds__(256) void k_motion_expand(MotionArgs a) {
+  const int64_t j = blockIdx.y;
   const int64_t slot = a.emit_off[j];
-  if (slot < 0) return;                               // uniform: frame not emitted
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  opened_tile(a, j, x0, y0, m0, e, o);
-  const int64_t wh = (int64_t)a.W * a.H;
-  uint8_t *dst = a.out + ((a.out_idx[1] + slot) & a.out_mask) * wh;
-  for (int idx = threadIdx.x; idx < TY * TX; idx += NTH) {
-    const int ly = idx / TX, lx = idx - ly * TX;
-    const int y = y0 + ly, x = x0 + lx;
-    if (y < a.H && x < a.W) dst[(int64_t)y * a.W + x] = o[ly][lx] ? 255 : 0;
-  }
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+  if (slot < 0) return;                                 // uniform: not emitted
+  const int W = a.W, H = a.H, wpr = a.words_per_row;
+  const int64_t wh = (int64_t)W * H;
+  const int64_t wi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
     a.index_out[(a.index_idx[1] + slot) & a.index_mask] = a.frame_base + j;
+  if (wi >= (int64_t)H * wpr) return;
+  const int y = (int)(wi / wpr), c = (int)(wi - (int64_t)y * wpr);
+  const uint32_t o = a.bits[j * (int64_t)H * wpr + wi];
+  uint8_t *dst = a.out + ((a.out_idx[1] + slot) & a.out_mask) * wh + (int64_t)y * W + c * 32;
+  uint32_t v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t nib = (o >> (4 * k)) & 0xFu;
+    v[k] = ((nib * 0x00204081u) & 0x01010101u) * 0xFFu;  // bit i -> byte i
+  }
+  if ((W % 32) == 0 && (wh % 16) == 0) {
+    reinterpret_cast<uint4 *>(dst)[0] = make_uint4(v[0], v[1], v[2], v[3]);
+    reinterpret_cast<uint4 *>(dst)[1] = make_uint4(v[4], v[5], v[6], v[7]);
+  } else {
+    const int n = min(32, W - c * 32);
+    for (int i = 0; i < n; ++i) dst[i] = (uint8_t)(v[i >> 2] >> (8 * (i & 3)));
+  }
 }
 
 // Exclusive scan of emit flags: emit_off[j] = output slot of firing j or -1,
@@ -145,10 +238,22 @@ __global__ void k_motion_commit(const int64_t *emit_off, int64_t n, int64_t *cur
   index_idx[1] += total;
 }
 
+constexpr int MOTION_F = 4;      // frames per wavefront (self-delay form)
+constexpr int MOTION_ROWS = 40;  // rows per band
+
 hipError_t launch_motion_count(const MotionArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  dim3 grid((a.W + TX - 1) / TX, (a.H + TY - 1) / TY, (unsigned)a.n);
-  hipLaunchKernelGGL(k_motion_count, grid, dim3(NTH), 0, s, a);
+  const int n_chunks = (a.words_per_row + MW_CHUNK - 1) / MW_CHUNK;
+  const int rows = MOTION_ROWS;
+  const int n_bands = (a.H + rows - 1) / rows;
+  if (a.prev) {
+    const int64_t blocks = (int64_t)n_chunks * n_bands * a.n;
+    hipLaunchKernelGGL(k_motion_bits<1>, dim3((unsigned)blocks), dim3(64), 0, s, a, rows, n_bands, n_chunks);
+  } else {
+    const int64_t blocks = (int64_t)n_chunks * n_bands * ((a.n + MOTION_F - 1) / MOTION_F);
+    hipLaunchKernelGGL(k_motion_bits<MOTION_F>, dim3((unsigned)blocks), dim3(64), 0, s, a, rows, n_bands,
+                       n_chunks);
+  }
   return hipGetLastError();
 }
 
@@ -160,8 +265,9 @@ hipError_t launch_motion_emit_scan(const int32_t *count, int64_t n, int64_t thre
 
 hipError_t launch_motion_emit(const MotionArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  dim3 grid((a.W + TX - 1) / TX, (a.H + TY - 1) / TY, (unsigned)a.n);
-  hipLaunchKernelGGL(k_motion_emit, grid, dim3(NTH), 0, s, a);
+  const int64_t words = (int64_t)a.H * a.words_per_row;
+  dim3 grid((unsigned)((words + 255) / 256), (unsigned)a.n);
+  hipLaunchKernelGGL(k_motion_expand, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(1024) void k_pers_scan(PersArgs a) {
 
 template <int M, int K>
 __global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
-  extern __shared__ float2 sx[];
+  extern __shared__ float2 lds[];                      // [Bg*M] coefficients, [tile+M-1] samples
   __shared__ int item_s;
   const int64_t total = a.tile_base[a.n_inst];
   for (;;) {
@@ -157,7 +157,8 @@ __global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
       if (pf >= 0) return d.x[(Rx + pf * d.r + d.r + ii) & d.x_mask];
       return d.hist[b * (M - 1) + (M - 1) + ii];
     };
-    dpd_tile<M, K>(sx, d.x, Rx + j * d.r, d.x_mask, d.y, Wy + j * d.r, d.y_mask, t0, nout, B, d.h, hist);
+    dpd_tile<M, K>(lds + a.Bg * M, lds, d.x, Rx + j * d.r, d.x_mask, d.y, Wy + j * d.r, d.y_mask, t0, nout, B,
+                   d.h, hist);
     __syncthreads();
   }
 }
@@ -201,8 +202,8 @@ struct Persistent {
 };
 
 static void drop_graph(Persistent *p) {
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
   p->graph = nullptr;
 }
@@ -211,22 +212,22 @@ void destroy_persistent(df_graph *g) {
   Persistent *p = g->pers;
   if (!p) return;
   drop_graph(p);
-  hipFree(p->inst);
-  hipFree(p->n_dev);
-  hipFree(p->fire_base);
-  hipFree(p->tile_base);
-  hipFree(p->prev_all);
-  hipFree(p->last_all);
-  hipFree(p->B_all);
-  hipFree(p->queue);
-  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  (void)hipFree(p->inst);
+  (void)hipFree(p->n_dev);
+  (void)hipFree(p->fire_base);
+  (void)hipFree(p->tile_base);
+  (void)hipFree(p->prev_all);
+  (void)hipFree(p->last_all);
+  (void)hipFree(p->B_all);
+  (void)hipFree(p->queue);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
   g->pers = nullptr;
 }
 
 template <int M, int K>
 static hipError_t launch_pers_body(const PersArgs &a, int threads, int blocks, hipStream_t s) {
-  const size_t lds = (size_t)(a.tile + M - 1) * sizeof(float2);
+  const size_t lds = (size_t)(a.tile + M - 1 + a.Bg * M) * sizeof(float2);
   hipLaunchKernelGGL((k_pers_body<M, K>), dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
@@ -338,8 +339,8 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
     HIPCHK(g, hipStreamSynchronize(g->stream));
     int64_t cap = 1024;
     while (cap < total) cap <<= 1;
-    hipFree(p->B_all);
-    hipFree(p->prev_all);
+    (void)hipFree(p->B_all);
+    (void)hipFree(p->prev_all);
     p->B_all = nullptr;
     p->prev_all = nullptr;
     HIPCHK(g, hipMalloc(&p->B_all, sizeof(int32_t) * cap));

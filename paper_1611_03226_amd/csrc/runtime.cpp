@@ -113,33 +113,34 @@ extern "C" df_status df_graph_create(df_graph **out, int device, void *stream) {
 }
 
 static void free_actor(Actor &a) {
-  hipFree(a.h);
-  hipFree(a.hist);
-  hipFree(a.B);
-  hipFree(a.prev);
-  hipFree(a.off);
-  hipFree(a.last);
-  hipFree(a.state);
-  hipFree(a.count);
-  hipFree(a.emit_off);
+  (void)hipFree(a.h);
+  (void)hipFree(a.hist);
+  (void)hipFree(a.B);
+  (void)hipFree(a.prev);
+  (void)hipFree(a.off);
+  (void)hipFree(a.last);
+  (void)hipFree(a.state);
+  (void)hipFree(a.count);
+  (void)hipFree(a.emit_off);
+  (void)hipFree(a.bits);
   a = Actor();
 }
 
 extern "C" df_status df_graph_destroy(df_graph *g) {
   if (!g) return fail(nullptr, DF_EINVAL, "null graph");
-  hipSetDevice(g->device);
-  if (g->stream) hipStreamSynchronize(g->stream);
+  (void)hipSetDevice(g->device);
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
   destroy_persistent(g);
   for (auto &pe : g->prof_pending) {
-    hipEventDestroy(pe.first);
-    hipEventDestroy(pe.second);
+    (void)hipEventDestroy(pe.first);
+    (void)hipEventDestroy(pe.second);
   }
-  for (auto ev : g->prof_pool) hipEventDestroy(ev);
-  for (auto &f : g->fifos) hipFree(f.ring);
+  for (auto ev : g->prof_pool) (void)hipEventDestroy(ev);
+  for (auto &f : g->fifos) (void)hipFree(f.ring);
   for (auto &a : g->actors) free_actor(a);
-  hipFree(g->idx_pool);
-  hipFree(g->err_dev);
-  if (g->own_stream && g->stream) hipStreamDestroy(g->stream);
+  (void)hipFree(g->idx_pool);
+  (void)hipFree(g->err_dev);
+  if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
   delete g;
   return DF_OK;
 }
@@ -187,14 +188,14 @@ extern "C" df_status df_fifo_create(df_graph *g, df_dtype dt, int64_t elems_per_
     else
       e = hipMemset(f.ring, 0, (size_t)(n_initial * f.token_bytes));
     if (e != hipSuccess) {
-      hipFree(f.ring);
+      (void)hipFree(f.ring);
       return fail_hip(g, e, "initial tokens");
     }
   }
   const int64_t init_idx[2] = {0, n_initial};
   e = hipMemcpy(f.idx, init_idx, sizeof init_idx, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    hipFree(f.ring);
+    (void)hipFree(f.ring);
     return fail_hip(g, e, "index init");
   }
   f.read_h = 0;
@@ -435,7 +436,7 @@ static df_status available(df_graph *g, Fifo &f, int64_t need, int64_t *avail) {
 static int64_t space_of(const Fifo &f) { return f.cap - (f.write_hi - f.read_h); }
 
 static hipError_t grow(void **p, size_t bytes) {
-  hipFree(*p);
+  (void)hipFree(*p);
   *p = nullptr;
   return hipMalloc(p, bytes);
 }
@@ -571,13 +572,17 @@ static df_status fire_motion(df_graph *g, Actor &a, int64_t n, int flags, int64_
   if (n_fired) *n_fired = n;
   if (n == 0) return DF_OK;
   const int64_t wh = (int64_t)p.width * p.height;
-  const int64_t chunk_max = 65535;                     // grid z limit of one launch
+  const int32_t wpr = (p.width + 31) / 32;
+  const int64_t frame_bits = (int64_t)wpr * p.height * 4;
+  // firings per chunk: grid limit of one launch, and <= 512 MiB of staged bits
+  const int64_t chunk_max = std::max<int64_t>(1, std::min<int64_t>(65535, (512ll << 20) / frame_bits));
   const int64_t want = std::min(n, chunk_max);
   if (want > a.cnt_cap) {
     HIPCHK(g, hipStreamSynchronize(g->stream));
-    const int64_t cap = next_pow2(want);
+    const int64_t cap = std::min(next_pow2(want), chunk_max);
     if (grow((void **)&a.count, sizeof(int32_t) * cap) != hipSuccess ||
-        grow((void **)&a.emit_off, sizeof(int64_t) * (cap + 1)) != hipSuccess)
+        grow((void **)&a.emit_off, sizeof(int64_t) * (cap + 1)) != hipSuccess ||
+        grow((void **)&a.bits, (size_t)(frame_bits * cap)) != hipSuccess)
       return fail(g, DF_ENOMEM, "scratch allocation failed");
     a.cnt_cap = cap;
   }
@@ -599,6 +604,8 @@ static df_status fire_motion(df_graph *g, Actor &a, int64_t n, int flags, int64_
     ma.index_mask = fi.mask;
     ma.count = a.count;
     ma.emit_off = a.emit_off;
+    ma.bits = a.bits;
+    ma.words_per_row = wpr;
     ma.n = k;
     ma.frame_base = a.fired;
     ma.W = p.width;

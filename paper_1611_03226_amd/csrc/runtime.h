@@ -49,6 +49,7 @@ struct Actor {
   uint8_t *state = nullptr;  // previous frame (self-delay form)
   int32_t *count = nullptr;
   int64_t *emit_off = nullptr;
+  uint32_t *bits = nullptr;  // bit-packed opened masks of a chunk of firings
   int64_t cnt_cap = 0;
 };
 

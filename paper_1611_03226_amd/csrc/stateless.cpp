@@ -54,8 +54,8 @@ hipError_t make_tables(const int32_t *ctrl, int64_t S, int64_t nf, int64_t r, in
 }
 
 void free_tables(Tables *t, hipStream_t s) {
-  if (t->B) hipFreeAsync(t->B, s);
-  if (t->prev) hipFreeAsync(t->prev, s);
+  if (t->B) (void)hipFreeAsync(t->B, s);
+  if (t->prev) (void)hipFreeAsync(t->prev, s);
 }
 
 int adj_chunk(int64_t r) { return (int)std::min<int64_t>(1024, r); }

@@ -127,3 +127,14 @@ def test_full_size_workload_bit_exact(self_delay):
             k += 1
         prev = w.frames[t]
     print(f"emitted {len(idx)} of 300")
+
+
+@pytest.mark.parametrize("self_delay", [True, False])
+def test_wide_frames_span_several_column_chunks(self_delay):
+    """2100 px rows need two 62-word column chunks; 4100 px three (and a
+    partial last word); 9 frames leave a partial frame chunk."""
+    for W in (2100, 4100):
+        say(f"motion wide W={W} self_delay={self_delay}")
+        w = gen_motion(seed=13, n_frames=9, width=W, height=45, rect_min=10, rect_max=40, segment=3)
+        masks, idx = run_motion_gpu(w.frames, self_delay, permille=0)
+        _check(w.frames, masks, idx, permille=0)
