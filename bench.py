@@ -30,6 +30,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+PER_FIRING = True
 METRIC = "DPD Msamples/s + motion frames/s at 1 GPU; % HBM roofline; batched vs per-firing"
 HBM_PEAK = 8.0e12                 # B/s, MI355X HBM3E
 # FP32 FMA issue: 256 CUs x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz.  Packed FP32
@@ -40,6 +41,11 @@ VALU_PEAK_PACKED = 2 * VALU_PEAK
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def num(x, nd=4):
+    """Rounded float, or None when not measured."""
+    return None if x is None or x != x else round(x, nd)
 
 
 def pow2(n):
@@ -59,6 +65,8 @@ def dpd_flops(ctrl, r, M):
 # ----------------------------------------------------------------------- main line
 
 def bench_dpd_scale(args, D, Graph, torch):
+    global PER_FIRING
+    PER_FIRING = not args.no_per_firing
     from workloads import dpd_scale
     w = dpd_scale()
     N, r, nf, M = len(w.x), w.r, w.n_firings, w.n_taps
@@ -104,7 +112,9 @@ def bench_dpd_scale(args, D, Graph, torch):
     G.close()
     flops = dpd_flops(w.ctrl, r, M)
     res = dict(ms=ms, body_ms=body, flops=flops, bytes=16.0 * N, N=N, err=err,
-               papr_db=w.notes["papr_db"])
+               papr_db=w.notes["papr_db"], per_firing_ms=float("nan"))
+    if not PER_FIRING:
+        return res
     # per-firing launches on the same workload (one batch of 4096 df_fire(1))
     G = Graph(0)
     ch = G.dpd_chain(w.h, r, cap_x=pow2(2 * N), cap_ctrl=pow2(2 * nf), cap_y=pow2(2 * N))
@@ -147,16 +157,18 @@ def bench_chain(D, Graph, torch, reps=50):
         G.fire(ch.actor, n)
     G.sync()
     batched = (time.perf_counter() - t0) * 1e6 / reps
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        for _ in range(n):
-            G.fire(ch.actor, 1)
-    G.sync()
-    per = (time.perf_counter() - t0) * 1e6 / reps
+    per = float("nan")
+    if PER_FIRING:
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for _ in range(n):
+                G.fire(ch.actor, 1)
+        G.sync()
+        per = (time.perf_counter() - t0) * 1e6 / reps
     G.close()
     return dict(workload="dpd chain 16384 samples, 64 firings of 256, B<=5, M=8, d=4",
-                us_per_batch_batched=round(batched, 2), us_per_batch_per_firing=round(per, 2),
-                speedup=round(per / batched, 2))
+                us_per_batch_batched=round(batched, 2), us_per_batch_per_firing=num(per, 2),
+                speedup=num(per / batched, 2))
 
 
 def bench_motion(D, Graph, torch, steps=3, warmup=1):
@@ -186,11 +198,13 @@ def bench_motion(D, Graph, torch, steps=3, warmup=1):
     D.df_profile_enable(G.g, False)
     body = body_ms / max(nl, 1)
     emitted = (G.status(mc.index)[1] - e0) / steps
-    t0 = time.perf_counter()
-    for _ in range(n):
-        G.fire(mc.actor, 1)
-    G.sync()
-    per_ms = (time.perf_counter() - t0) * 1e3
+    per_ms = float("nan")
+    if PER_FIRING:
+        t0 = time.perf_counter()
+        for _ in range(n):
+            G.fire(mc.actor, 1)
+        G.sync()
+        per_ms = (time.perf_counter() - t0) * 1e3
     G.close()
     wh = W * H
     bytes_alg = n * wh + emitted * (wh + 8)
@@ -199,7 +213,7 @@ def bench_motion(D, Graph, torch, steps=3, warmup=1):
                 emit_fraction=round(emitted / n, 4),
                 hbm_frac_alg=round(bytes_alg / (body * 1e-3) / HBM_PEAK, 4),
                 achieved_GBps=round(bytes_alg / (body * 1e-3) / 1e9, 1),
-                per_frame_fps=round(n / (per_ms * 1e-3), 1), speedup_vs_per_frame=round(per_ms / ms, 2))
+                per_frame_fps=num(n / (per_ms * 1e-3), 1), speedup_vs_per_frame=num(per_ms / ms, 2))
 
 
 def bench_instances(D, Graph, torch, steps=2):
@@ -242,12 +256,14 @@ def bench_instances(D, Graph, torch, steps=2):
         kms, kn = D.df_profile_read(G.g)
         D.df_profile_enable(G.g, False)
         res[mode + "_body_ms"] = kms / max(kn, 1) if mode != "many" else kms / steps
-    t0 = time.perf_counter()
-    for a, nf in zip(actors, nfs):
-        for _ in range(nf):
-            G.fire(a, 1)
-    G.sync()
-    res["per_firing"] = (time.perf_counter() - t0) * 1e3
+    res["per_firing"] = float("nan")
+    if PER_FIRING:
+        t0 = time.perf_counter()
+        for a, nf in zip(actors, nfs):
+            for _ in range(nf):
+                G.fire(a, 1)
+        G.sync()
+        res["per_firing"] = (time.perf_counter() - t0) * 1e3
     G.close()
     total = float(L.sum())
     flops = sum(dpd_flops(np.full(nf, b), r, M) for nf, b in zip(nfs, w.n_branches))
@@ -258,11 +274,11 @@ def bench_instances(D, Graph, torch, steps=2):
                 msps_graph=round(total / (res["graph"] * 1e-3) / 1e6, 1),
                 msps_persistent=round(total / (res["persistent"] * 1e-3) / 1e6, 1),
                 msps_per_actor=round(total / (res["many"] * 1e-3) / 1e6, 1),
-                msps_per_firing=round(total / (res["per_firing"] * 1e-3) / 1e6, 1),
-                ms=dict((k, round(v, 4)) for k, v in res.items()),
+                msps_per_firing=num(total / (res["per_firing"] * 1e-3) / 1e6, 1),
+                ms=dict((k, num(v)) for k, v in res.items()),
                 persistent_valu_frac=round(flops / (body * 1e-3) / VALU_PEAK, 4),
                 persistent_hbm_frac=round(16 * total / (body * 1e-3) / HBM_PEAK, 4),
-                speedup_graph_vs_per_firing=round(res["per_firing"] / res["graph"], 1))
+                speedup_graph_vs_per_firing=num(res["per_firing"] / res["graph"], 1))
 
 
 def bench_adaptation(D, torch, steps=10, warmup=2):
@@ -338,6 +354,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,instances,adaptation")
+    ap.add_argument("--no-per-firing", action="store_true", help="skip the per-firing launch comparisons")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (reference for traffic counters)")
     args = ap.parse_args()
@@ -369,9 +387,9 @@ def main():
                      "algorithmic_flops_per_launch": m["flops"],
                      "frac_of_packed_peak": round(achieved * 1e12 / VALU_PEAK_PACKED, 4),
                      "hbm_frac": round(m["bytes"] / body_s / HBM_PEAK, 4)},
-        "per_firing": {"ms_per_batch": round(m["per_firing_ms"], 3),
-                       "msps": round(m["N"] / (m["per_firing_ms"] * 1e-3) / 1e6, 1),
-                       "batched_speedup": round(m["per_firing_ms"] / m["ms"], 1)},
+        "per_firing": {"ms_per_batch": num(m["per_firing_ms"], 3),
+                       "msps": num(m["N"] / (m["per_firing_ms"] * 1e-3) / 1e6, 1),
+                       "batched_speedup": num(m["per_firing_ms"] / m["ms"], 1)},
         "sampled_error_vs_oracle": m["err"],
     }
     if args.calibrate_copy:
@@ -382,15 +400,17 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = nbytes
+    only = set(filter(None, args.only.split(",")))
+    extras = [("chain", lambda: bench_chain(D, Graph, torch)),
+              ("motion", lambda: bench_motion(D, Graph, torch)),
+              ("instances", lambda: bench_instances(D, Graph, torch)),
+              ("adaptation", lambda: bench_adaptation(D, torch))]
     if not args.no_extras:
-        log("dpd chain")
-        out["chain"] = bench_chain(D, Graph, torch)
-        log("motion")
-        out["motion"] = bench_motion(D, Graph, torch)
-        log("instances")
-        out["instances"] = bench_instances(D, Graph, torch)
-        log("adaptation")
-        out["adaptation"] = bench_adaptation(D, torch)
+        for name, fn in extras:
+            if only and name not in only:
+                continue
+            log(name)
+            out[name] = fn()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()

@@ -45,6 +45,7 @@ struct DpdArgs {
   int32_t M;
   int32_t tile;           // outputs per workgroup (tiled kernel)
   int32_t tiles_per_firing;
+  const int32_t *order;   // processing order of the firings (grouped by B) or nullptr
 };
 
 // Control intake + offset scan over segments of firings (one workgroup per
@@ -127,6 +128,7 @@ struct AdjArgs {
 // ---------------------------------------------------------------- launchers
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
 hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread);
+hipError_t launch_order_by_b(const int32_t *B, int64_t n, int32_t B_max, int32_t *order, hipStream_t s);
 hipError_t launch_dpd_commit(const DpdCommitArgs &a, hipStream_t s);
 hipError_t launch_advance(int64_t *idx, int64_t delta, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);

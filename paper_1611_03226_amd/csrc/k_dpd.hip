@@ -64,17 +64,18 @@ __global__ __launch_bounds__(256) void k_dpd_generic(DpdArgs a) {
 // window of K+M-1 samples staged through LDS.
 template <int M, int K>
 __global__ __launch_bounds__(512) void k_dpd_tiled(DpdArgs a) {
-  extern __shared__ float2 lds[];                      // [B_max*M] coefficients, [tile+M-1] samples
-  const int64_t g = blockIdx.x / a.tiles_per_firing;
-  const int64_t tk = blockIdx.x - g * a.tiles_per_firing;
+  extern __shared__ float2 lds[];   // [B_max*M] coefficients, [2*B_max*(M-1)] histories, window
+  const int64_t k = blockIdx.x / a.tiles_per_firing;
+  const int64_t tk = blockIdx.x - k * a.tiles_per_firing;
+  const int64_t g = a.order ? a.order[k] : k;
   const int64_t t0 = tk * a.tile;
   const int nout = (int)min((int64_t)a.tile, a.r - t0);
   const int B = a.B ? a.B[g] : a.B_const;
   const int64_t Rx = a.x_idx ? a.x_idx[0] : 0;
   const int64_t Wy = a.y_idx ? a.y_idx[1] : 0;
   auto hist = [&](int b, int64_t ii) { return hist_sample(a, Rx, b, g, prev_of(a, b, g), ii); };
-  dpd_tile<M, K>(lds + a.B_max * M, lds, a.x, Rx + g * a.r, a.x_mask, a.y, Wy + g * a.r, a.y_mask, t0, nout, B,
-                 a.h, hist);
+  dpd_tile<M, K>(lds + a.B_max * M + lds_history(a.B_max, M), lds, lds + a.B_max * M, a.x, Rx + g * a.r, a.x_mask,
+                 a.y, Wy + g * a.r, a.y_mask, t0, nout, B, a.h, hist);
 }
 
 template <int M, int K>
@@ -83,7 +84,7 @@ static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile) {
   a.tile = tile;
   a.tiles_per_firing = (int32_t)((a.r + tile - 1) / tile);
   const int threads = tile / K;
-  const size_t lds = (size_t)(tile + M - 1 + a.B_max * M) * sizeof(float2);
+  const size_t lds = (size_t)(lds_window(tile + M - 1) + a.B_max * M + lds_history(a.B_max, M)) * sizeof(float2);
   const int64_t blocks = a.n_firings * a.tiles_per_firing;
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_dpd_tiled<M, K>), dim3((unsigned)blocks), dim3(threads), lds, s, a);

@@ -54,6 +54,34 @@ __global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
   if (lane == 0 && a.last_out) a.last_out[(int64_t)seg * a.B_max + b] = lastw >= 0 ? g0 + lastw : -1;
 }
 
+// Processing order of a batch's firings, grouped by branch count B (largest
+// first).  The body kernels compile one fully unrolled code path per B;
+// grouping keeps the workgroups resident on a compute unit on one or two
+// paths, so their instructions stay cached.  The order inside a group is
+// irrelevant to the results (every firing's outputs are independent).
+__global__ __launch_bounds__(1024) void k_order_by_b(const int32_t *B, int64_t n, int32_t B_max, int32_t *order) {
+  __shared__ int32_t hist[kMaxBranches + 1], cursor[kMaxBranches + 1];
+  if (threadIdx.x <= kMaxBranches) hist[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) atomicAdd(&hist[B[j]], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int v = B_max; v >= 0; --v) {
+      cursor[v] = run;
+      run += hist[v];
+    }
+  }
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) order[atomicAdd(&cursor[B[j]], 1)] = (int32_t)j;
+}
+
+hipError_t launch_order_by_b(const int32_t *B, int64_t n, int32_t B_max, int32_t *order, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_order_by_b, dim3(1), dim3(1024), 0, s, B, n, B_max, order);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s) {
   if (a.n_segs <= 0 || a.seg_firings <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scan, dim3(a.n_segs), dim3(64 * a.B_max), 0, s, a);

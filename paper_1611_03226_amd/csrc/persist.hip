@@ -2,9 +2,9 @@
 //
 // Every instance is an independent actor with its own channels, coefficients
 // and control tokens; a batch fires instance i n_i times.  The chain is
-//   prep:     exclusive scans of n_i and of n_i * tiles_per_firing_i
-//             (firing and work-item bases), work-queue reset
+//   prep:     exclusive scan of n_i (firing bases), work-queue reset
 //   scan:     per-instance control intake and branch offset scan
+//   order:    instances grouped by branch count, work-item bases in that order
 //   body:     a persistent grid whose workgroups pull (instance, firing,
 //             tile) work items from a device counter until none is left
 //   commit:   per-instance channel indices and carried branch histories
@@ -47,7 +47,8 @@ struct PersArgs {
   int32_t Bg;             // largest n_branches_max of the instances
   const int64_t *n_fire;  // [n_inst]
   int64_t *fire_base;     // [n_inst + 1]
-  int64_t *tile_base;     // [n_inst + 1]
+  int64_t *tile_base;     // [n_inst + 1] work-item bases in processing order
+  int32_t *inst_order;    // [n_inst] processing order of the instances
   int32_t *B_all;         // [cap]
   int64_t *prev_all;      // [Bg][cap], instance-local firing index or -1
   int64_t *last_all;      // [n_inst][Bg]
@@ -57,39 +58,78 @@ struct PersArgs {
   int32_t tile;
 };
 
-// One wavefront: exclusive scans of the firing and tile counts.
+// One wavefront: exclusive scan of the firing counts (firing bases).
 __global__ __launch_bounds__(64) void k_pers_prep(PersArgs a) {
   const int lane = threadIdx.x;
-  int64_t cf = 0, ct = 0;
+  int64_t cf = 0;
   for (int c = 0; c < a.n_inst; c += 64) {
     const int i = c + lane;
-    int64_t nf = 0, nt = 0;
-    if (i < a.n_inst) {
-      nf = a.n_fire[i];
-      nt = nf * a.inst[i].tpf;
-    }
-    int64_t sf = nf, st = nt;                      // inclusive wave scans
+    const int64_t nf = i < a.n_inst ? a.n_fire[i] : 0;
+    int64_t sf = nf;                               // inclusive wave scan
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const int64_t uf = __shfl_up(sf, d);
-      const int64_t ut = __shfl_up(st, d);
-      if (lane >= d) {
-        sf += uf;
-        st += ut;
-      }
+      if (lane >= d) sf += uf;
     }
-    if (i < a.n_inst) {
-      a.fire_base[i] = cf + sf - nf;
-      a.tile_base[i] = ct + st - nt;
-    }
+    if (i < a.n_inst) a.fire_base[i] = cf + sf - nf;
     cf += __shfl(sf, 63);
-    ct += __shfl(st, 63);
   }
   if (lane == 0) {
     a.fire_base[a.n_inst] = cf;
-    a.tile_base[a.n_inst] = ct;
     a.queue[0] = 0;
   }
+}
+
+// Processing order of the instances, grouped by the branch count of their
+// first firing (largest first), and the work-item bases in that order.  The
+// body compiles one unrolled code path per branch count; grouping keeps the
+// workgroups resident on a compute unit on few paths (instruction cache).
+// The order never changes a result.
+__global__ __launch_bounds__(1024) void k_pers_order(PersArgs a) {
+  __shared__ int32_t hist[kMaxBranches + 1], cursor[kMaxBranches + 1];
+  __shared__ int64_t wsum[16];
+  if (threadIdx.x <= kMaxBranches) hist[threadIdx.x] = 0;
+  __syncthreads();
+  auto key = [&](int i) { return a.n_fire[i] > 0 ? a.B_all[a.fire_base[i]] : 0; };
+  for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) atomicAdd(&hist[key(i)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int v = kMaxBranches; v >= 0; --v) {
+      cursor[v] = run;
+      run += hist[v];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) a.inst_order[atomicAdd(&cursor[key(i)], 1)] = i;
+  __syncthreads();
+  // exclusive scan of tiles over the ordered instances
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int64_t carry = 0;
+  for (int c = 0; c < a.n_inst; c += blockDim.x) {
+    const int k = c + threadIdx.x;
+    int64_t nt = 0;
+    if (k < a.n_inst) {
+      const int i = a.inst_order[k];
+      nt = a.n_fire[i] * a.inst[i].tpf;
+    }
+    int64_t sc = nt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t u = __shfl_up(sc, d);
+      if (lane >= d) sc += u;
+    }
+    if (lane == 63) wsum[wid] = sc;
+    __syncthreads();
+    int64_t before = carry;
+    for (int w = 0; w < wid; ++w) before += wsum[w];
+    if (k < a.n_inst) a.tile_base[k] = before + sc - nt;
+    int64_t total = 0;
+    for (int w = 0; w < nw; ++w) total += wsum[w];
+    __syncthreads();
+    carry += total;
+  }
+  if (threadIdx.x == 0) a.tile_base[a.n_inst] = carry;
 }
 
 // One workgroup per instance, one wavefront per branch (as the single-actor
@@ -129,7 +169,7 @@ __global__ __launch_bounds__(1024) void k_pers_scan(PersArgs a) {
 
 template <int M, int K>
 __global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
-  extern __shared__ float2 lds[];                      // [Bg*M] coefficients, [tile+M-1] samples
+  extern __shared__ float2 lds[];   // [Bg*M] coefficients, [2*Bg*(M-1)] histories, window
   __shared__ int item_s;
   const int64_t total = a.tile_base[a.n_inst];
   for (;;) {
@@ -138,17 +178,18 @@ __global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
     const int64_t item = item_s;
     __syncthreads();
     if (item >= total) break;                       // uniform: every wave leaves
-    int lo = 0, hi = a.n_inst - 1;                  // last instance with base <= item
+    int lo = 0, hi = a.n_inst - 1;                  // last ordered instance with base <= item
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (a.tile_base[mid] <= item) lo = mid; else hi = mid - 1;
     }
-    const InstDesc &d = a.inst[lo];
+    const int inst = a.inst_order[lo];
+    const InstDesc &d = a.inst[inst];
     const int64_t local = item - a.tile_base[lo];
     const int64_t j = local / d.tpf;
     const int64_t t0 = (local - j * d.tpf) * a.tile;
     const int nout = (int)min((int64_t)a.tile, d.r - t0);
-    const int64_t gfire = a.fire_base[lo] + j;
+    const int64_t gfire = a.fire_base[inst] + j;
     const int B = a.B_all[gfire];
     const int64_t Rx = d.x_idx[0];
     const int64_t Wy = d.y_idx[1];
@@ -157,8 +198,8 @@ __global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
       if (pf >= 0) return d.x[(Rx + pf * d.r + d.r + ii) & d.x_mask];
       return d.hist[b * (M - 1) + (M - 1) + ii];
     };
-    dpd_tile<M, K>(lds + a.Bg * M, lds, d.x, Rx + j * d.r, d.x_mask, d.y, Wy + j * d.r, d.y_mask, t0, nout, B,
-                   d.h, hist);
+    dpd_tile<M, K>(lds + a.Bg * M + lds_history(a.Bg, M), lds, lds + a.Bg * M, d.x, Rx + j * d.r, d.x_mask, d.y,
+                   Wy + j * d.r, d.y_mask, t0, nout, B, d.h, hist);
     __syncthreads();
   }
 }
@@ -193,7 +234,7 @@ struct Persistent {
   int64_t *n_dev = nullptr;
   std::vector<int64_t> n_host;
   int64_t *fire_base = nullptr, *tile_base = nullptr, *prev_all = nullptr, *last_all = nullptr;
-  int32_t *B_all = nullptr, *queue = nullptr;
+  int32_t *B_all = nullptr, *queue = nullptr, *inst_order = nullptr;
   int64_t cap = 0;
   int tile = 0, K = 0, bpc = 0, ncu = 0;
   hipStream_t cap_stream = nullptr;
@@ -220,6 +261,7 @@ void destroy_persistent(df_graph *g) {
   (void)hipFree(p->last_all);
   (void)hipFree(p->B_all);
   (void)hipFree(p->queue);
+  (void)hipFree(p->inst_order);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
   g->pers = nullptr;
@@ -227,7 +269,7 @@ void destroy_persistent(df_graph *g) {
 
 template <int M, int K>
 static hipError_t launch_pers_body(const PersArgs &a, int threads, int blocks, hipStream_t s) {
-  const size_t lds = (size_t)(a.tile + M - 1 + a.Bg * M) * sizeof(float2);
+  const size_t lds = (size_t)(lds_window(a.tile + M - 1) + a.Bg * M + lds_history(a.Bg, M)) * sizeof(float2);
   hipLaunchKernelGGL((k_pers_body<M, K>), dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
@@ -237,6 +279,8 @@ static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pers_scan, dim3(a.n_inst), dim3(64 * a.Bg), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pers_order, dim3(1), dim3(1024), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int threads = p->tile / p->K;
   const int blocks = p->bpc * p->ncu;
@@ -326,6 +370,7 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
     HIPCHK(g, hipMalloc(&p->tile_base, sizeof(int64_t) * (n_actors + 1)));
     HIPCHK(g, hipMalloc(&p->last_all, sizeof(int64_t) * n_actors * Bg));
     HIPCHK(g, hipMalloc(&p->queue, sizeof(int32_t) * 64));
+    HIPCHK(g, hipMalloc(&p->inst_order, sizeof(int32_t) * n_actors));
   }
   // Tile configuration: a multiple of 64*K outputs, no larger than needed.
   const int K = g->outputs_per_thread == 8 ? 8 : 4;
@@ -399,6 +444,7 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
   pa.last_all = p->last_all;
   pa.cap = p->cap;
   pa.queue = p->queue;
+  pa.inst_order = p->inst_order;
   pa.err = g->err_dev;
   pa.tile = p->tile;
   if (flags & DF_FIRE_GRAPH) {

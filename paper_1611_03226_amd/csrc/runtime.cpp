@@ -116,6 +116,7 @@ static void free_actor(Actor &a) {
   (void)hipFree(a.h);
   (void)hipFree(a.hist);
   (void)hipFree(a.B);
+  (void)hipFree(a.order);
   (void)hipFree(a.prev);
   (void)hipFree(a.off);
   (void)hipFree(a.last);
@@ -447,6 +448,7 @@ df_status dfh::ensure_dpd_scratch(df_graph *g, Actor &a, int64_t n) {
   const int64_t cap = std::max<int64_t>(next_pow2(n), 64);
   const int bm = a.dp.n_branches_max;
   if (grow((void **)&a.B, sizeof(int32_t) * cap) != hipSuccess ||
+      grow((void **)&a.order, sizeof(int32_t) * cap) != hipSuccess ||
       grow((void **)&a.prev, sizeof(int64_t) * bm * cap) != hipSuccess ||
       grow((void **)&a.off, sizeof(int64_t) * bm * cap) != hipSuccess)
     return fail(g, DF_ENOMEM, "scratch allocation failed");
@@ -493,6 +495,8 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   sa.r = r;
   sa.err = g->err_dev;
   HIPCHK(g, launch_scan(sa, g->stream));
+  const bool ordered = n > 64;                       // grouping pays off only for many workgroups
+  if (ordered) HIPCHK(g, launch_order_by_b(a.B, n, bm, a.order, g->stream));
 
   DpdArgs da{};
   da.x = (const float2 *)fx.ring;
@@ -504,6 +508,7 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   da.h = a.h;
   da.hist = a.hist;
   da.B = a.B;
+  da.order = ordered ? a.order : nullptr;
   da.prev = a.prev;
   da.prev_stride = a.scratch_n;
   da.seg_firings = n;

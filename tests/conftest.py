@@ -9,3 +9,17 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+def pytest_collection_modifyitems(config, items):
+    """In a session that runs GPU tests, initialise torch's HIP context first,
+    so every test sees the same initialisation order (torch, then the
+    library) whichever test runs first."""
+    if any(item.get_closest_marker("gpu") for item in items):
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+                torch.cuda.set_device(0)
+        except Exception:
+            pass
