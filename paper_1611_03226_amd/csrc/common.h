@@ -125,6 +125,10 @@ struct AdjArgs {
   float2 *grad;           // [B_max][M]
 };
 
+// Workgroups of `kernel` (threads, dynamic LDS bytes) resident on the whole
+// current device at once (occupancy x compute units), cached per kernel shape.
+int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes);
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
 hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread);

@@ -93,6 +93,17 @@ __global__ __launch_bounds__(512) void k_adj_partial(AdjArgs a) {
       }
       if (lane == 0 && m0 + q < M) red[b * M + m0 + q] = make_float2(vr, vi);
     }
+  // taps before the firing start read branch b's history source: the last
+  // M-1 samples of its previous feeding firing (zeros if none), staged in
+  // LDS by all threads at once
+  float2 *hx = red + BM * M;              // [BM][M-1]
+  if (n0 == 0) {
+    for (int t = threadIdx.x; t < B * (M - 1); t += blockDim.x) {
+      const int b = t / (M - 1), i = t - b * (M - 1);
+      const int64_t pf = adj_prev(a, b, g);
+      hx[t] = pf >= 0 ? a.x[pf * a.r + a.r - (M - 1) + i] : make_float2(0.f, 0.f);
+    }
+  }
   __syncthreads();
   for (int t = threadIdx.x; t < BM * M; t += blockDim.x) {
     const int b = t / M, mm = t - b * M;
@@ -100,13 +111,10 @@ __global__ __launch_bounds__(512) void k_adj_partial(AdjArgs a) {
     if (b < B) {
       sr = red[t].x;
       si = red[t].y;
-      if (n0 == 0 && mm > 0) {
-        // taps before the firing start: branch b's history source
-        const int64_t pf = adj_prev(a, b, g);
+      if (n0 == 0) {
+        // output i, tap mm reads history sample i - mm (< 0)
         for (int i = 0; i < mm && i < nout; ++i) {
-          const int64_t ii = i - mm;
-          float2 xv = make_float2(0.f, 0.f);
-          if (pf >= 0) xv = a.x[pf * a.r + a.r + ii];
+          const float2 xv = hx[b * (M - 1) + (M - 1) + i - mm];
           const float pp = fmaf(xv.x, xv.x, xv.y * xv.y);
           float pb = 1.f;
           for (int e = 0; e < b; ++e) pb *= pp;
@@ -149,7 +157,7 @@ hipError_t launch_adj(const AdjArgs &a, hipStream_t s) {
   const int64_t blocks = a.n_firings * a.chunks_per_firing;
   if (blocks > 0) {
     const int threads = 64 * ((a.M + 3) / 4);          // one wavefront per 4 taps
-    const size_t lds = sizeof(float2) * ((size_t)2 * a.chunk + a.M - 1 + (size_t)a.B_max * a.M);
+    const size_t lds = sizeof(float2) * ((size_t)2 * a.chunk + a.M - 1 + (size_t)a.B_max * (2 * a.M - 1));
     switch (a.B_max) {
 #define DF_CASE(n) \
   case n: hipLaunchKernelGGL(k_adj_partial<n>, dim3((unsigned)blocks), dim3(threads), lds, s, a); break;

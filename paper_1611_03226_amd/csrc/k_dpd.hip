@@ -59,23 +59,58 @@ __global__ __launch_bounds__(256) void k_dpd_generic(DpdArgs a) {
 }
 
 // ------------------------------------------------------------------ tiled
-// A workgroup computes `tile` consecutive outputs of one firing (so B is
-// uniform); each thread computes K consecutive outputs from a register
-// window of K+M-1 samples staged through LDS.
+// Grid-stride loop over the batch's tiles (in the B-grouped firing order);
+// each workgroup prefetches its next tile while computing the current one.
 template <int M, int K>
-__global__ __launch_bounds__(512) void k_dpd_tiled(DpdArgs a) {
+__global__ __launch_bounds__(256) void k_dpd_tiled(DpdArgs a) {
   extern __shared__ float2 lds[];   // [B_max*M] coefficients, [2*B_max*(M-1)] histories, window
-  const int64_t k = blockIdx.x / a.tiles_per_firing;
-  const int64_t tk = blockIdx.x - k * a.tiles_per_firing;
-  const int64_t g = a.order ? a.order[k] : k;
-  const int64_t t0 = tk * a.tile;
-  const int nout = (int)min((int64_t)a.tile, a.r - t0);
-  const int B = a.B ? a.B[g] : a.B_const;
+  float2 *sh = lds, *sq = lds + a.B_max * M, *sx = sq + lds_history(a.B_max, M);
+  const int64_t n_items = a.n_firings * a.tiles_per_firing;
+  int64_t item = blockIdx.x;
+  if (item >= n_items) return;                       // uniform
   const int64_t Rx = a.x_idx ? a.x_idx[0] : 0;
   const int64_t Wy = a.y_idx ? a.y_idx[1] : 0;
-  auto hist = [&](int b, int64_t ii) { return hist_sample(a, Rx, b, g, prev_of(a, b, g), ii); };
-  dpd_tile<M, K>(lds + a.B_max * M + lds_history(a.B_max, M), lds, lds + a.B_max * M, a.x, Rx + g * a.r, a.x_mask,
-                 a.y, Wy + g * a.r, a.y_mask, t0, nout, B, a.h, hist);
+  for (int idx = threadIdx.x; idx < a.B_max * M; idx += blockDim.x) sh[idx] = a.h[idx];
+  auto job_of = [&](int64_t it, int64_t &g) {
+    const int64_t k = it / a.tiles_per_firing;
+    const int64_t tk = it - k * a.tiles_per_firing;
+    g = a.order ? a.order[k] : k;
+    TileJob j;
+    j.t0 = tk * a.tile;
+    j.nout = (int)min((int64_t)a.tile, a.r - j.t0);
+    j.B = a.B ? a.B[g] : a.B_const;
+    j.head = j.t0 == 0 && j.B > 0 && M > 1;
+    j.xb = Rx + g * a.r;
+    j.yb = Wy + g * a.r;
+    return j;
+  };
+  int64_t g;
+  TileJob job = job_of(item, g);
+  TileRegs<M, K> regs;
+  tile_prefetch<M, K>(regs, job, a.x, a.x_mask,
+                      [&](int b, int64_t ii) { return hist_sample(a, Rx, b, g, prev_of(a, b, g), ii); });
+  for (;;) {
+    tile_commit<M, K>(sx, sq, regs, job);
+    __syncthreads();
+    const int64_t next = item + gridDim.x;
+    int64_t ng = 0;
+    TileJob nj = job;
+    if (next < n_items) {
+      nj = job_of(next, ng);
+      tile_prefetch<M, K>(regs, nj, a.x, a.x_mask,
+                          [&](int b, int64_t ii) { return hist_sample(a, Rx, b, ng, prev_of(a, b, ng), ii); });
+    }
+    if (job.head) {
+      tile_head_sums<M>(sq, sh, job.B);
+      __syncthreads();
+    }
+    tile_outputs<M, K>(sx, sh, sq, job, a.y, a.y_mask);
+    if (next >= n_items) break;
+    __syncthreads();
+    item = next;
+    job = nj;
+    g = ng;
+  }
 }
 
 template <int M, int K>
@@ -85,15 +120,17 @@ static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile) {
   a.tiles_per_firing = (int32_t)((a.r + tile - 1) / tile);
   const int threads = tile / K;
   const size_t lds = (size_t)(lds_window(tile + M - 1) + a.B_max * M + lds_history(a.B_max, M)) * sizeof(float2);
-  const int64_t blocks = a.n_firings * a.tiles_per_firing;
-  if (blocks <= 0) return hipSuccess;
+  const int64_t items = a.n_firings * a.tiles_per_firing;
+  if (items <= 0) return hipSuccess;
+  const int64_t resident = resident_blocks((const void *)k_dpd_tiled<M, K>, threads, lds);
+  const int64_t blocks = items < resident ? items : resident;
   hipLaunchKernelGGL((k_dpd_tiled<M, K>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread) {
   if (a.n_firings <= 0) return hipSuccess;
-  // Tile: a multiple of 64*K outputs, at most 512 threads, no larger than
+  // Tile: a multiple of 64*K outputs, at most 256 threads, no larger than
   // needed for one firing.
   const int K = outputs_per_thread == 8 ? 8 : 4;
   int t = tile > 0 ? tile : 1024;
@@ -101,7 +138,15 @@ hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int output
   if ((int64_t)t > rr) t = (int)rr;
   t = (t / (64 * K)) * (64 * K);
   if (t < 64 * K) t = 64 * K;
-  if (t / K > 512) t = 512 * K;
+  if (t / K > 256) t = 256 * K;
+  // the history prefetch gives each thread one sample: B_max*(M-1) <= threads
+  const int need = a.B_max * (a.M - 1);
+  while (t / K < need && t / K < 256) t += 64 * K;
+  if (t / K < need) {
+    const int64_t total = a.n_firings * a.r;
+    hipLaunchKernelGGL(k_dpd_generic, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   if (a.M == 16 && K == 4) return launch_tiled<16, 4>(a, s, t);
   if (a.M == 16 && K == 8) return launch_tiled<16, 8>(a, s, t);
   if (a.M == 8 && K == 4) return launch_tiled<8, 4>(a, s, t);

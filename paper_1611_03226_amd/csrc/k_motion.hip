@@ -58,56 +58,48 @@ __device__ __forceinline__ void load_word(const uint8_t *frame, int y, int x0, i
   }
 }
 
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
 
 // Bit i of the result: |cur_i - prev_i| > thr for the 32 pixels of a word.
-__device__ __forceinline__ uint32_t thresh_bits(const uint32_t (&c)[8], const uint32_t (&p)[8], u16x2 thr) {
-  uint32_t bits = 0;
-  const u16x2 one = {1, 1};
+// Even and odd bytes are spread into 16-bit lanes (byte permutes); with
+// d = cur - prev, the pixel is unchanged iff d - (thr+1) and -(thr+1) - d are
+// both negative, i.e. bit 15 of their AND; those bits are gathered and the
+// word inverted once.
+__device__ __forceinline__ uint32_t thresh_bits(const uint32_t (&c)[8], const uint32_t (&p)[8], i16x2 t1,
+                                                i16x2 nt1) {
+  uint32_t keep = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    // even bytes (pixels 0, 2) and odd bytes (pixels 1, 3) as u16 pairs
-    const u16x2 ce = __builtin_bit_cast(u16x2, c[k] & 0x00FF00FFu);
-    const u16x2 co = __builtin_bit_cast(u16x2, (c[k] >> 8) & 0x00FF00FFu);
-    const u16x2 pe = __builtin_bit_cast(u16x2, p[k] & 0x00FF00FFu);
-    const u16x2 po = __builtin_bit_cast(u16x2, (p[k] >> 8) & 0x00FF00FFu);
-    const u16x2 de = __builtin_elementwise_max(ce, pe) - __builtin_elementwise_min(ce, pe);
-    const u16x2 dd = __builtin_elementwise_max(co, po) - __builtin_elementwise_min(co, po);
-    // 1 where the difference exceeds the threshold, else 0
-    const u16x2 ge = __builtin_elementwise_min(__builtin_elementwise_sub_sat(de, thr), one);
-    const u16x2 go = __builtin_elementwise_min(__builtin_elementwise_sub_sat(dd, thr), one);
-    const uint32_t t = __builtin_bit_cast(uint32_t, ge) | (__builtin_bit_cast(uint32_t, go) << 1);
-    bits |= ((t | (t >> 14)) & 0xFu) << (4 * k);   // pixels 0,1 from bits 0,1; 2,3 from bits 16,17
+    const i16x2 ce = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(c[k], c[k], 0x0c020c00u));   // bytes 0,2
+    const i16x2 co = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(c[k], c[k], 0x0c030c01u));   // bytes 1,3
+    const i16x2 pe = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(p[k], p[k], 0x0c020c00u));
+    const i16x2 po = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(p[k], p[k], 0x0c030c01u));
+    const i16x2 de = ce - pe, dd = co - po;
+    const uint32_t ye = __builtin_bit_cast(uint32_t, de - t1) & __builtin_bit_cast(uint32_t, nt1 - de);
+    const uint32_t yo = __builtin_bit_cast(uint32_t, dd - t1) & __builtin_bit_cast(uint32_t, nt1 - dd);
+    // unchanged flags: pixel 0 bit 15, pixel 2 bit 31 (ye); pixels 1, 3 (yo)
+    const uint32_t t = ((ye >> 15) & 0x00010001u) | ((yo >> 14) & 0x00020002u);
+    keep |= ((t | (t >> 14)) & 0xFu) << (4 * k);
   }
-  return bits;
+  return ~keep;
 }
 
 // Row y of the F+1 frames a wavefront needs: buf[f] is the previous frame of
 // frame f and buf[f+1] its current frame (self-delay form: frames j0-1 ..
 // j0+F-1 of the input channel, the first from the state for j0 = 0; the
 // two-channel form has F = 1: buf[0] from the PREV channel, buf[1] from CUR).
-template <int F>
-__device__ __forceinline__ void load_rows(const MotionArgs &a, int64_t j0, int nfr, int y, int x0, bool fast,
+template <int F, bool FAST>
+__device__ __forceinline__ void load_rows(const uint8_t *const (&fr)[F + 1], int nfr, int y, int x0, int W,
                                           bool active, uint32_t (&buf)[F + 1][8]) {
-  if (!active || y < 0 || y >= a.H) return;
-  const int64_t wh = (int64_t)a.W * a.H;
-  const int64_t Rc = a.cur_idx[0];
+  if (!active) return;
 #pragma unroll
   for (int f = 0; f <= F; ++f) {
     if (f > nfr) break;
-    const uint8_t *fr;
-    if (a.prev) {
-      fr = f == 0 ? a.prev + ((a.prev_idx[0] + j0) & a.prev_mask) * wh
-                  : a.cur + ((Rc + j0) & a.cur_mask) * wh;
-    } else {
-      const int64_t j = j0 + f - 1;
-      fr = j < 0 ? a.state : a.cur + ((Rc + j) & a.cur_mask) * wh;
-    }
-    load_word(fr, y, x0, a.W, fast, buf[f]);
+    load_word(fr[f], y, x0, W, FAST, buf[f]);
   }
 }
 
-template <int F>
+template <int F, bool FAST>
 __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int n_bands, int n_chunks) {
   const int lane = threadIdx.x;
   const int blk = blockIdx.x;
@@ -115,17 +107,32 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
   const int band = (blk / n_chunks) % n_bands;
   const int64_t j0 = (int64_t)(blk / (n_chunks * n_bands)) * F;
   const int nfr = (int)min((int64_t)F, a.n - j0);
-  const int H = a.H, wpr = a.words_per_row;
+  const int H = a.H, W = a.W, wpr = a.words_per_row;
   const int c = chunk * MW_CHUNK + lane - 1;
   const bool word_in = c >= 0 && c < wpr;
   const bool out_lane = lane >= 1 && lane <= MW_CHUNK && word_in;
-  const int x0 = c * 32;
-  const uint32_t valid = (c == wpr - 1 && (a.W & 31)) ? ((1u << (a.W & 31)) - 1u) : 0xFFFFFFFFu;
-  const int64_t wh = (int64_t)a.W * H;
-  const bool fast = (a.W % 32) == 0 && (wh % 16) == 0 && word_in;
-  const u16x2 thr = {(unsigned short)a.thr, (unsigned short)a.thr};
+  const int x0 = word_in ? c * 32 : 0;
+  const uint32_t valid = (c == wpr - 1 && (W & 31)) ? ((1u << (W & 31)) - 1u) : 0xFFFFFFFFu;
+  const int64_t wh = (int64_t)W * H;
+  const short t1s = (short)(a.thr + 1);
+  const i16x2 t1 = {t1s, t1s}, nt1 = {(short)-t1s, (short)-t1s};
   const int y0 = band * rows, y1 = min(H, y0 + rows);
   uint32_t *__restrict__ bits = a.bits;
+
+  // frame base pointers of the chunk (see load_rows)
+  const uint8_t *fr[F + 1];
+  {
+    const int64_t Rc = a.cur_idx[0];
+#pragma unroll
+    for (int f = 0; f <= F; ++f) {
+      if (a.prev) {
+        fr[f] = f == 0 ? a.prev + ((a.prev_idx[0] + j0) & a.prev_mask) * wh : a.cur + ((Rc + j0) & a.cur_mask) * wh;
+      } else {
+        const int64_t j = j0 + f - 1;
+        fr[f] = j < 0 ? a.state : a.cur + ((Rc + min(j, a.n - 1)) & a.cur_mask) * wh;
+      }
+    }
+  }
 
   uint32_t hm2[F], hm1[F], he3[F], he2[F];
   int cnt[F];
@@ -133,18 +140,17 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
   for (int f = 0; f < F; ++f) hm2[f] = hm1[f] = he3[f] = he2[f] = 0, cnt[f] = 0;
 
   auto process = [&](const uint32_t (&buf)[F + 1][8], int y) {
-    const bool row_in = y >= 0 && y < H;
+    const bool in = y >= 0 && y < H && word_in;
+    const bool e_in = y - 1 >= 0 && y - 1 < H && word_in;
 #pragma unroll
     for (int f = 0; f < F; ++f) {
       if (f >= nfr) break;                                  // uniform
-      uint32_t m0 = 0xFFFFFFFFu;                            // outside the frame: set
-      if (row_in && word_in) m0 = thresh_bits(buf[f + 1], buf[f], thr) | ~valid;
+      const uint32_t th = thresh_bits(buf[f + 1], buf[f], t1, nt1);
+      const uint32_t m0 = in ? (th | ~valid) : 0xFFFFFFFFu; // outside the frame: set
       // horizontal AND with the neighbour words' edge bits
       const uint32_t lw = __shfl_up(m0, 1), rw = __shfl_down(m0, 1);
       const uint32_t hm = m0 & ((m0 << 1) | (lw >> 31)) & ((m0 >> 1) | (rw << 31));
-      uint32_t e = hm2[f] & hm1[f] & hm;                    // e(y-1)
-      if (!(y - 1 >= 0 && y - 1 < H) || !word_in) e = 0;    // outside the frame: clear
-      e &= valid;
+      const uint32_t e = e_in ? (hm2[f] & hm1[f] & hm & valid) : 0u;   // e(y-1); outside: clear
       const uint32_t le = __shfl_up(e, 1), re = __shfl_down(e, 1);
       const uint32_t he = e | ((e << 1) | (le >> 31)) | ((e >> 1) | (re << 31));
       const uint32_t o = (he3[f] | he2[f] | he) & valid;    // o(y-2)
@@ -161,15 +167,22 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
   };
 
   // two register row buffers: the loads of the next row are in flight while
-  // the current row is processed
+  // the current row is processed (rows outside the frame are not loaded)
   uint32_t A[F + 1][8], Bf[F + 1][8];
+#pragma unroll
+  for (int f = 0; f <= F; ++f)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) A[f][k] = Bf[f][k] = 0;
   const int ylast = y1 + 1;
-  load_rows<F>(a, j0, nfr, y0 - 2, x0, fast, word_in, A);
+  auto rowload = [&](int y, uint32_t (&buf)[F + 1][8]) {
+    load_rows<F, FAST>(fr, nfr, y, x0, W, word_in && y >= 0 && y < H, buf);
+  };
+  rowload(y0 - 2, A);
   for (int y = y0 - 2; y <= ylast; y += 2) {
-    if (y + 1 <= ylast) load_rows<F>(a, j0, nfr, y + 1, x0, fast, word_in, Bf);
+    if (y + 1 <= ylast) rowload(y + 1, Bf);
     process(A, y);
     if (y + 1 > ylast) break;
-    if (y + 2 <= ylast) load_rows<F>(a, j0, nfr, y + 2, x0, fast, word_in, A);
+    if (y + 2 <= ylast) rowload(y + 2, A);
     process(Bf, y + 1);
   }
 #pragma unroll
@@ -182,31 +195,35 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
 }
 
 // Expand the bit-packed mask of every emitted frame to 0/255 bytes at the
-// frame's output slot; one thread per 32-pixel word.
+// frame's output slot.  One thread per 16-pixel half word, so the lanes of a
+// wavefront store one contiguous 1 KiB span per instruction.
+template <bool FAST>
 __global__ __launch_bounds__(256) void k_motion_expand(MotionArgs a) {
   const int64_t j = blockIdx.y;
   const int64_t slot = a.emit_off[j];
   if (slot < 0) return;                                 // uniform: not emitted
   const int W = a.W, H = a.H, wpr = a.words_per_row;
   const int64_t wh = (int64_t)W * H;
-  const int64_t wi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t hw = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0)
     a.index_out[(a.index_idx[1] + slot) & a.index_mask] = a.frame_base + j;
-  if (wi >= (int64_t)H * wpr) return;
+  if (hw >= 2 * (int64_t)H * wpr) return;
+  const int64_t wi = hw >> 1;
+  const int half = (int)(hw & 1);
   const int y = (int)(wi / wpr), c = (int)(wi - (int64_t)y * wpr);
-  const uint32_t o = a.bits[j * (int64_t)H * wpr + wi];
-  uint8_t *dst = a.out + ((a.out_idx[1] + slot) & a.out_mask) * wh + (int64_t)y * W + c * 32;
-  uint32_t v[8];
+  const uint32_t o = a.bits[j * (int64_t)H * wpr + wi] >> (16 * half);
+  const int x = c * 32 + 16 * half;
+  uint8_t *dst = a.out + ((a.out_idx[1] + slot) & a.out_mask) * wh + (int64_t)y * W + x;
+  uint32_t v[4];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < 4; ++k) {
     const uint32_t nib = (o >> (4 * k)) & 0xFu;
     v[k] = ((nib * 0x00204081u) & 0x01010101u) * 0xFFu;  // bit i -> byte i
   }
-  if ((W % 32) == 0 && (wh % 16) == 0) {
-    reinterpret_cast<uint4 *>(dst)[0] = make_uint4(v[0], v[1], v[2], v[3]);
-    reinterpret_cast<uint4 *>(dst)[1] = make_uint4(v[4], v[5], v[6], v[7]);
+  if (FAST) {
+    *reinterpret_cast<uint4 *>(dst) = make_uint4(v[0], v[1], v[2], v[3]);
   } else {
-    const int n = min(32, W - c * 32);
+    const int n = min(16, W - x);
     for (int i = 0; i < n; ++i) dst[i] = (uint8_t)(v[i >> 2] >> (8 * (i & 3)));
   }
 }
@@ -239,22 +256,27 @@ __global__ void k_motion_commit(const int64_t *emit_off, int64_t n, int64_t *cur
 }
 
 constexpr int MOTION_F = 4;      // frames per wavefront (self-delay form)
-constexpr int MOTION_ROWS = 40;  // rows per band
+constexpr int MOTION_ROWS = 32;  // rows per band
+
+template <int F>
+static hipError_t launch_bits(const MotionArgs &a, hipStream_t s, int64_t blocks, int rows, int n_bands,
+                              int n_chunks) {
+  const bool fast = (a.W % 32) == 0 && ((int64_t)a.W * a.H) % 16 == 0;
+  if (fast)
+    hipLaunchKernelGGL((k_motion_bits<F, true>), dim3((unsigned)blocks), dim3(64), 0, s, a, rows, n_bands, n_chunks);
+  else
+    hipLaunchKernelGGL((k_motion_bits<F, false>), dim3((unsigned)blocks), dim3(64), 0, s, a, rows, n_bands, n_chunks);
+  return hipGetLastError();
+}
 
 hipError_t launch_motion_count(const MotionArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   const int n_chunks = (a.words_per_row + MW_CHUNK - 1) / MW_CHUNK;
   const int rows = MOTION_ROWS;
   const int n_bands = (a.H + rows - 1) / rows;
-  if (a.prev) {
-    const int64_t blocks = (int64_t)n_chunks * n_bands * a.n;
-    hipLaunchKernelGGL(k_motion_bits<1>, dim3((unsigned)blocks), dim3(64), 0, s, a, rows, n_bands, n_chunks);
-  } else {
-    const int64_t blocks = (int64_t)n_chunks * n_bands * ((a.n + MOTION_F - 1) / MOTION_F);
-    hipLaunchKernelGGL(k_motion_bits<MOTION_F>, dim3((unsigned)blocks), dim3(64), 0, s, a, rows, n_bands,
-                       n_chunks);
-  }
-  return hipGetLastError();
+  if (a.prev) return launch_bits<1>(a, s, (int64_t)n_chunks * n_bands * a.n, rows, n_bands, n_chunks);
+  return launch_bits<MOTION_F>(a, s, (int64_t)n_chunks * n_bands * ((a.n + MOTION_F - 1) / MOTION_F), rows, n_bands,
+                               n_chunks);
 }
 
 hipError_t launch_motion_emit_scan(const int32_t *count, int64_t n, int64_t thresh, int64_t *off,
@@ -265,9 +287,12 @@ hipError_t launch_motion_emit_scan(const int32_t *count, int64_t n, int64_t thre
 
 hipError_t launch_motion_emit(const MotionArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  const int64_t words = (int64_t)a.H * a.words_per_row;
-  dim3 grid((unsigned)((words + 255) / 256), (unsigned)a.n);
-  hipLaunchKernelGGL(k_motion_expand, grid, dim3(256), 0, s, a);
+  const int64_t halves = 2 * (int64_t)a.H * a.words_per_row;
+  dim3 grid((unsigned)((halves + 255) / 256), (unsigned)a.n);
+  if ((a.W % 32) == 0 && ((int64_t)a.W * a.H) % 16 == 0)
+    hipLaunchKernelGGL(k_motion_expand<true>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_motion_expand<false>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

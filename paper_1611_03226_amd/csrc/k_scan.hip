@@ -82,6 +82,29 @@ hipError_t launch_order_by_b(const int32_t *B, int64_t n, int32_t B_max, int32_t
   return hipGetLastError();
 }
 
+int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes) {
+  struct Entry {
+    const void *k;
+    int threads, dev;
+    size_t lds;
+    int64_t n;
+  };
+  static Entry cache[64];
+  static int used = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  for (int i = 0; i < used; ++i)
+    if (cache[i].k == kernel && cache[i].threads == threads && cache[i].lds == lds_bytes && cache[i].dev == dev)
+      return cache[i].n;
+  int per_cu = 0, ncu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds_bytes) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
+  const int64_t n = (int64_t)per_cu * ncu;
+  if (used < 64) cache[used++] = Entry{kernel, threads, dev, lds_bytes, n};
+  return n;
+}
+
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s) {
   if (a.n_segs <= 0 || a.seg_firings <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scan, dim3(a.n_segs), dim3(64 * a.B_max), 0, s, a);

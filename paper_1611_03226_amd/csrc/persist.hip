@@ -167,40 +167,88 @@ __global__ __launch_bounds__(1024) void k_pers_scan(PersArgs a) {
   if (lane == 0) a.last_all[(int64_t)i * a.Bg + b] = lastw;
 }
 
+constexpr int kCoefRegs = 4;   // coefficients per thread (B_max*M <= 4*threads)
+
+// Persistent body: workgroups pull (instance, firing, tile) work items from
+// the queue; the next item's window, histories and coefficients are loaded
+// into registers while the current item is computed from LDS.
 template <int M, int K>
 __global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
   extern __shared__ float2 lds[];   // [Bg*M] coefficients, [2*Bg*(M-1)] histories, window
+  float2 *sh = lds, *sq = lds + a.Bg * M, *sx = sq + lds_history(a.Bg, M);
   __shared__ int item_s;
   const int64_t total = a.tile_base[a.n_inst];
-  for (;;) {
-    if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1);
-    __syncthreads();
-    const int64_t item = item_s;
-    __syncthreads();
-    if (item >= total) break;                       // uniform: every wave leaves
-    int lo = 0, hi = a.n_inst - 1;                  // last ordered instance with base <= item
+  if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1);
+  __syncthreads();
+  int64_t item = item_s;
+  if (item >= total) return;                          // uniform: every wave leaves
+  struct Item {
+    int inst;
+    int64_t gfire, Rx, j;
+  };
+  auto decode = [&](int64_t it, Item &d, TileJob &job) {
+    int lo = 0, hi = a.n_inst - 1;                    // last ordered instance with base <= it
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (a.tile_base[mid] <= item) lo = mid; else hi = mid - 1;
+      if (a.tile_base[mid] <= it) lo = mid; else hi = mid - 1;
     }
-    const int inst = a.inst_order[lo];
-    const InstDesc &d = a.inst[inst];
-    const int64_t local = item - a.tile_base[lo];
-    const int64_t j = local / d.tpf;
-    const int64_t t0 = (local - j * d.tpf) * a.tile;
-    const int nout = (int)min((int64_t)a.tile, d.r - t0);
-    const int64_t gfire = a.fire_base[inst] + j;
-    const int B = a.B_all[gfire];
-    const int64_t Rx = d.x_idx[0];
-    const int64_t Wy = d.y_idx[1];
-    auto hist = [&](int b, int64_t ii) {
-      const int64_t pf = a.prev_all[(int64_t)b * a.cap + gfire];
-      if (pf >= 0) return d.x[(Rx + pf * d.r + d.r + ii) & d.x_mask];
-      return d.hist[b * (M - 1) + (M - 1) + ii];
-    };
-    dpd_tile<M, K>(lds + a.Bg * M + lds_history(a.Bg, M), lds, lds + a.Bg * M, d.x, Rx + j * d.r, d.x_mask, d.y,
-                   Wy + j * d.r, d.y_mask, t0, nout, B, d.h, hist);
+    d.inst = a.inst_order[lo];
+    const InstDesc &ds = a.inst[d.inst];
+    const int64_t local = it - a.tile_base[lo];
+    d.j = local / ds.tpf;
+    d.gfire = a.fire_base[d.inst] + d.j;
+    d.Rx = ds.x_idx[0];
+    job.t0 = (local - d.j * ds.tpf) * a.tile;
+    job.nout = (int)min((int64_t)a.tile, ds.r - job.t0);
+    job.B = a.B_all[d.gfire];
+    job.head = (job.t0 == 0 && job.B > 0 && M > 1) ? 1 : 0;
+    job.xb = d.Rx + d.j * ds.r;
+    job.yb = ds.y_idx[1] + d.j * ds.r;
+  };
+  auto prefetch = [&](const Item &d, const TileJob &job, TileRegs<M, K> &r, float2 (&cr)[kCoefRegs]) {
+    const InstDesc &ds = a.inst[d.inst];
+    tile_prefetch<M, K>(r, job, ds.x, ds.x_mask, [&](int b, int64_t ii) {
+      const int64_t pf = a.prev_all[(int64_t)b * a.cap + d.gfire];
+      if (pf >= 0) return ds.x[(d.Rx + pf * ds.r + ds.r + ii) & ds.x_mask];
+      return ds.hist[b * (M - 1) + (M - 1) + ii];
+    });
+#pragma unroll
+    for (int u = 0; u < kCoefRegs; ++u) {
+      const int idx = threadIdx.x + u * blockDim.x;
+      cr[u] = idx < job.B * M ? ds.h[idx] : make_float2(0.f, 0.f);
+    }
+  };
+  Item cur;
+  TileJob job;
+  decode(item, cur, job);
+  TileRegs<M, K> regs;
+  float2 creg[kCoefRegs];
+  prefetch(cur, job, regs, creg);
+  for (;;) {
+    tile_commit<M, K>(sx, sq, regs, job);
+#pragma unroll
+    for (int u = 0; u < kCoefRegs; ++u) {
+      const int idx = threadIdx.x + u * blockDim.x;
+      if (idx < job.B * M) sh[idx] = creg[u];
+    }
+    if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1);
     __syncthreads();
+    const int64_t next = item_s;
+    Item nd = cur;
+    TileJob nj = job;
+    if (next < total) {
+      decode(next, nd, nj);
+      prefetch(nd, nj, regs, creg);
+    }
+    if (job.head) {
+      tile_head_sums<M>(sq, sh, job.B);
+      __syncthreads();
+    }
+    tile_outputs<M, K>(sx, sh, sq, job, a.inst[cur.inst].y, a.inst[cur.inst].y_mask);
+    if (next >= total) break;
+    __syncthreads();
+    cur = nd;
+    job = nj;
   }
 }
 
@@ -275,6 +323,8 @@ static hipError_t launch_pers_body(const PersArgs &a, int threads, int blocks, h
 }
 
 static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s, df_graph *prof_g) {
+  if (a.Bg * p->M > kCoefRegs * (p->tile / p->K) || a.Bg * (p->M - 1) > kHistRegs * (p->tile / p->K))
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pers_prep, dim3(1), dim3(64), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -378,6 +428,8 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
   const int64_t rr = ((max_r + 64 * K - 1) / (64 * K)) * (64 * K);
   if (tile > rr) tile = (int)rr;
   tile = std::max(64 * K, std::min(512 * K, (tile / (64 * K)) * (64 * K)));
+  // one history sample and up to kCoefRegs coefficients per thread
+  while (tile / K < 512 && (tile / K < Bg * (M - 1) || Bg * M > kCoefRegs * (tile / K))) tile += 64 * K;
   const int bpc = g->blocks_per_cu > 0 ? g->blocks_per_cu : 4;
   bool rebuild = !same_list || tile != p->tile || K != p->K || bpc != p->bpc;
   if (total > p->cap) {
