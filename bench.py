@@ -31,12 +31,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PER_FIRING = True
+COPY = {"Bps": None}               # measured stream-copy bandwidth
 METRIC = "DPD Msamples/s + motion frames/s at 1 GPU; % HBM roofline; batched vs per-firing"
 HBM_PEAK = 8.0e12                 # B/s, MI355X HBM3E
 # FP32 FMA issue: 256 CUs x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz.  Packed FP32
 # (two FMAs per lane per cycle, 157.3 TFLOP/s) is disabled at compile time.
 VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
 VALU_PEAK_PACKED = 2 * VALU_PEAK
+
+
+# HBM traffic of the dominant kernel, from two rocprofv3 counter runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on the stream-copy
+# kernel; reported only while the kernel's sources are the ones profiled.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dpd_tiled_dpd_scale_2p24_traffic.md")
+KERNEL_SOURCES = ("paper_1611_03226_amd/csrc/k_dpd.hip", "paper_1611_03226_amd/csrc/dpd_tile.h",
+                  "paper_1611_03226_amd/csrc/common.h", "paper_1611_03226_amd/csrc/k_scan.hip")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch recorded in the traffic summary, or None if it
+    is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.strip()[2:].split(": ", 1) for line in fh if line.startswith("- ") and ": " in line)
+        if kv.get("source_sha256") != kernel_sources_sha256():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -213,6 +244,7 @@ def bench_motion(D, Graph, torch, steps=3, warmup=1):
                 emit_fraction=round(emitted / n, 4),
                 hbm_frac_alg=round(bytes_alg / (body * 1e-3) / HBM_PEAK, 4),
                 achieved_GBps=round(bytes_alg / (body * 1e-3) / 1e9, 1),
+                hbm_frac_of_copy=num(bytes_alg / (body * 1e-3) / COPY["Bps"]) if COPY["Bps"] else None,
                 per_frame_fps=num(n / (per_ms * 1e-3), 1), speedup_vs_per_frame=num(per_ms / ms, 2))
 
 
@@ -347,6 +379,69 @@ def cpu_baseline(budget_s=12.0):
                        f"FP64 sequential dataflow scheduler, {dt:.1f} s")
 
 
+def summarize_pmc(fetch_csv, write_csv, bench_json):
+    """Traffic summary: per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the
+    actor body and of the stream copy, scaled by the copy's bytes."""
+    import csv
+
+    def per_dispatch(path, counter):
+        vals = {}
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                name = row["Kernel_Name"]
+                key = "copy" if "k_stream_copy" in name else ("dpd" if "k_dpd_tiled<16, 4>" in name else None)
+                if key:
+                    vals.setdefault(key, {}).setdefault(row["Dispatch_Id"], 0.0)
+                    vals[key][row["Dispatch_Id"]] += float(row["Counter_Value"])
+        return {k: (sum(v.values()) / len(v), len(v)) for k, v in vals.items()}
+
+    with open(bench_json) as fh:
+        line = [ln for ln in fh if ln.startswith("{")][-1]
+    b = json.loads(line)
+    copy_bytes = b["hbm_copy"]["bytes_read"]
+    alg = b["roofline"]["algorithmic_bytes_per_launch"]
+    f = per_dispatch(fetch_csv, "FETCH_SIZE")
+    w = per_dispatch(write_csv, "WRITE_SIZE")
+    fr = f["copy"][0] * 1024 / copy_bytes        # counter bytes per copied byte (read side)
+    fw = w["copy"][0] * 1024 / copy_bytes
+    rd = f["dpd"][0] * 1024 / fr
+    wr = w["dpd"][0] * 1024 / fw
+    lines = [
+        "# HBM traffic of k_dpd_tiled<16,4>, 2^24-sample workload (4096 firings of 4096, B 1..10, M 16)",
+        "",
+        "Commands (on the GPU host, from the repository root; `cd /tmp && export TMPDIR=/tmp` first):",
+        "",
+        "    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'k_dpd_tiled|k_stream_copy' -d pmc_fetch -o fetch "
+        "--output-format csv -- python3 /root/repo/bench.py --no-cpu --no-extras --no-per-firing --steps 5 "
+        "--warmup 1 > fetch.json",
+        "    rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'k_dpd_tiled|k_stream_copy' -d pmc_write -o write "
+        "--output-format csv -- python3 /root/repo/bench.py --no-cpu --no-extras --no-per-firing --steps 5 "
+        "--warmup 1 > write.json",
+        "    python3 /root/repo/bench.py --summarize-pmc pmc_fetch/fetch_counter_collection.csv "
+        "pmc_write/write_counter_collection.csv fetch.json",
+        "",
+        f"Stream copy of {copy_bytes} bytes (k_stream_copy, {f['copy'][1]} dispatches): "
+        f"FETCH_SIZE {f['copy'][0]:.1f} KiB, WRITE_SIZE {w['copy'][0]:.1f} KiB per dispatch; "
+        f"scale factors {fr:.4f} (read) and {fw:.4f} (write) counter bytes per byte moved.",
+        "",
+        f"k_dpd_tiled<16,4> ({f['dpd'][1]} / {w['dpd'][1]} dispatches): FETCH_SIZE {f['dpd'][0]:.1f} KiB, "
+        f"WRITE_SIZE {w['dpd'][0]:.1f} KiB per dispatch.",
+        "",
+        f"- hbm_read_bytes_per_launch: {rd:.0f}",
+        f"- hbm_write_bytes_per_launch: {wr:.0f}",
+        f"- hbm_bytes_per_launch: {rd + wr:.0f}",
+        f"- algorithmic_bytes_per_launch: {alg:.0f}",
+        f"- traffic_over_algorithmic: {(rd + wr) / alg:.4f}",
+        f"- source_sha256: {b['roofline']['kernel_sources_sha256']}",
+        "",
+    ]
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,9 +451,14 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,instances,adaptation")
     ap.add_argument("--no-per-firing", action="store_true", help="skip the per-firing launch comparisons")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="also run one plain device copy of MIB MiB (reference for traffic counters)")
+    ap.add_argument("--calibrate-copy", type=int, default=1024, metavar="MIB",
+                    help="stream-copy reference size in MiB (bandwidth and traffic-counter reference; 0: off)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="write the traffic summary from two rocprofv3 --pmc runs of this script (no GPU)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on one "
               f"MI355X; sharding across GPUs is described, not implemented)", file=sys.stderr)
@@ -382,7 +482,8 @@ def main():
                                "control uniform 1..10 branches (odd orders to 19), 16 taps",
                    "n_samples": m["N"], "firing_size": 4096, "n_branches_max": 10, "n_taps": 16},
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK / 1e12, 1),
-                     "unit": "TFLOP/s", "frac": round(achieved * 1e12 / VALU_PEAK, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved * 1e12 / VALU_PEAK, 4), "traffic": measured_traffic(),
+                     "algorithmic_bytes_per_launch": m["bytes"], "kernel_sources_sha256": kernel_sources_sha256(),
                      "kernel": "k_dpd_tiled<16,4>", "kernel_ms": round(m["body_ms"], 4),
                      "algorithmic_flops_per_launch": m["flops"],
                      "frac_of_packed_peak": round(achieved * 1e12 / VALU_PEAK_PACKED, 4),
@@ -394,12 +495,22 @@ def main():
     }
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
-        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        D.df_stream_copy(src, dst, nbytes)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        reps = 10
+        for _ in range(reps):
+            D.df_stream_copy(src, dst, nbytes, stream=torch.cuda.current_stream())
+        ev1.record()
         torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        out["calibration_copy_bytes"] = nbytes
+        copy_s = ev0.elapsed_time(ev1) * 1e-3 / reps
+        COPY["Bps"] = 2.0 * nbytes / copy_s
+        out["hbm_copy"] = {"kernel": "k_stream_copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                           "GBps": round(COPY["Bps"] / 1e9, 1), "frac_of_peak": round(COPY["Bps"] / HBM_PEAK, 4)}
+        out["roofline"]["hbm_frac_of_copy"] = round(m["bytes"] / body_s / COPY["Bps"], 4)
+        del src, dst
     only = set(filter(None, args.only.split(",")))
     extras = [("chain", lambda: bench_chain(D, Graph, torch)),
               ("motion", lambda: bench_motion(D, Graph, torch)),

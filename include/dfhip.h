@@ -287,6 +287,16 @@ df_status df_mp_input_adjoint(void *stream, const void *u, const void *a,
                               const void *g, void *Gu, int64_t n_streams,
                               int64_t len, int32_t K, int32_t Q);
 
+/* Measurement helper (no operation of the method): copies `bytes` bytes from
+ * device buffer src to device buffer dst on `stream` (NULL: the null stream)
+ * with a plain 16-byte-vector stream-copy kernel.  It is the reference
+ * against which the actor kernels' bandwidth and HBM traffic counters are
+ * scaled.  bytes must be a multiple of 16 and both pointers 16-byte
+ * aligned (else DF_EINVAL); the buffers must not overlap and stay owned by
+ * the caller, who keeps them alive until the stream has passed the copy. */
+df_status df_stream_copy(void *stream, const void *src, void *dst,
+                         int64_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -141,6 +141,7 @@ hipError_t launch_motion_emit_scan(const int32_t *count, int64_t n, int64_t emit
                                    int64_t *emit_off, hipStream_t s);
 hipError_t launch_motion_emit(const MotionArgs &a, hipStream_t s);
 hipError_t launch_adj(const AdjArgs &a, hipStream_t s);
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
 hipError_t launch_mp_adj(const float2 *u, const float2 *a, const float2 *g, float2 *Gu, int64_t n_streams,
                          int64_t len, int K, int Q, hipStream_t s);
 hipError_t launch_motion_commit(const int64_t *emit_off, int64_t n, int64_t *cur_idx, int64_t *prev_idx,

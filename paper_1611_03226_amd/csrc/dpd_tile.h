@@ -13,6 +13,23 @@
 
 namespace dfh {
 
+// Read-only device data seen through the constant address space: loads from
+// it at wavefront-uniform addresses become scalar loads into SGPRs, which the
+// FMAs read directly (no VGPRs, no LDS traffic for the coefficients).  Only
+// memory that no kernel of the launch writes may be read this way.
+typedef const __attribute__((address_space(4))) float2 *cfloat2p;
+
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(const T *p) {
+  return (const __attribute__((address_space(4))) T *)p;
+}
+
+// Element i of a constant-space complex array.
+__device__ __forceinline__ float2 ldc(cfloat2p p, int i) {
+  const __attribute__((address_space(4))) float *f = (const __attribute__((address_space(4))) float *)p;
+  return make_float2(f[2 * i], f[2 * i + 1]);
+}
+
 // LDS slot of window sample i: one pad slot per 8 samples, so the K-strided
 // register-window reads of a wavefront fall on distinct banks.
 __host__ __device__ constexpr int lds_slot(int i) { return i + (i >> 3); }
@@ -24,14 +41,13 @@ __host__ __device__ constexpr int lds_window(int n) { return lds_slot(n) + 1; }
 // K samples (one new LDS read per tap; the shift is a register rename).
 // Reads stay inside the window buffer (index < tile+M-1); in a partial tile,
 // slots past the staged samples only feed outputs that are not stored.
-// sh: the firing's coefficients staged in LDS ([B][M]); each tap reads its B
-// coefficients with broadcast LDS loads (all lanes read the same address).
+// hg: the firing's coefficients [B][M] (uniform address: scalar loads).
 // Software pipeline of depth one: tap m+1's coefficients and sample are
 // loaded before tap m's arithmetic; a compiler fence after each tap keeps
 // later loads from being hoisted (which would keep every tap's
 // coefficients live at once and spill).
 template <int M, int K, int B>
-__device__ __forceinline__ void horner_taps(const float2 *sh, const float2 *sx, int q0, float (&ar)[K],
+__device__ __forceinline__ void horner_taps(cfloat2p hg, const float2 *sx, int q0, float (&ar)[K],
                                             float (&ai)[K]) {
   float2 wv[K];
   float pv[K];
@@ -42,14 +58,14 @@ __device__ __forceinline__ void horner_taps(const float2 *sh, const float2 *sx, 
   }
   float2 hc[B];
 #pragma unroll
-  for (int b = 0; b < B; ++b) hc[b] = sh[b * M];
+  for (int b = 0; b < B; ++b) hc[b] = ldc(hg, b * M);
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     float2 hn[B];
     float2 wn = make_float2(0.f, 0.f);
     if (m + 1 < M) {
 #pragma unroll
-      for (int b = 0; b < B; ++b) hn[b] = sh[b * M + m + 1];
+      for (int b = 0; b < B; ++b) hn[b] = ldc(hg, b * M + m + 1);
       wn = sx[lds_slot(q0 + M - 2 - m)];
     }
 #pragma unroll
@@ -149,7 +165,7 @@ __device__ __forceinline__ void tile_commit(float2 *sx, float2 *sq, const TileRe
 // History part of output q < M-1 for branch b (after the commit barrier):
 //   hp[b][q] = sum_{m=q+1}^{M-1} h_b[m] psi_b(history sample q - m).
 template <int M>
-__device__ __forceinline__ void tile_head_sums(float2 *sq, const float2 *sh, int B) {
+__device__ __forceinline__ void tile_head_sums(float2 *sq, cfloat2p hg, int B) {
   constexpr int L = M - 1;
   float2 *hp = sq + B * L;
   for (int idx = threadIdx.x; idx < B * L; idx += blockDim.x) {
@@ -161,7 +177,7 @@ __device__ __forceinline__ void tile_head_sums(float2 *sq, const float2 *sh, int
       float pb = 1.f;
       for (int e = 0; e < b; ++e) pb *= pp;
       const float xr = pb * xv.x, xi = pb * xv.y;
-      const float2 c = sh[b * M + m];
+      const float2 c = ldc(hg, b * M + m);
       sr = fmaf(c.x, xr, sr);
       sr = fmaf(-c.y, xi, sr);
       si = fmaf(c.x, xi, si);
@@ -171,10 +187,10 @@ __device__ __forceinline__ void tile_head_sums(float2 *sq, const float2 *sh, int
   }
 }
 
-// The tile's outputs from LDS (window sx, coefficients sh [B][M], history
-// sums in sq) to the output ring.
+// The tile's outputs (window sx and history sums sq in LDS, coefficients hg
+// [B][M]) to the output ring.
 template <int M, int K>
-__device__ __forceinline__ void tile_outputs(const float2 *sx, const float2 *sh, const float2 *sq, const TileJob &j,
+__device__ __forceinline__ void tile_outputs(const float2 *sx, cfloat2p hg, const float2 *sq, const TileJob &j,
                                              float2 *__restrict__ y, int64_t y_mask) {
   constexpr int L = M - 1;
   const int q0 = threadIdx.x * K;
@@ -184,7 +200,7 @@ __device__ __forceinline__ void tile_outputs(const float2 *sx, const float2 *sh,
   for (int k = 0; k < K; ++k) ar[k] = ai[k] = 0.f;
   switch (j.B) {
 #define DF_CASE(n) \
-  case n: horner_taps<M, K, n>(sh, sx, q0, ar, ai); break;
+  case n: horner_taps<M, K, n>(hg, sx, q0, ar, ai); break;
     DF_CASE(1) DF_CASE(2) DF_CASE(3) DF_CASE(4) DF_CASE(5) DF_CASE(6) DF_CASE(7) DF_CASE(8)
     DF_CASE(9) DF_CASE(10) DF_CASE(11) DF_CASE(12) DF_CASE(13) DF_CASE(14) DF_CASE(15) DF_CASE(16)
 #undef DF_CASE

@@ -63,14 +63,14 @@ __global__ __launch_bounds__(256) void k_dpd_generic(DpdArgs a) {
 // each workgroup prefetches its next tile while computing the current one.
 template <int M, int K>
 __global__ __launch_bounds__(256) void k_dpd_tiled(DpdArgs a) {
-  extern __shared__ float2 lds[];   // [B_max*M] coefficients, [2*B_max*(M-1)] histories, window
-  float2 *sh = lds, *sq = lds + a.B_max * M, *sx = sq + lds_history(a.B_max, M);
+  extern __shared__ float2 lds[];   // [2*B_max*(M-1)] histories, window
+  float2 *sq = lds, *sx = sq + lds_history(a.B_max, M);
+  const cfloat2p hg = as_const(a.h);
   const int64_t n_items = a.n_firings * a.tiles_per_firing;
   int64_t item = blockIdx.x;
   if (item >= n_items) return;                       // uniform
   const int64_t Rx = a.x_idx ? a.x_idx[0] : 0;
   const int64_t Wy = a.y_idx ? a.y_idx[1] : 0;
-  for (int idx = threadIdx.x; idx < a.B_max * M; idx += blockDim.x) sh[idx] = a.h[idx];
   auto job_of = [&](int64_t it, int64_t &g) {
     const int64_t k = it / a.tiles_per_firing;
     const int64_t tk = it - k * a.tiles_per_firing;
@@ -101,10 +101,10 @@ __global__ __launch_bounds__(256) void k_dpd_tiled(DpdArgs a) {
                           [&](int b, int64_t ii) { return hist_sample(a, Rx, b, ng, prev_of(a, b, ng), ii); });
     }
     if (job.head) {
-      tile_head_sums<M>(sq, sh, job.B);
+      tile_head_sums<M>(sq, hg, job.B);
       __syncthreads();
     }
-    tile_outputs<M, K>(sx, sh, sq, job, a.y, a.y_mask);
+    tile_outputs<M, K>(sx, hg, sq, job, a.y, a.y_mask);
     if (next >= n_items) break;
     __syncthreads();
     item = next;
@@ -119,7 +119,7 @@ static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile) {
   a.tile = tile;
   a.tiles_per_firing = (int32_t)((a.r + tile - 1) / tile);
   const int threads = tile / K;
-  const size_t lds = (size_t)(lds_window(tile + M - 1) + a.B_max * M + lds_history(a.B_max, M)) * sizeof(float2);
+  const size_t lds = (size_t)(lds_window(tile + M - 1) + lds_history(a.B_max, M)) * sizeof(float2);
   const int64_t items = a.n_firings * a.tiles_per_firing;
   if (items <= 0) return hipSuccess;
   const int64_t resident = resident_blocks((const void *)k_dpd_tiled<M, K>, threads, lds);

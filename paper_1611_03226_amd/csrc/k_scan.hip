@@ -9,49 +9,115 @@
 //   last_b    = max{i < n : firing i feeds branch b}
 // where "feeds" is B_i > b (branch history) or always (shared history).
 //
-// One workgroup per segment of firings, one wavefront per branch.  A
-// 0/1 feed flag per lane makes both scans a ballot: the exclusive count is
-// the popcount of the ballot bits below the lane, the exclusive max is the
-// highest such bit, carried across 64-firing chunks.
+// One workgroup per segment of firings, which it walks in chunks of four
+// firings per thread.  Per chunk and branch, a thread counts its fed
+// firings and finds the last one; wavefront shuffles scan these (sum and
+// max), LDS holds the per-wavefront totals, and the segment carries
+// (count and last feeder so far) advance once per chunk.
 #include "common.h"
 
 namespace dfh {
 
-__global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
+constexpr int kScanThreads = 1024;
+constexpr int kScanWaves = kScanThreads / 64;
+
+__device__ __forceinline__ int wave_incl_sum(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_incl_max(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v = max(v, t);
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
+  __shared__ int wsum[kScanWaves][kMaxBranches], wlast[kScanWaves][kMaxBranches];
+  __shared__ int64_t carry_cnt[kMaxBranches], carry_last[kMaxBranches];
   const int seg = blockIdx.x;
-  const int b = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int64_t R = a.ctrl_idx ? a.ctrl_idx[0] : 0;
   const int64_t g0 = (int64_t)seg * a.seg_firings;
-  const uint64_t below_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-  int64_t count = 0;
-  int64_t lastw = -1;
-  for (int64_t c = 0; c < a.seg_firings; c += 64) {
-    const int64_t j = c + lane;
-    const bool in = j < a.seg_firings;
-    int32_t B = 0;
-    if (in) {
-      int32_t v = a.ctrl[(R + g0 + j) & a.ctrl_mask];
-      if (v < 0 || v > a.B_max) {
-        if (b == 0 && a.err) atomicOr(a.err, (int32_t)kErrControl);
-        v = 0;
+  if (tid < a.B_max) carry_cnt[tid] = 0, carry_last[tid] = -1;
+  const int64_t per_chunk = 4 * (int64_t)blockDim.x;
+  for (int64_t c0 = 0; c0 < a.seg_firings; c0 += per_chunk) {
+    const int64_t j0 = c0 + 4 * (int64_t)tid;          // first firing of this thread (segment-local)
+    int Bv[4];
+    bool in[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      in[k] = j0 + k < a.seg_firings;
+      int v = 0;
+      if (in[k]) {
+        v = a.ctrl[(R + g0 + j0 + k) & a.ctrl_mask];
+        if (v < 0 || v > a.B_max) {
+          if (a.err) atomicOr(a.err, (int32_t)kErrControl);
+          v = 0;
+        }
+        a.B_out[g0 + j0 + k] = v;
       }
-      B = v;
-      if (b == 0) a.B_out[g0 + j] = B;
+      Bv[k] = v;
     }
-    const bool fed = in && (a.hist_mode == 1 || B > b);
-    const uint64_t bal = __ballot(fed);
-    const uint64_t below = bal & below_mask;
-    if (in) {
-      const int64_t pv = below ? (c + 63 - __clzll((long long)below)) : lastw;
-      a.prev_out[(int64_t)b * a.stride + g0 + j] = pv >= 0 ? g0 + pv : -1;
-      if (a.off_out)
-        a.off_out[(int64_t)b * a.stride + g0 + j] = a.r * (count + __popcll(below));
+    // pass 1: per-wavefront totals for every branch
+    for (int b = 0; b < a.B_max; ++b) {
+      int c = 0, l = -1;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool f = in[k] && (a.hist_mode == 1 || Bv[k] > b);
+        c += f;
+        if (f) l = (int)(j0 - c0) + k;                  // chunk-local index
+      }
+      const int cs = wave_incl_sum(c, lane), ls = wave_incl_max(l, lane);
+      if (lane == 63) wsum[wave][b] = cs, wlast[wave][b] = ls;
     }
-    count += __popcll(bal);
-    if (bal) lastw = c + 63 - __clzll((long long)bal);
+    __syncthreads();
+    // pass 2: exclusive count and exclusive max per firing
+    for (int b = 0; b < a.B_max; ++b) {
+      bool f[4];
+      int c = 0, l = -1;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        f[k] = in[k] && (a.hist_mode == 1 || Bv[k] > b);
+        c += f[k];
+        if (f[k]) l = (int)(j0 - c0) + k;
+      }
+      const int cs = wave_incl_sum(c, lane), ls = wave_incl_max(l, lane);
+      int lprev = __shfl_up(ls, 1);
+      if (lane == 0) lprev = -1;
+      int64_t cnt = carry_cnt[b] + (cs - c);
+      int wl = -1;
+      for (int w = 0; w < wave; ++w) cnt += wsum[w][b], wl = max(wl, wlast[w][b]);
+      wl = max(wl, lprev);
+      int64_t last = wl >= 0 ? c0 + wl : carry_last[b];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (!in[k]) break;
+        const int64_t o = (int64_t)b * a.stride + g0 + j0 + k;
+        a.prev_out[o] = last >= 0 ? g0 + last : -1;
+        if (a.off_out) a.off_out[o] = a.r * cnt;
+        if (f[k]) cnt += 1, last = j0 + k;
+      }
+    }
+    __syncthreads();
+    if (tid < a.B_max) {
+      int64_t cnt = 0;
+      int wl = -1;
+      for (int w = 0; w < nw; ++w) cnt += wsum[w][tid], wl = max(wl, wlast[w][tid]);
+      carry_cnt[tid] += cnt;
+      if (wl >= 0) carry_last[tid] = c0 + wl;
+    }
+    __syncthreads();
   }
-  if (lane == 0 && a.last_out) a.last_out[(int64_t)seg * a.B_max + b] = lastw >= 0 ? g0 + lastw : -1;
+  if (tid < a.B_max && a.last_out)
+    a.last_out[(int64_t)seg * a.B_max + tid] = carry_last[tid] >= 0 ? g0 + carry_last[tid] : -1;
 }
 
 // Processing order of a batch's firings, grouped by branch count B (largest
@@ -107,7 +173,11 @@ int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes) {
 
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s) {
   if (a.n_segs <= 0 || a.seg_firings <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scan, dim3(a.n_segs), dim3(64 * a.B_max), 0, s, a);
+  if (a.B_max < 1 || a.B_max > kMaxBranches) return hipErrorInvalidValue;
+  // four firings per thread; small segments take fewer wavefronts
+  int64_t waves = (a.seg_firings + 255) / 256;
+  if (waves > kScanWaves) waves = kScanWaves;
+  hipLaunchKernelGGL(k_scan, dim3(a.n_segs), dim3(64 * (unsigned)waves), 0, s, a);
   return hipGetLastError();
 }
 

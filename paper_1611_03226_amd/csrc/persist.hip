@@ -167,20 +167,22 @@ __global__ __launch_bounds__(1024) void k_pers_scan(PersArgs a) {
   if (lane == 0) a.last_all[(int64_t)i * a.Bg + b] = lastw;
 }
 
-constexpr int kCoefRegs = 4;   // coefficients per thread (B_max*M <= 4*threads)
-
 // Persistent body: workgroups pull (instance, firing, tile) work items from
-// the queue; the next item's window, histories and coefficients are loaded
-// into registers while the current item is computed from LDS.
+// the queue; the next item's window and histories are loaded into registers
+// while the current item is computed from LDS.  The item number is made
+// wavefront-uniform, so the instance table and the instance's coefficients
+// are read with scalar loads.
 template <int M, int K>
 __global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
-  extern __shared__ float2 lds[];   // [Bg*M] coefficients, [2*Bg*(M-1)] histories, window
-  float2 *sh = lds, *sq = lds + a.Bg * M, *sx = sq + lds_history(a.Bg, M);
+  extern __shared__ float2 lds[];   // [2*Bg*(M-1)] histories, window
+  float2 *sq = lds, *sx = sq + lds_history(a.Bg, M);
   __shared__ int item_s;
-  const int64_t total = a.tile_base[a.n_inst];
+  const auto *inst = as_const(a.inst);
+  const auto *tile_base = as_const(a.tile_base);
+  const int64_t total = tile_base[a.n_inst];
   if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1);
   __syncthreads();
-  int64_t item = item_s;
+  int64_t item = __builtin_amdgcn_readfirstlane(item_s);
   if (item >= total) return;                          // uniform: every wave leaves
   struct Item {
     int inst;
@@ -190,61 +192,51 @@ __global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
     int lo = 0, hi = a.n_inst - 1;                    // last ordered instance with base <= it
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (a.tile_base[mid] <= it) lo = mid; else hi = mid - 1;
+      if (tile_base[mid] <= it) lo = mid; else hi = mid - 1;
     }
-    d.inst = a.inst_order[lo];
-    const InstDesc &ds = a.inst[d.inst];
-    const int64_t local = it - a.tile_base[lo];
+    d.inst = as_const(a.inst_order)[lo];
+    const auto &ds = inst[d.inst];
+    const int64_t local = it - tile_base[lo];
     d.j = local / ds.tpf;
-    d.gfire = a.fire_base[d.inst] + d.j;
-    d.Rx = ds.x_idx[0];
+    d.gfire = as_const(a.fire_base)[d.inst] + d.j;
+    d.Rx = as_const(ds.x_idx)[0];
     job.t0 = (local - d.j * ds.tpf) * a.tile;
     job.nout = (int)min((int64_t)a.tile, ds.r - job.t0);
-    job.B = a.B_all[d.gfire];
+    job.B = as_const(a.B_all)[d.gfire];
     job.head = (job.t0 == 0 && job.B > 0 && M > 1) ? 1 : 0;
     job.xb = d.Rx + d.j * ds.r;
-    job.yb = ds.y_idx[1] + d.j * ds.r;
+    job.yb = as_const(ds.y_idx)[1] + d.j * ds.r;
   };
-  auto prefetch = [&](const Item &d, const TileJob &job, TileRegs<M, K> &r, float2 (&cr)[kCoefRegs]) {
-    const InstDesc &ds = a.inst[d.inst];
+  auto prefetch = [&](const Item &d, const TileJob &job, TileRegs<M, K> &r) {
+    const auto &ds = inst[d.inst];
     tile_prefetch<M, K>(r, job, ds.x, ds.x_mask, [&](int b, int64_t ii) {
       const int64_t pf = a.prev_all[(int64_t)b * a.cap + d.gfire];
       if (pf >= 0) return ds.x[(d.Rx + pf * ds.r + ds.r + ii) & ds.x_mask];
       return ds.hist[b * (M - 1) + (M - 1) + ii];
     });
-#pragma unroll
-    for (int u = 0; u < kCoefRegs; ++u) {
-      const int idx = threadIdx.x + u * blockDim.x;
-      cr[u] = idx < job.B * M ? ds.h[idx] : make_float2(0.f, 0.f);
-    }
   };
   Item cur;
   TileJob job;
   decode(item, cur, job);
   TileRegs<M, K> regs;
-  float2 creg[kCoefRegs];
-  prefetch(cur, job, regs, creg);
+  prefetch(cur, job, regs);
   for (;;) {
     tile_commit<M, K>(sx, sq, regs, job);
-#pragma unroll
-    for (int u = 0; u < kCoefRegs; ++u) {
-      const int idx = threadIdx.x + u * blockDim.x;
-      if (idx < job.B * M) sh[idx] = creg[u];
-    }
     if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1);
     __syncthreads();
-    const int64_t next = item_s;
+    const int64_t next = __builtin_amdgcn_readfirstlane(item_s);
     Item nd = cur;
     TileJob nj = job;
     if (next < total) {
       decode(next, nd, nj);
-      prefetch(nd, nj, regs, creg);
+      prefetch(nd, nj, regs);
     }
+    const cfloat2p hg = as_const(inst[cur.inst].h);
     if (job.head) {
-      tile_head_sums<M>(sq, sh, job.B);
+      tile_head_sums<M>(sq, hg, job.B);
       __syncthreads();
     }
-    tile_outputs<M, K>(sx, sh, sq, job, a.inst[cur.inst].y, a.inst[cur.inst].y_mask);
+    tile_outputs<M, K>(sx, hg, sq, job, inst[cur.inst].y, inst[cur.inst].y_mask);
     if (next >= total) break;
     __syncthreads();
     cur = nd;
@@ -317,14 +309,13 @@ void destroy_persistent(df_graph *g) {
 
 template <int M, int K>
 static hipError_t launch_pers_body(const PersArgs &a, int threads, int blocks, hipStream_t s) {
-  const size_t lds = (size_t)(lds_window(a.tile + M - 1) + a.Bg * M + lds_history(a.Bg, M)) * sizeof(float2);
+  const size_t lds = (size_t)(lds_window(a.tile + M - 1) + lds_history(a.Bg, M)) * sizeof(float2);
   hipLaunchKernelGGL((k_pers_body<M, K>), dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
 static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s, df_graph *prof_g) {
-  if (a.Bg * p->M > kCoefRegs * (p->tile / p->K) || a.Bg * (p->M - 1) > kHistRegs * (p->tile / p->K))
-    return hipErrorInvalidValue;
+  if (a.Bg * (p->M - 1) > kHistRegs * (p->tile / p->K)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pers_prep, dim3(1), dim3(64), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -428,8 +419,8 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
   const int64_t rr = ((max_r + 64 * K - 1) / (64 * K)) * (64 * K);
   if (tile > rr) tile = (int)rr;
   tile = std::max(64 * K, std::min(512 * K, (tile / (64 * K)) * (64 * K)));
-  // one history sample and up to kCoefRegs coefficients per thread
-  while (tile / K < 512 && (tile / K < Bg * (M - 1) || Bg * M > kCoefRegs * (tile / K))) tile += 64 * K;
+  // one history sample per thread
+  while (tile / K < 512 && tile / K < Bg * (M - 1)) tile += 64 * K;
   const int bpc = g->blocks_per_cu > 0 ? g->blocks_per_cu : 4;
   bool rebuild = !same_list || tile != p->tile || K != p->K || bpc != p->bpc;
   if (total > p->cap) {

@@ -178,3 +178,13 @@ extern "C" df_status df_mp_input_adjoint(void *stream, const void *u, const void
   if (e != hipSuccess) return fail_hip(nullptr, e, "df_mp_input_adjoint");
   return DF_OK;
 }
+
+extern "C" df_status df_stream_copy(void *stream, const void *src, void *dst, int64_t bytes) {
+  if (bytes < 0 || bytes % 16) return fail(nullptr, DF_EINVAL, "bytes must be a non-negative multiple of 16");
+  if (bytes == 0) return DF_OK;
+  if (!src || !dst) return fail(nullptr, DF_EINVAL, "null pointer");
+  if (((uintptr_t)src | (uintptr_t)dst) % 16) return fail(nullptr, DF_EINVAL, "pointers must be 16-byte aligned");
+  hipError_t e = launch_stream_copy(src, dst, bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "df_stream_copy");
+  return DF_OK;
+}

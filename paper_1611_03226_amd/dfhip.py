@@ -68,6 +68,7 @@ _SIGS = {
     "df_dpd_coeff_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32, _P, _I64], _I32),
     "df_dpd_coeff_adjoint_work_bytes": ([_I64, _I64, _I64, _I32, _I32], _I64),
     "df_mp_input_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I32, _I32], _I32),
+    "df_stream_copy": ([_P, _P, _P, _I64], _I32),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -261,3 +262,8 @@ def df_mp_input_adjoint(u, a, g, Gu, stream=None) -> None:
     K, Q = a.shape
     _check(_lib.df_mp_input_adjoint(_stream_ptr(stream), _dev_ptr(u), _dev_ptr(a), _dev_ptr(g), _dev_ptr(Gu),
                                     S, L, K, Q))
+
+
+def df_stream_copy(src, dst, nbytes: int, stream=None) -> None:
+    """Plain device copy of nbytes (bandwidth / traffic-counter reference)."""
+    _check(_lib.df_stream_copy(_stream_ptr(stream), _dev_ptr(src), _dev_ptr(dst), nbytes))

@@ -81,3 +81,12 @@ def test_stateless_null_pointers_and_work_size():
     wb2 = D.df_dpd_coeff_adjoint_work_bytes(2, 4096, 256, 4, 8)
     assert wb2 == 2 * 16 * 1 * 4 * 8 * 8
     assert lib.df_dpd_coeff_adjoint(None, None, None, None, None, 2, 4096, 256, 4, 8, 0, None, 0) == D.DF_EINVAL
+
+
+def test_stream_copy_validation():
+    from paper_1611_03226_amd import dfhip as D
+    lib = D._lib
+    assert lib.df_stream_copy(None, None, None, 0) == D.DF_OK          # nothing to copy
+    assert lib.df_stream_copy(None, None, None, 24) == D.DF_EINVAL     # not a multiple of 16
+    assert lib.df_stream_copy(None, None, None, -16) == D.DF_EINVAL
+    assert lib.df_stream_copy(None, None, None, 32) == D.DF_EINVAL     # null pointers
