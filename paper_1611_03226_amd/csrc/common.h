@@ -45,7 +45,8 @@ struct DpdArgs {
   int32_t M;
   int32_t tile;           // outputs per workgroup (tiled kernel)
   int32_t tiles_per_firing;
-  const int32_t *order;   // processing order of the firings (grouped by B) or nullptr
+  const int32_t *order;   // processing order, pairs (firing, B) grouped by B, or nullptr
+  float2 *corr;           // [n_firings][M-1] head corrections (tiled kernels)
 };
 
 // Control intake + offset scan over segments of firings (one workgroup per
@@ -131,6 +132,8 @@ int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes);
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
+bool dpd_tiled_shape(int M);
+hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s);
 hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread);
 hipError_t launch_order_by_b(const int32_t *B, int64_t n, int32_t B_max, int32_t *order, hipStream_t s);
 hipError_t launch_dpd_commit(const DpdCommitArgs &a, hipStream_t s);

@@ -96,132 +96,192 @@ __device__ __forceinline__ void horner_taps(cfloat2p hg, const float2 *sx, int q
   }
 }
 
-// LDS float2 slots for the branch histories and their per-(branch, output)
-// sums, [B_max][M-1] each.
-__host__ __device__ constexpr int lds_history(int B_max, int M) { return 2 * B_max * (M > 1 ? M - 1 : 1); }
+// LDS float2 slots for a firing's head corrections (M-1 outputs).
+__host__ __device__ constexpr int lds_corr(int M) { return M > 1 ? M - 1 : 1; }
+
+// Head correction of one firing (one wavefront).  Outputs q < M-1 of a
+// firing reach back before its first sample, where branch b reads its own
+// history source (the tail of its last feeding firing, or the carried
+// state).  The tile body stages zeros there; this adds the difference:
+//   corr[q] = sum_{b<B} sum_{m=q+1}^{M-1} h_b[m] psi_b(src_b[q-m]),
+// accumulated branch by branch.  Lane i holds history sample i (i < M-1)
+// of every branch, loaded all at once; psi values move between lanes by
+// shuffles and the coefficients are scalar loads (B is uniform).
+//   src_of(b)          -> history source firing of branch b (-1: state)
+//   sample(b, pf, i)   -> sample i of branch b's history
+template <int M, class SrcOf, class Sample>
+__device__ __forceinline__ void head_correction(int B, cfloat2p hg, SrcOf src_of, Sample sample, float2 *out) {
+  constexpr int L = M - 1;
+  const int lane = threadIdx.x & 63;
+  const bool in = lane < L;
+  int64_t pf[kMaxBranches];
+#pragma unroll
+  for (int b = 0; b < kMaxBranches; ++b) pf[b] = (b < B && in) ? src_of(b) : -1;
+  float2 xs[kMaxBranches];
+#pragma unroll
+  for (int b = 0; b < kMaxBranches; ++b) xs[b] = (b < B && in) ? sample(b, pf[b], lane) : make_float2(0.f, 0.f);
+  float cr = 0.f, ci = 0.f;
+#pragma unroll
+  for (int b = 0; b < kMaxBranches; ++b) {
+    if (b >= B) continue;                              // uniform
+    const float pp = fmaf(xs[b].x, xs[b].x, xs[b].y * xs[b].y);
+    float pb = 1.f;
+    for (int e = 0; e < b; ++e) pb *= pp;
+    const float psr = pb * xs[b].x, psi = pb * xs[b].y;
+    float sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int m = 1; m < M; ++m) {
+      const float2 c = ldc(hg, b * M + m);
+      const int src = lane - m + L;                    // history sample q - m
+      const float vr = __shfl(psr, src), vi = __shfl(psi, src);
+      if (m > lane) {
+        sr = fmaf(c.x, vr, sr);
+        sr = fmaf(-c.y, vi, sr);
+        si = fmaf(c.x, vi, si);
+        si = fmaf(c.y, vr, si);
+      }
+    }
+    cr += sr;
+    ci += si;
+  }
+  if (in) out[lane] = make_float2(cr, ci);
+}
 
 // The tile pipeline.  A workgroup of NT threads computes tiles of K*NT
-// consecutive outputs of one firing (B uniform over the tile).  For the next
-// tile it first loads, into registers, its share of the input window
-// (K*NT + M-1 samples) and, for the first tile of a firing, of the branch
-// histories; while those loads are in flight it computes the current tile
-// from LDS.  Every rounding step is an explicit fmaf or a single operation,
-// so all kernels built from these pieces produce bit-identical outputs.
+// consecutive outputs of one firing (B uniform over the tile), walking the
+// batch's tiles with a grid stride.  Loads are issued well before their use:
+// the descriptor of tile i+2 (one register, lane-distributed) and the window
+// and head corrections of tile i+1 are loaded while tile i is computed.
+// Samples before the firing start are staged as zeros; a firing's first
+// M-1 outputs then add their head correction.  Every rounding step is an
+// explicit fmaf or a single operation, so all kernels built from these
+// pieces produce bit-identical outputs.
 
-constexpr int kHistRegs = 1;   // history samples per thread: launchers keep B_max*(M-1) <= threads
-
-struct TileJob {
-  int64_t xb;      // ring position of the firing's first input sample
-  int64_t yb;      // ring position of the firing's first output sample
-  int64_t t0;      // first output of the tile within the firing
-  int nout;        // outputs in the tile
-  int B;           // active branches of the firing
-  int head;        // first tile of a firing with active branches (0/1)
+// Everything about one tile, uniform across the workgroup.
+struct Job {
+  const float2 *x;        // input ring
+  float2 *y;              // output ring
+  const float2 *h;        // coefficients [B][M] of the firing's actor
+  const float2 *corr;     // the firing's head corrections [M-1] (used when head)
+  int64_t x_mask, y_mask;
+  int64_t xb, yb;         // ring positions of the firing's first input / output sample
+  int t0;                 // first output of the tile within the firing
+  int nout;               // outputs in the tile
+  int B;                  // active branches of the firing
+  int head;               // first tile of a firing with active branches (0/1)
 };
 
 template <int M, int K>
 struct TileRegs {
   float2 win[K + 1];
-  float2 hst[kHistRegs];
+  float2 cv;              // head correction of output threadIdx.x (< M-1)
 };
 
-// Loads of the next tile (issued early; consumed by tile_commit).
-// hist(b, ii) returns branch b's input sample ii < 0 before the firing start.
-template <int M, int K, class Hist>
-__device__ __forceinline__ void tile_prefetch(TileRegs<M, K> &r, const TileJob &j, const float2 *__restrict__ x,
-                                              int64_t x_mask, Hist hist) {
+// Loads of tile j into registers (issued early, consumed by commit).
+template <int M, int K>
+__device__ __forceinline__ void load_tile(TileRegs<M, K> &r, const Job &j) {
 #pragma unroll
   for (int u = 0; u < K + 1; ++u) {
     const int idx = threadIdx.x + u * blockDim.x;
-    const int64_t pos = j.t0 - (M - 1) + idx;
-    r.win[u] = (idx < j.nout + M - 1 && pos >= 0) ? x[(j.xb + pos) & x_mask] : make_float2(0.f, 0.f);
+    const int64_t pos = (int64_t)j.t0 - (M - 1) + idx;
+    r.win[u] = (idx < j.nout + M - 1 && pos >= 0) ? j.x[(j.xb + pos) & j.x_mask] : make_float2(0.f, 0.f);
   }
-  constexpr int L = M - 1;
-#pragma unroll
-  for (int u = 0; u < kHistRegs; ++u) {
-    const int idx = threadIdx.x + u * blockDim.x;
-    r.hst[u] = (j.head && idx < j.B * L) ? hist(idx / L, (int64_t)(idx % L - L)) : make_float2(0.f, 0.f);
-  }
+  r.cv = (j.head && (int)threadIdx.x < M - 1) ? j.corr[threadIdx.x] : make_float2(0.f, 0.f);
 }
 
-// Registers -> LDS: the window into sx, the histories into sq.
 template <int M, int K>
-__device__ __forceinline__ void tile_commit(float2 *sx, float2 *sq, const TileRegs<M, K> &r, const TileJob &j) {
+__device__ __forceinline__ void commit_tile(float2 *sx, float2 *sc, const TileRegs<M, K> &r, const Job &j) {
 #pragma unroll
   for (int u = 0; u < K + 1; ++u) {
     const int idx = threadIdx.x + u * blockDim.x;
     if (idx < j.nout + M - 1) sx[lds_slot(idx)] = r.win[u];
   }
-  constexpr int L = M - 1;
-  if (j.head) {
-#pragma unroll
-    for (int u = 0; u < kHistRegs; ++u) {
-      const int idx = threadIdx.x + u * blockDim.x;
-      if (idx < j.B * L) sq[idx] = r.hst[u];
-    }
-  }
+  if (j.head && (int)threadIdx.x < M - 1) sc[threadIdx.x] = r.cv;
 }
 
-// History part of output q < M-1 for branch b (after the commit barrier):
-//   hp[b][q] = sum_{m=q+1}^{M-1} h_b[m] psi_b(history sample q - m).
-template <int M>
-__device__ __forceinline__ void tile_head_sums(float2 *sq, cfloat2p hg, int B) {
-  constexpr int L = M - 1;
-  float2 *hp = sq + B * L;
-  for (int idx = threadIdx.x; idx < B * L; idx += blockDim.x) {
-    const int b = idx / L, q = idx - b * L;
-    float sr = 0.f, si = 0.f;
-    for (int m = q + 1; m < M; ++m) {
-      const float2 xv = sq[b * L + q - m + L];
-      const float pp = fmaf(xv.x, xv.x, xv.y * xv.y);
-      float pb = 1.f;
-      for (int e = 0; e < b; ++e) pb *= pp;
-      const float xr = pb * xv.x, xi = pb * xv.y;
-      const float2 c = ldc(hg, b * M + m);
-      sr = fmaf(c.x, xr, sr);
-      sr = fmaf(-c.y, xi, sr);
-      si = fmaf(c.x, xi, si);
-      si = fmaf(c.y, xr, si);
-    }
-    hp[idx] = make_float2(sr, si);
-  }
-}
-
-// The tile's outputs (window sx and history sums sq in LDS, coefficients hg
-// [B][M]) to the output ring.
-template <int M, int K>
-__device__ __forceinline__ void tile_outputs(const float2 *sx, cfloat2p hg, const float2 *sq, const TileJob &j,
-                                             float2 *__restrict__ y, int64_t y_mask) {
-  constexpr int L = M - 1;
+// The tile's main arithmetic (window in sx) for this thread's K outputs.
+// BC: largest branch count compiled (10 or 16; fewer unrolled paths keep
+// the register budget of the common configurations small).
+template <int M, int K, int BC>
+__device__ __forceinline__ void tile_compute(const float2 *sx, cfloat2p hg, const Job &j, float (&ar)[K],
+                                             float (&ai)[K]) {
   const int q0 = threadIdx.x * K;
-  if (q0 >= j.nout) return;
-  float ar[K], ai[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) ar[k] = ai[k] = 0.f;
+  if (q0 >= j.nout) return;
   switch (j.B) {
 #define DF_CASE(n) \
-  case n: horner_taps<M, K, n>(hg, sx, q0, ar, ai); break;
+  case n:                                                  \
+    if constexpr (n <= BC) horner_taps<M, K, n>(hg, sx, q0, ar, ai); \
+    break;
     DF_CASE(1) DF_CASE(2) DF_CASE(3) DF_CASE(4) DF_CASE(5) DF_CASE(6) DF_CASE(7) DF_CASE(8)
     DF_CASE(9) DF_CASE(10) DF_CASE(11) DF_CASE(12) DF_CASE(13) DF_CASE(14) DF_CASE(15) DF_CASE(16)
 #undef DF_CASE
     default: break;
   }
-  if (j.head && q0 < L) {
-    const float2 *hp = sq + j.B * L;
+}
+
+// Store this thread's outputs; in a firing's first tile, outputs q < M-1
+// first add their head correction (staged in sc).
+template <int M, int K>
+__device__ __forceinline__ void tile_store(const float2 *sc, const Job &j, float (&ar)[K], float (&ai)[K]) {
+  const int q0 = threadIdx.x * K;
+  if (q0 >= j.nout) return;
+  if (j.head && q0 < M - 1) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int q = q0 + k;
-      if (q >= L || q >= j.nout) continue;
-      for (int b = 0; b < j.B; ++b) {
-        ar[k] += hp[b * L + q].x;
-        ai[k] += hp[b * L + q].y;
+      if (q < M - 1 && q < j.nout) {
+        ar[k] += sc[q].x;
+        ai[k] += sc[q].y;
       }
     }
   }
   const int64_t yo = j.yb + j.t0 + q0;
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (q0 + k < j.nout) y[(yo + k) & y_mask] = make_float2(ar[k], ai[k]);
+    if (q0 + k < j.nout) j.y[(yo + k) & j.y_mask] = make_float2(ar[k], ai[k]);
+}
+
+// Word w of a lane-distributed descriptor (lane w holds word w).
+__device__ __forceinline__ uint32_t dword_at(uint32_t dv, int w) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)dv, w);
+}
+__device__ __forceinline__ uint64_t qword_at(uint32_t dv, int w) {
+  return (uint64_t)dword_at(dv, w) | ((uint64_t)dword_at(dv, w + 1) << 32);
+}
+
+// The whole pipelined loop over tiles blockIdx.x, +gridDim.x, ... < n_items.
+// src.fetch(k) loads tile k's raw descriptor lane-distributed into one
+// register (a vector load, two tiles ahead); src.expand(dv, k, job) turns it
+// into the uniform Job (lane reads) when the tile's loads are issued.
+template <int M, int K, int BC, class Src>
+__device__ __forceinline__ void run_tiles(float2 *sx, float2 *sc, int64_t n_items, Src &src) {
+  const int64_t s = gridDim.x;
+  int64_t item = blockIdx.x;
+  if (item >= n_items) return;                       // uniform
+  Job cur, nxt;
+  src.expand(src.fetch(item), item, cur);
+  TileRegs<M, K> regs;
+  load_tile<M, K>(regs, cur);
+  bool has_next = item + s < n_items;
+  if (has_next) src.expand(src.fetch(item + s), item + s, nxt);
+  for (;;) {
+    commit_tile<M, K>(sx, sc, regs, cur);
+    __syncthreads();
+    const bool has_nn = item + 2 * s < n_items;
+    if (has_next) load_tile<M, K>(regs, nxt);
+    const uint32_t dv_nn = has_nn ? src.fetch(item + 2 * s) : 0u;
+    float ar[K], ai[K];
+    tile_compute<M, K, BC>(sx, as_const(cur.h), cur, ar, ai);
+    tile_store<M, K>(sc, cur, ar, ai);
+    if (!has_next) break;
+    __syncthreads();
+    item += s;
+    cur = nxt;
+    if (has_nn) src.expand(dv_nn, item + s, nxt);
+    has_next = has_nn;
+  }
 }
 
 }  // namespace dfh

@@ -58,78 +58,102 @@ __global__ __launch_bounds__(256) void k_dpd_generic(DpdArgs a) {
   a.y[(Wy + t) & a.y_mask] = make_float2(ar, ai);
 }
 
-// ------------------------------------------------------------------ tiled
-// Grid-stride loop over the batch's tiles (in the B-grouped firing order);
-// each workgroup prefetches its next tile while computing the current one.
-template <int M, int K>
-__global__ __launch_bounds__(256) void k_dpd_tiled(DpdArgs a) {
-  extern __shared__ float2 lds[];   // [2*B_max*(M-1)] histories, window
-  float2 *sq = lds, *sx = sq + lds_history(a.B_max, M);
-  const cfloat2p hg = as_const(a.h);
-  const int64_t n_items = a.n_firings * a.tiles_per_firing;
-  int64_t item = blockIdx.x;
-  if (item >= n_items) return;                       // uniform
-  const int64_t Rx = a.x_idx ? a.x_idx[0] : 0;
-  const int64_t Wy = a.y_idx ? a.y_idx[1] : 0;
-  auto job_of = [&](int64_t it, int64_t &g) {
-    const int64_t k = it / a.tiles_per_firing;
-    const int64_t tk = it - k * a.tiles_per_firing;
-    g = a.order ? a.order[k] : k;
-    TileJob j;
-    j.t0 = tk * a.tile;
-    j.nout = (int)min((int64_t)a.tile, a.r - j.t0);
-    j.B = a.B ? a.B[g] : a.B_const;
-    j.head = j.t0 == 0 && j.B > 0 && M > 1;
-    j.xb = Rx + g * a.r;
-    j.yb = Wy + g * a.r;
-    return j;
-  };
-  int64_t g;
-  TileJob job = job_of(item, g);
-  TileRegs<M, K> regs;
-  tile_prefetch<M, K>(regs, job, a.x, a.x_mask,
-                      [&](int b, int64_t ii) { return hist_sample(a, Rx, b, g, prev_of(a, b, g), ii); });
-  for (;;) {
-    tile_commit<M, K>(sx, sq, regs, job);
-    __syncthreads();
-    const int64_t next = item + gridDim.x;
-    int64_t ng = 0;
-    TileJob nj = job;
-    if (next < n_items) {
-      nj = job_of(next, ng);
-      tile_prefetch<M, K>(regs, nj, a.x, a.x_mask,
-                          [&](int b, int64_t ii) { return hist_sample(a, Rx, b, ng, prev_of(a, b, ng), ii); });
-    }
-    if (job.head) {
-      tile_head_sums<M>(sq, hg, job.B);
-      __syncthreads();
-    }
-    tile_outputs<M, K>(sx, hg, sq, job, a.y, a.y_mask);
-    if (next >= n_items) break;
-    __syncthreads();
-    item = next;
-    job = nj;
-    g = ng;
-  }
+// ------------------------------------------------------------------ heads
+// Head corrections of every firing with B > 0 (one wavefront per firing);
+// corr[g][q], q < M-1.  Read by the tiled body.
+template <int M>
+__global__ __launch_bounds__(256) void k_dpd_heads(DpdArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (g >= a.n_firings) return;                      // uniform per wavefront
+  const int B = a.B ? as_const(a.B)[g] : a.B_const;
+  if (B <= 0) return;
+  const int64_t Rx = a.x_idx ? as_const(a.x_idx)[0] : 0;
+  head_correction<M>(
+      B, as_const(a.h), [&](int b) { return prev_of(a, b, g); },
+      [&](int b, int64_t pf, int i) { return hist_sample(a, Rx, b, g, pf, (int64_t)i - (M - 1)); },
+      a.corr + g * (M - 1));
 }
 
-template <int M, int K>
+// ------------------------------------------------------------------ tiled
+// Tile descriptors of a single actor's batch: tile k is tile k % tpf of the
+// (k / tpf)-th firing in processing order (pairs (firing, B) from
+// k_order_by_b, or firing order).
+struct SingleSrc {
+  const DpdArgs &a;
+  int64_t Rx, Wy;
+  __device__ uint32_t fetch(int64_t it) const {
+    const int lane = threadIdx.x & 63;
+    const int64_t k = it / a.tiles_per_firing;
+    if (a.order) return lane < 2 ? (uint32_t)a.order[2 * k + lane] : 0u;
+    if (lane == 0) return (uint32_t)k;
+    if (lane == 1) return (uint32_t)(a.B ? a.B[k] : a.B_const);
+    return 0u;
+  }
+  __device__ void expand(uint32_t dv, int64_t it, Job &j) const {
+    const int64_t k = it / a.tiles_per_firing;
+    const int64_t tk = it - k * a.tiles_per_firing;
+    const int64_t g = dword_at(dv, 0);
+    const int B = (int)dword_at(dv, 1);
+    j.x = a.x;
+    j.y = a.y;
+    j.h = a.h;
+    j.corr = a.corr + g * (a.M - 1);
+    j.x_mask = a.x_mask;
+    j.y_mask = a.y_mask;
+    j.xb = Rx + g * a.r;
+    j.yb = Wy + g * a.r;
+    j.t0 = (int)(tk * a.tile);
+    j.nout = (int)min((int64_t)a.tile, a.r - j.t0);
+    j.B = B;
+    j.head = (j.t0 == 0 && B > 0) ? 1 : 0;
+  }
+};
+
+// Grid-stride loop over the batch's tiles in the B-grouped firing order,
+// pipelined as run_tiles describes.
+template <int M, int K, int BC>
+__global__ __launch_bounds__(256) void k_dpd_tiled(DpdArgs a) {
+  extern __shared__ float2 lds[];   // [M-1] head corrections, window
+  float2 *sc = lds, *sx = sc + lds_corr(M);
+  SingleSrc src{a, a.x_idx ? as_const(a.x_idx)[0] : 0, a.y_idx ? as_const(a.y_idx)[1] : 0};
+  run_tiles<M, K, BC>(sx, sc, a.n_firings * a.tiles_per_firing, src);
+}
+
+template <int M, int K, int BC>
 static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile) {
   DpdArgs a = a0;
   a.tile = tile;
   a.tiles_per_firing = (int32_t)((a.r + tile - 1) / tile);
   const int threads = tile / K;
-  const size_t lds = (size_t)(lds_window(tile + M - 1) + lds_history(a.B_max, M)) * sizeof(float2);
+  const size_t lds = (size_t)(lds_window(tile + M - 1) + lds_corr(M)) * sizeof(float2);
   const int64_t items = a.n_firings * a.tiles_per_firing;
   if (items <= 0) return hipSuccess;
-  const int64_t resident = resident_blocks((const void *)k_dpd_tiled<M, K>, threads, lds);
+  const int64_t resident = resident_blocks((const void *)k_dpd_tiled<M, K, BC>, threads, lds);
   const int64_t blocks = items < resident ? items : resident;
-  hipLaunchKernelGGL((k_dpd_tiled<M, K>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+  hipLaunchKernelGGL((k_dpd_tiled<M, K, BC>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+bool dpd_tiled_shape(int M) { return M == 4 || M == 8 || M == 16; }
+
+hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s) {
+  if (a.n_firings <= 0 || !dpd_tiled_shape(a.M)) return hipSuccess;
+  if (!a.corr) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((a.n_firings + 3) / 4));
+  if (a.M == 16) hipLaunchKernelGGL(k_dpd_heads<16>, grid, dim3(256), 0, s, a);
+  else if (a.M == 8) hipLaunchKernelGGL(k_dpd_heads<8>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_dpd_heads<4>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread) {
   if (a.n_firings <= 0) return hipSuccess;
+  if (!dpd_tiled_shape(a.M)) {
+    const int64_t total = a.n_firings * a.r;
+    hipLaunchKernelGGL(k_dpd_generic, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (!a.corr) return hipErrorInvalidValue;          // launch_dpd_heads fills it first
   // Tile: a multiple of 64*K outputs, at most 256 threads, no larger than
   // needed for one firing.
   const int K = outputs_per_thread == 8 ? 8 : 4;
@@ -139,23 +163,12 @@ hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int output
   t = (t / (64 * K)) * (64 * K);
   if (t < 64 * K) t = 64 * K;
   if (t / K > 256) t = 256 * K;
-  // the history prefetch gives each thread one sample: B_max*(M-1) <= threads
-  const int need = a.B_max * (a.M - 1);
-  while (t / K < need && t / K < 256) t += 64 * K;
-  if (t / K < need) {
-    const int64_t total = a.n_firings * a.r;
-    hipLaunchKernelGGL(k_dpd_generic, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
-  }
-  if (a.M == 16 && K == 4) return launch_tiled<16, 4>(a, s, t);
-  if (a.M == 16 && K == 8) return launch_tiled<16, 8>(a, s, t);
-  if (a.M == 8 && K == 4) return launch_tiled<8, 4>(a, s, t);
-  if (a.M == 8 && K == 8) return launch_tiled<8, 8>(a, s, t);
-  if (a.M == 4 && K == 4) return launch_tiled<4, 4>(a, s, t);
-  if (a.M == 4 && K == 8) return launch_tiled<4, 8>(a, s, t);
-  const int64_t total = a.n_firings * a.r;
-  hipLaunchKernelGGL(k_dpd_generic, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
-  return hipGetLastError();
+  const bool small = a.B_max <= 10;
+#define DF_TILED(m, k)                                                                      \
+  if (a.M == m && K == k) return small ? launch_tiled<m, k, 10>(a, s, t) : launch_tiled<m, k, 16>(a, s, t);
+  DF_TILED(16, 4) DF_TILED(16, 8) DF_TILED(8, 4) DF_TILED(8, 8) DF_TILED(4, 4) DF_TILED(4, 8)
+#undef DF_TILED
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------ commit

@@ -9,11 +9,12 @@
 //   last_b    = max{i < n : firing i feeds branch b}
 // where "feeds" is B_i > b (branch history) or always (shared history).
 //
-// One workgroup per segment of firings, which it walks in chunks of four
-// firings per thread.  Per chunk and branch, a thread counts its fed
-// firings and finds the last one; wavefront shuffles scan these (sum and
-// max), LDS holds the per-wavefront totals, and the segment carries
-// (count and last feeder so far) advance once per chunk.
+// One workgroup per segment of firings, which it walks in chunks of one
+// firing per thread.  Per chunk and branch, a wavefront ballot of the feed
+// flags gives the in-wavefront exclusive count (popcount of the bits below
+// the lane) and last feeder (highest bit below the lane); the per-wavefront
+// totals become exclusive prefixes in LDS, and the segment carries (count
+// and last feeder so far) advance once per chunk.
 #include "common.h"
 
 namespace dfh {
@@ -21,98 +22,69 @@ namespace dfh {
 constexpr int kScanThreads = 1024;
 constexpr int kScanWaves = kScanThreads / 64;
 
-__device__ __forceinline__ int wave_incl_sum(int v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(v, o);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
-
-__device__ __forceinline__ int wave_incl_max(int v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(v, o);
-    if (lane >= o) v = max(v, t);
-  }
-  return v;
-}
-
 __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
   __shared__ int wsum[kScanWaves][kMaxBranches], wlast[kScanWaves][kMaxBranches];
-  __shared__ int64_t carry_cnt[kMaxBranches], carry_last[kMaxBranches];
+  __shared__ int64_t carry_cnt[kMaxBranches], carry_last[kMaxBranches], chunk_cnt[kMaxBranches];
+  __shared__ int chunk_last[kMaxBranches];
   const int seg = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int64_t R = a.ctrl_idx ? a.ctrl_idx[0] : 0;
   const int64_t g0 = (int64_t)seg * a.seg_firings;
+  const uint64_t below_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
   if (tid < a.B_max) carry_cnt[tid] = 0, carry_last[tid] = -1;
-  const int64_t per_chunk = 4 * (int64_t)blockDim.x;
-  for (int64_t c0 = 0; c0 < a.seg_firings; c0 += per_chunk) {
-    const int64_t j0 = c0 + 4 * (int64_t)tid;          // first firing of this thread (segment-local)
-    int Bv[4];
-    bool in[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      in[k] = j0 + k < a.seg_firings;
-      int v = 0;
-      if (in[k]) {
-        v = a.ctrl[(R + g0 + j0 + k) & a.ctrl_mask];
-        if (v < 0 || v > a.B_max) {
-          if (a.err) atomicOr(a.err, (int32_t)kErrControl);
-          v = 0;
-        }
-        a.B_out[g0 + j0 + k] = v;
+  for (int64_t c0 = 0; c0 < a.seg_firings; c0 += blockDim.x) {
+    const int64_t j = c0 + tid;                       // segment-local firing
+    const bool in = j < a.seg_firings;
+    int Bv = 0;
+    if (in) {
+      Bv = a.ctrl[(R + g0 + j) & a.ctrl_mask];
+      if (Bv < 0 || Bv > a.B_max) {
+        if (a.err) atomicOr(a.err, (int32_t)kErrControl);
+        Bv = 0;
       }
-      Bv[k] = v;
+      a.B_out[g0 + j] = Bv;
     }
-    // pass 1: per-wavefront totals for every branch
+    // wavefront totals
     for (int b = 0; b < a.B_max; ++b) {
-      int c = 0, l = -1;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const bool f = in[k] && (a.hist_mode == 1 || Bv[k] > b);
-        c += f;
-        if (f) l = (int)(j0 - c0) + k;                  // chunk-local index
+      const uint64_t bal = __ballot(in && (a.hist_mode == 1 || Bv > b));
+      if (lane == 0) {
+        wsum[wave][b] = __popcll(bal);
+        wlast[wave][b] = bal ? 64 * wave + 63 - __clzll((long long)bal) : -1;
       }
-      const int cs = wave_incl_sum(c, lane), ls = wave_incl_max(l, lane);
-      if (lane == 63) wsum[wave][b] = cs, wlast[wave][b] = ls;
     }
     __syncthreads();
-    // pass 2: exclusive count and exclusive max per firing
-    for (int b = 0; b < a.B_max; ++b) {
-      bool f[4];
-      int c = 0, l = -1;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        f[k] = in[k] && (a.hist_mode == 1 || Bv[k] > b);
-        c += f[k];
-        if (f[k]) l = (int)(j0 - c0) + k;
-      }
-      const int cs = wave_incl_sum(c, lane), ls = wave_incl_max(l, lane);
-      int lprev = __shfl_up(ls, 1);
-      if (lane == 0) lprev = -1;
-      int64_t cnt = carry_cnt[b] + (cs - c);
+    // per branch: totals over the chunk into the carries, and the
+    // per-wavefront totals turned into exclusive prefixes (in place)
+    if (tid < a.B_max) {
+      int64_t cnt = 0;
       int wl = -1;
-      for (int w = 0; w < wave; ++w) cnt += wsum[w][b], wl = max(wl, wlast[w][b]);
-      wl = max(wl, lprev);
-      int64_t last = wl >= 0 ? c0 + wl : carry_last[b];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (!in[k]) break;
-        const int64_t o = (int64_t)b * a.stride + g0 + j0 + k;
+      for (int w = 0; w < nw; ++w) {
+        const int s_ = wsum[w][tid], l_ = wlast[w][tid];
+        wsum[w][tid] = (int)cnt;
+        wlast[w][tid] = wl;
+        cnt += s_;
+        wl = max(wl, l_);
+      }
+      chunk_cnt[tid] = cnt;
+      chunk_last[tid] = wl;
+    }
+    __syncthreads();
+    for (int b = 0; b < a.B_max; ++b) {
+      const uint64_t bal = __ballot(in && (a.hist_mode == 1 || Bv > b));
+      const uint64_t below = bal & below_mask;
+      const int64_t cnt = carry_cnt[b] + wsum[wave][b] + __popcll(below);
+      const int wl = below ? 64 * wave + 63 - __clzll((long long)below) : wlast[wave][b];
+      const int64_t last = wl >= 0 ? c0 + wl : carry_last[b];
+      if (in) {
+        const int64_t o = (int64_t)b * a.stride + g0 + j;
         a.prev_out[o] = last >= 0 ? g0 + last : -1;
         if (a.off_out) a.off_out[o] = a.r * cnt;
-        if (f[k]) cnt += 1, last = j0 + k;
       }
     }
     __syncthreads();
     if (tid < a.B_max) {
-      int64_t cnt = 0;
-      int wl = -1;
-      for (int w = 0; w < nw; ++w) cnt += wsum[w][tid], wl = max(wl, wlast[w][tid]);
-      carry_cnt[tid] += cnt;
-      if (wl >= 0) carry_last[tid] = c0 + wl;
+      carry_cnt[tid] += chunk_cnt[tid];
+      if (chunk_last[tid] >= 0) carry_last[tid] = c0 + chunk_last[tid];
     }
     __syncthreads();
   }
@@ -121,10 +93,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
 }
 
 // Processing order of a batch's firings, grouped by branch count B (largest
-// first).  The body kernels compile one fully unrolled code path per B;
-// grouping keeps the workgroups resident on a compute unit on one or two
-// paths, so their instructions stay cached.  The order inside a group is
-// irrelevant to the results (every firing's outputs are independent).
+// first), as pairs (firing, B).  The body kernels compile one fully unrolled
+// code path per B; grouping keeps the workgroups resident on a compute unit
+// on one or two paths, so their instructions stay cached.  The order inside
+// a group is irrelevant to the results (every firing's outputs are
+// independent).
 __global__ __launch_bounds__(1024) void k_order_by_b(const int32_t *B, int64_t n, int32_t B_max, int32_t *order) {
   __shared__ int32_t hist[kMaxBranches + 1], cursor[kMaxBranches + 1];
   if (threadIdx.x <= kMaxBranches) hist[threadIdx.x] = 0;
@@ -139,7 +112,12 @@ __global__ __launch_bounds__(1024) void k_order_by_b(const int32_t *B, int64_t n
     }
   }
   __syncthreads();
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) order[atomicAdd(&cursor[B[j]], 1)] = (int32_t)j;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const int v = B[j];
+    const int k = atomicAdd(&cursor[v], 1);
+    order[2 * k] = (int32_t)j;
+    order[2 * k + 1] = v;
+  }
 }
 
 hipError_t launch_order_by_b(const int32_t *B, int64_t n, int32_t B_max, int32_t *order, hipStream_t s) {
@@ -174,8 +152,8 @@ int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes) {
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s) {
   if (a.n_segs <= 0 || a.seg_firings <= 0) return hipSuccess;
   if (a.B_max < 1 || a.B_max > kMaxBranches) return hipErrorInvalidValue;
-  // four firings per thread; small segments take fewer wavefronts
-  int64_t waves = (a.seg_firings + 255) / 256;
+  // one firing per thread; small segments take fewer wavefronts
+  int64_t waves = (a.seg_firings + 63) / 64;
   if (waves > kScanWaves) waves = kScanWaves;
   hipLaunchKernelGGL(k_scan, dim3(a.n_segs), dim3(64 * (unsigned)waves), 0, s, a);
   return hipGetLastError();

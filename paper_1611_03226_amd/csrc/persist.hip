@@ -2,17 +2,20 @@
 //
 // Every instance is an independent actor with its own channels, coefficients
 // and control tokens; a batch fires instance i n_i times.  The chain is
-//   prep:     exclusive scan of n_i (firing bases), work-queue reset
+//   prep:     exclusive scan of n_i (firing bases)
 //   scan:     per-instance control intake and branch offset scan
+//   heads:    head corrections of every firing (one wavefront each)
 //   order:    instances grouped by branch count, work-item bases in that order
-//   body:     a persistent grid whose workgroups pull (instance, firing,
-//             tile) work items from a device counter until none is left
+//   items:    one descriptor per (instance, firing, tile) work item, in
+//             processing order
+//   body:     a persistent grid walking the work items with a grid stride
 //   commit:   per-instance channel indices and carried branch histories
 // All counts live in device memory, so the chain can be captured once in a
 // HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -41,6 +44,19 @@ struct InstDesc {
   int32_t pad;
 };
 
+// Work-item descriptor (what the body needs about one tile).
+struct PItem {
+  const float2 *x;
+  float2 *y;
+  const float2 *h;
+  const float2 *corr;     // head corrections of the firing [M-1]
+  int64_t x_mask, y_mask;
+  int64_t xb, yb;         // ring positions of the firing's first input / output sample
+  int32_t t0, nout, B, head;
+};
+
+static_assert(sizeof(PItem) % 4 == 0 && sizeof(PItem) / 4 <= 64, "descriptor fits one register");
+
 struct PersArgs {
   const InstDesc *inst;
   int32_t n_inst;
@@ -53,7 +69,9 @@ struct PersArgs {
   int64_t *prev_all;      // [Bg][cap], instance-local firing index or -1
   int64_t *last_all;      // [n_inst][Bg]
   int64_t cap;
-  int32_t *queue;
+  PItem *items;           // [items_cap]
+  float2 *corr_all;       // [cap][M-1] head corrections
+  int32_t M;
   int32_t *err;
   int32_t tile;
 };
@@ -74,10 +92,7 @@ __global__ __launch_bounds__(64) void k_pers_prep(PersArgs a) {
     if (i < a.n_inst) a.fire_base[i] = cf + sf - nf;
     cf += __shfl(sf, 63);
   }
-  if (lane == 0) {
-    a.fire_base[a.n_inst] = cf;
-    a.queue[0] = 0;
-  }
+  if (lane == 0) a.fire_base[a.n_inst] = cf;
 }
 
 // Processing order of the instances, grouped by the branch count of their
@@ -167,81 +182,100 @@ __global__ __launch_bounds__(1024) void k_pers_scan(PersArgs a) {
   if (lane == 0) a.last_all[(int64_t)i * a.Bg + b] = lastw;
 }
 
-// Persistent body: workgroups pull (instance, firing, tile) work items from
-// the queue; the next item's window and histories are loaded into registers
-// while the current item is computed from LDS.  The item number is made
-// wavefront-uniform, so the instance table and the instance's coefficients
-// are read with scalar loads.
-template <int M, int K>
-__global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
-  extern __shared__ float2 lds[];   // [2*Bg*(M-1)] histories, window
-  float2 *sq = lds, *sx = sq + lds_history(a.Bg, M);
-  __shared__ int item_s;
-  const auto *inst = as_const(a.inst);
-  const auto *tile_base = as_const(a.tile_base);
-  const int64_t total = tile_base[a.n_inst];
-  if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1);
-  __syncthreads();
-  int64_t item = __builtin_amdgcn_readfirstlane(item_s);
-  if (item >= total) return;                          // uniform: every wave leaves
-  struct Item {
-    int inst;
-    int64_t gfire, Rx, j;
-  };
-  auto decode = [&](int64_t it, Item &d, TileJob &job) {
-    int lo = 0, hi = a.n_inst - 1;                    // last ordered instance with base <= it
+// Work-item descriptors: item k (processing order) -> the last ordered
+// instance whose tile base is <= k, its firing and tile.
+__global__ __launch_bounds__(256) void k_pers_items(PersArgs a) {
+  const int64_t total = a.tile_base[a.n_inst];
+  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < total; it += (int64_t)gridDim.x * 256) {
+    int lo = 0, hi = a.n_inst - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (tile_base[mid] <= it) lo = mid; else hi = mid - 1;
+      if (a.tile_base[mid] <= it) lo = mid; else hi = mid - 1;
     }
-    d.inst = as_const(a.inst_order)[lo];
-    const auto &ds = inst[d.inst];
-    const int64_t local = it - tile_base[lo];
-    d.j = local / ds.tpf;
-    d.gfire = as_const(a.fire_base)[d.inst] + d.j;
-    d.Rx = as_const(ds.x_idx)[0];
-    job.t0 = (local - d.j * ds.tpf) * a.tile;
-    job.nout = (int)min((int64_t)a.tile, ds.r - job.t0);
-    job.B = as_const(a.B_all)[d.gfire];
-    job.head = (job.t0 == 0 && job.B > 0 && M > 1) ? 1 : 0;
-    job.xb = d.Rx + d.j * ds.r;
-    job.yb = as_const(ds.y_idx)[1] + d.j * ds.r;
-  };
-  auto prefetch = [&](const Item &d, const TileJob &job, TileRegs<M, K> &r) {
-    const auto &ds = inst[d.inst];
-    tile_prefetch<M, K>(r, job, ds.x, ds.x_mask, [&](int b, int64_t ii) {
-      const int64_t pf = a.prev_all[(int64_t)b * a.cap + d.gfire];
-      if (pf >= 0) return ds.x[(d.Rx + pf * ds.r + ds.r + ii) & ds.x_mask];
-      return ds.hist[b * (M - 1) + (M - 1) + ii];
-    });
-  };
-  Item cur;
-  TileJob job;
-  decode(item, cur, job);
-  TileRegs<M, K> regs;
-  prefetch(cur, job, regs);
-  for (;;) {
-    tile_commit<M, K>(sx, sq, regs, job);
-    if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1);
-    __syncthreads();
-    const int64_t next = __builtin_amdgcn_readfirstlane(item_s);
-    Item nd = cur;
-    TileJob nj = job;
-    if (next < total) {
-      decode(next, nd, nj);
-      prefetch(nd, nj, regs);
-    }
-    const cfloat2p hg = as_const(inst[cur.inst].h);
-    if (job.head) {
-      tile_head_sums<M>(sq, hg, job.B);
-      __syncthreads();
-    }
-    tile_outputs<M, K>(sx, hg, sq, job, inst[cur.inst].y, inst[cur.inst].y_mask);
-    if (next >= total) break;
-    __syncthreads();
-    cur = nd;
-    job = nj;
+    const int i = a.inst_order[lo];
+    const InstDesc &d = a.inst[i];
+    const int64_t local = it - a.tile_base[lo];
+    const int64_t j = local / d.tpf;
+    const int64_t t0 = (local - j * d.tpf) * a.tile;
+    const int64_t gf = a.fire_base[i] + j;
+    const int B = a.B_all[gf];
+    const int64_t Rx = d.x_idx[0];
+    PItem p;
+    p.x = d.x;
+    p.y = d.y;
+    p.h = d.h;
+    p.corr = a.corr_all + gf * (a.M - 1);
+    p.x_mask = d.x_mask;
+    p.y_mask = d.y_mask;
+    p.xb = Rx + j * d.r;
+    p.yb = d.y_idx[1] + j * d.r;
+    p.t0 = (int32_t)t0;
+    p.nout = (int32_t)min((int64_t)a.tile, d.r - t0);
+    p.B = B;
+    p.head = (t0 == 0 && B > 0) ? 1 : 0;
+    a.items[it] = p;
   }
+}
+
+// Tile descriptors of the persistent batch: the work-item table.
+struct ItemSrc {
+  const PersArgs &a;
+  static constexpr int kWords = (int)(sizeof(PItem) / 4);
+  __device__ uint32_t fetch(int64_t it) const {
+    const int lane = threadIdx.x & 63;
+    return lane < kWords ? reinterpret_cast<const uint32_t *>(a.items + it)[lane] : 0u;
+  }
+  __device__ void expand(uint32_t dv, int64_t, Job &j) const {
+    j.x = (const float2 *)qword_at(dv, offsetof(PItem, x) / 4);
+    j.y = (float2 *)qword_at(dv, offsetof(PItem, y) / 4);
+    j.h = (const float2 *)qword_at(dv, offsetof(PItem, h) / 4);
+    j.corr = (const float2 *)qword_at(dv, offsetof(PItem, corr) / 4);
+    j.x_mask = (int64_t)qword_at(dv, offsetof(PItem, x_mask) / 4);
+    j.y_mask = (int64_t)qword_at(dv, offsetof(PItem, y_mask) / 4);
+    j.xb = (int64_t)qword_at(dv, offsetof(PItem, xb) / 4);
+    j.yb = (int64_t)qword_at(dv, offsetof(PItem, yb) / 4);
+    j.t0 = (int)dword_at(dv, offsetof(PItem, t0) / 4);
+    j.nout = (int)dword_at(dv, offsetof(PItem, nout) / 4);
+    j.B = (int)dword_at(dv, offsetof(PItem, B) / 4);
+    j.head = (int)dword_at(dv, offsetof(PItem, head) / 4);
+  }
+};
+
+// Head corrections of all instances' firings: wavefront w takes global
+// firings w, w + total wavefronts, ...; the instance of a firing is the last
+// one whose firing base is <= it.
+template <int M>
+__global__ __launch_bounds__(256) void k_pers_heads(PersArgs a) {
+  const int64_t total = a.fire_base[a.n_inst];
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t gf = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); gf < total;
+       gf += nwaves) {
+    int lo = 0, hi = a.n_inst - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.fire_base[mid] <= gf) lo = mid; else hi = mid - 1;
+    }
+    const InstDesc &d = a.inst[lo];
+    const int B = a.B_all[gf];
+    if (B <= 0) continue;
+    const int64_t Rx = d.x_idx[0];
+    head_correction<M>(
+        B, as_const(d.h), [&](int b) { return a.prev_all[(int64_t)b * a.cap + gf]; },
+        [&](int b, int64_t pf, int i) {
+          if (pf >= 0) return d.x[(Rx + pf * d.r + d.r - (M - 1) + i) & d.x_mask];
+          return d.hist[b * (M - 1) + i];
+        },
+        a.corr_all + gf * (M - 1));
+  }
+}
+
+// Persistent body: a grid-stride walk over the work items (run_tiles).
+template <int M, int K, int BC>
+__global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
+  extern __shared__ float2 lds[];   // [M-1] head corrections, window
+  float2 *sc = lds, *sx = sc + lds_corr(M);
+  ItemSrc src{a};
+  run_tiles<M, K, BC>(sx, sc, as_const(a.tile_base)[a.n_inst], src);
 }
 
 __global__ __launch_bounds__(256) void k_pers_commit(PersArgs a, int M) {
@@ -274,8 +308,10 @@ struct Persistent {
   int64_t *n_dev = nullptr;
   std::vector<int64_t> n_host;
   int64_t *fire_base = nullptr, *tile_base = nullptr, *prev_all = nullptr, *last_all = nullptr;
-  int32_t *B_all = nullptr, *queue = nullptr, *inst_order = nullptr;
-  int64_t cap = 0;
+  float2 *corr_all = nullptr;
+  int32_t *B_all = nullptr, *inst_order = nullptr;
+  PItem *items = nullptr;
+  int64_t cap = 0, items_cap = 0;
   int tile = 0, K = 0, bpc = 0, ncu = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -298,41 +334,48 @@ void destroy_persistent(df_graph *g) {
   (void)hipFree(p->fire_base);
   (void)hipFree(p->tile_base);
   (void)hipFree(p->prev_all);
+  (void)hipFree(p->corr_all);
   (void)hipFree(p->last_all);
   (void)hipFree(p->B_all);
-  (void)hipFree(p->queue);
+  (void)hipFree(p->items);
   (void)hipFree(p->inst_order);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
   g->pers = nullptr;
 }
 
-template <int M, int K>
+template <int M, int K, int BC>
 static hipError_t launch_pers_body(const PersArgs &a, int threads, int blocks, hipStream_t s) {
-  const size_t lds = (size_t)(lds_window(a.tile + M - 1) + lds_history(a.Bg, M)) * sizeof(float2);
-  hipLaunchKernelGGL((k_pers_body<M, K>), dim3(blocks), dim3(threads), lds, s, a);
+  const size_t lds = (size_t)(lds_window(a.tile + M - 1) + lds_corr(M)) * sizeof(float2);
+  hipLaunchKernelGGL((k_pers_body<M, K, BC>), dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
 static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s, df_graph *prof_g) {
-  if (a.Bg * (p->M - 1) > kHistRegs * (p->tile / p->K)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pers_prep, dim3(1), dim3(64), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pers_scan, dim3(a.n_inst), dim3(64 * a.Bg), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (p->M == 16) hipLaunchKernelGGL(k_pers_heads<16>, dim3(4 * p->ncu), dim3(256), 0, s, a);
+  else if (p->M == 8) hipLaunchKernelGGL(k_pers_heads<8>, dim3(4 * p->ncu), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_pers_heads<4>, dim3(4 * p->ncu), dim3(256), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_pers_order, dim3(1), dim3(1024), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pers_items, dim3(4 * p->ncu), dim3(256), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int threads = p->tile / p->K;
   const int blocks = p->bpc * p->ncu;
   if (prof_g && (e = prof_begin(prof_g)) != hipSuccess) return e;
-  if (p->M == 16 && p->K == 4) e = launch_pers_body<16, 4>(a, threads, blocks, s);
-  else if (p->M == 16 && p->K == 8) e = launch_pers_body<16, 8>(a, threads, blocks, s);
-  else if (p->M == 8 && p->K == 4) e = launch_pers_body<8, 4>(a, threads, blocks, s);
-  else if (p->M == 8 && p->K == 8) e = launch_pers_body<8, 8>(a, threads, blocks, s);
-  else if (p->M == 4 && p->K == 4) e = launch_pers_body<4, 4>(a, threads, blocks, s);
-  else if (p->M == 4 && p->K == 8) e = launch_pers_body<4, 8>(a, threads, blocks, s);
-  else return hipErrorInvalidValue;
+  const bool small = a.Bg <= 10;
+#define DF_PERS(m, k)                                                                              \
+  if (p->M == m && p->K == k)                                                                      \
+    e = small ? launch_pers_body<m, k, 10>(a, threads, blocks, s) : launch_pers_body<m, k, 16>(a, threads, blocks, s); \
+  else
+  DF_PERS(16, 4) DF_PERS(16, 8) DF_PERS(8, 4) DF_PERS(8, 8) DF_PERS(4, 4) DF_PERS(4, 8)
+  return hipErrorInvalidValue;
+#undef DF_PERS
   if (e != hipSuccess) return e;
   if (prof_g && (e = prof_end(prof_g)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_pers_commit, dim3(a.n_inst), dim3(256), 0, s, a, p->M);
@@ -410,7 +453,6 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
     HIPCHK(g, hipMalloc(&p->fire_base, sizeof(int64_t) * (n_actors + 1)));
     HIPCHK(g, hipMalloc(&p->tile_base, sizeof(int64_t) * (n_actors + 1)));
     HIPCHK(g, hipMalloc(&p->last_all, sizeof(int64_t) * n_actors * Bg));
-    HIPCHK(g, hipMalloc(&p->queue, sizeof(int32_t) * 64));
     HIPCHK(g, hipMalloc(&p->inst_order, sizeof(int32_t) * n_actors));
   }
   // Tile configuration: a multiple of 64*K outputs, no larger than needed.
@@ -419,8 +461,6 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
   const int64_t rr = ((max_r + 64 * K - 1) / (64 * K)) * (64 * K);
   if (tile > rr) tile = (int)rr;
   tile = std::max(64 * K, std::min(512 * K, (tile / (64 * K)) * (64 * K)));
-  // one history sample per thread
-  while (tile / K < 512 && tile / K < Bg * (M - 1)) tile += 64 * K;
   const int bpc = g->blocks_per_cu > 0 ? g->blocks_per_cu : 4;
   bool rebuild = !same_list || tile != p->tile || K != p->K || bpc != p->bpc;
   if (total > p->cap) {
@@ -429,11 +469,29 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
     while (cap < total) cap <<= 1;
     (void)hipFree(p->B_all);
     (void)hipFree(p->prev_all);
+    (void)hipFree(p->corr_all);
     p->B_all = nullptr;
     p->prev_all = nullptr;
+    p->corr_all = nullptr;
     HIPCHK(g, hipMalloc(&p->B_all, sizeof(int32_t) * cap));
     HIPCHK(g, hipMalloc(&p->prev_all, sizeof(int64_t) * cap * Bg));
+    HIPCHK(g, hipMalloc(&p->corr_all, sizeof(float2) * cap * (M - 1)));
     p->cap = cap;
+    rebuild = true;
+  }
+  int64_t n_items = 0;
+  for (int i = 0; i < n_actors; ++i) {
+    const int64_t r = g->actors[actors[i]].dp.firing_size;
+    n_items += n_firings[i] * ((r + tile - 1) / tile);
+  }
+  if (n_items > p->items_cap) {
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    int64_t cap = 1024;
+    while (cap < n_items) cap <<= 1;
+    (void)hipFree(p->items);
+    p->items = nullptr;
+    HIPCHK(g, hipMalloc(&p->items, sizeof(PItem) * cap));
+    p->items_cap = cap;
     rebuild = true;
   }
   if (rebuild) {
@@ -486,7 +544,9 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
   pa.prev_all = p->prev_all;
   pa.last_all = p->last_all;
   pa.cap = p->cap;
-  pa.queue = p->queue;
+  pa.items = p->items;
+  pa.corr_all = p->corr_all;
+  pa.M = p->M;
   pa.inst_order = p->inst_order;
   pa.err = g->err_dev;
   pa.tile = p->tile;

@@ -117,6 +117,7 @@ static void free_actor(Actor &a) {
   (void)hipFree(a.hist);
   (void)hipFree(a.B);
   (void)hipFree(a.order);
+  (void)hipFree(a.corr);
   (void)hipFree(a.prev);
   (void)hipFree(a.off);
   (void)hipFree(a.last);
@@ -448,9 +449,10 @@ df_status dfh::ensure_dpd_scratch(df_graph *g, Actor &a, int64_t n) {
   const int64_t cap = std::max<int64_t>(next_pow2(n), 64);
   const int bm = a.dp.n_branches_max;
   if (grow((void **)&a.B, sizeof(int32_t) * cap) != hipSuccess ||
-      grow((void **)&a.order, sizeof(int32_t) * cap) != hipSuccess ||
+      grow((void **)&a.order, 2 * sizeof(int32_t) * cap) != hipSuccess ||
       grow((void **)&a.prev, sizeof(int64_t) * bm * cap) != hipSuccess ||
-      grow((void **)&a.off, sizeof(int64_t) * bm * cap) != hipSuccess)
+      grow((void **)&a.off, sizeof(int64_t) * bm * cap) != hipSuccess ||
+      grow((void **)&a.corr, sizeof(float2) * std::max(a.dp.n_taps - 1, 1) * cap) != hipSuccess)
     return fail(g, DF_ENOMEM, "scratch allocation failed");
   a.scratch_n = cap;
   return DF_OK;
@@ -516,6 +518,8 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   da.r = r;
   da.B_max = bm;
   da.M = M;
+  da.corr = a.corr;
+  HIPCHK(g, launch_dpd_heads(da, g->stream));
   HIPCHK(g, prof_begin(g));
   HIPCHK(g, launch_dpd_body(da, g->stream, g->tile, g->outputs_per_thread));
   HIPCHK(g, prof_end(g));

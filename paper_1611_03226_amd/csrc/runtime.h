@@ -41,7 +41,8 @@ struct Actor {
   float2 *hist = nullptr;    // [B_max][M-1] carried branch histories
   int64_t scratch_n = 0;
   int32_t *B = nullptr;      // [scratch_n]
-  int32_t *order = nullptr;  // [scratch_n] firings grouped by B
+  int32_t *order = nullptr;  // [scratch_n][2] (firing, B) grouped by B
+  float2 *corr = nullptr;    // [scratch_n][M-1] head corrections
   int64_t *prev = nullptr;   // [B_max][scratch_n]
   int64_t *off = nullptr;    // [B_max][scratch_n]
   int64_t *last = nullptr;   // [B_max]

@@ -79,16 +79,23 @@ extern "C" df_status df_dpd_forward(void *stream, const void *x, const int32_t *
   a.M = M;
   Tables t;
   hipError_t e;
+  float2 *corr = nullptr;
   if (!ctrl) {
     // All branches active in every firing: a row is one convolution.
     a.B_const = B_max;
     a.seg_firings = 1;
     a.n_firings = S;
     a.r = len;
-    e = launch_dpd_body(a, s, 0, 4);
+    e = hipMallocAsync((void **)&corr, sizeof(float2) * std::max(M - 1, 1) * S, s);
+    if (e == hipSuccess) {
+      a.corr = corr;
+      e = launch_dpd_heads(a, s);
+    }
+    if (e == hipSuccess) e = launch_dpd_body(a, s, 0, 4);
   } else {
     const int64_t nf = len / r;
     e = make_tables(ctrl, S, nf, r, B_max, hist, s, &t);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&corr, sizeof(float2) * std::max(M - 1, 1) * S * nf, s);
     if (e == hipSuccess) {
       a.B = t.B;
       a.prev = t.prev;
@@ -96,10 +103,13 @@ extern "C" df_status df_dpd_forward(void *stream, const void *x, const int32_t *
       a.seg_firings = nf;
       a.n_firings = S * nf;
       a.r = r;
-      e = launch_dpd_body(a, s, 0, 4);
+      a.corr = corr;
+      e = launch_dpd_heads(a, s);
+      if (e == hipSuccess) e = launch_dpd_body(a, s, 0, 4);
     }
     free_tables(&t, s);
   }
+  if (corr) (void)hipFreeAsync(corr, s);
   if (e != hipSuccess) return fail_hip(nullptr, e, "df_dpd_forward");
   return DF_OK;
 }
