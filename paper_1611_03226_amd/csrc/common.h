@@ -63,6 +63,8 @@ struct ScanArgs {
   int64_t *prev_out;      // [B_max][stride]
   int64_t *off_out;       // [B_max][stride] (may be nullptr)
   int64_t *last_out;      // [n_segs][B_max] (may be nullptr)
+  int32_t *order_out;     // [n][2] (firing, B) grouped by B, largest first (one segment), or nullptr
+  int64_t *grp;           // [scan_groups][B_max][2] scratch: count and last feeder before each 64-firing group
   int64_t stride;
   int64_t r;
   int32_t *err;           // sticky error word (may be nullptr)
@@ -131,11 +133,18 @@ struct AdjArgs {
 int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes);
 
 // ---------------------------------------------------------------- launchers
+int64_t scan_groups(int64_t n_segs, int64_t seg_firings);   // 64-firing groups of a scan
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
+// Optional start/stop events of one kernel launch (timing rides on the
+// dispatch itself: hipExtLaunchKernel), or none.
+struct KTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 bool dpd_tiled_shape(int M);
 hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s);
-hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread);
-hipError_t launch_order_by_b(const int32_t *B, int64_t n, int32_t B_max, int32_t *order, hipStream_t s);
+hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread,
+                           const KTiming *timing = nullptr);
 hipError_t launch_dpd_commit(const DpdCommitArgs &a, hipStream_t s);
 hipError_t launch_advance(int64_t *idx, int64_t delta, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);

@@ -99,52 +99,78 @@ __device__ __forceinline__ void horner_taps(cfloat2p hg, const float2 *sx, int q
 // LDS float2 slots for a firing's head corrections (M-1 outputs).
 __host__ __device__ constexpr int lds_corr(int M) { return M > 1 ? M - 1 : 1; }
 
-// Head correction of one firing (one wavefront).  Outputs q < M-1 of a
-// firing reach back before its first sample, where branch b reads its own
-// history source (the tail of its last feeding firing, or the carried
-// state).  The tile body stages zeros there; this adds the difference:
+// Lane i of a 16-lane row receives lane i+S of the same row (0 past the
+// row end): one DPP move.
+template <int S>
+__device__ __forceinline__ float row_shl(float v) {
+  if constexpr (S == 0) {
+    return v;
+  } else {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x100 + S, 0xF, 0xF, true));
+  }
+}
+
+// Taps m..M-1 of one branch's head correction for output i of the lane's
+// row: psi of history sample i - m sits in lane (M-1) + i - m of the row.
+// For m <= i (no history term) that lane is an idle lane of the row (psi 0)
+// or past the row end (the shift yields 0), so every tap is summed.
+template <int M, int m>
+__device__ __forceinline__ void head_taps(cfloat2p hg, int b, float psr, float psi, float &sr, float &si) {
+  const float2 c = ldc(hg, b * M + m);
+  const float vr = row_shl<M - 1 - m>(psr), vi = row_shl<M - 1 - m>(psi);
+  sr = fmaf(c.x, vr, sr);
+  sr = fmaf(-c.y, vi, sr);
+  si = fmaf(c.x, vi, si);
+  si = fmaf(c.y, vr, si);
+  if constexpr (m + 1 < M) head_taps<M, m + 1>(hg, b, psr, psi, sr, si);
+}
+
+// Head corrections of up to four firings of one actor (one wavefront; lane
+// 16*row + i serves firing `row`, history sample / output i).  Outputs
+// q < M-1 of a firing reach back before its first sample, where branch b
+// reads its own history source (the tail of its last feeding firing, or the
+// carried state).  The tile body stages zeros there; this adds the
+// difference:
 //   corr[q] = sum_{b<B} sum_{m=q+1}^{M-1} h_b[m] psi_b(src_b[q-m]),
-// accumulated branch by branch.  Lane i holds history sample i (i < M-1)
-// of every branch, loaded all at once; psi values move between lanes by
-// shuffles and the coefficients are scalar loads (B is uniform).
-//   src_of(b)          -> history source firing of branch b (-1: state)
-//   sample(b, pf, i)   -> sample i of branch b's history
-template <int M, class SrcOf, class Sample>
-__device__ __forceinline__ void head_correction(int B, cfloat2p hg, SrcOf src_of, Sample sample, float2 *out) {
+// accumulated branch by branch.  All history loads are issued at once; psi
+// values move inside a row by DPP row shifts; the coefficients are the same
+// for every row (uniform scalar loads).
+//   B_of(row) -> branch count of the row's firing (0: no correction)
+//   src_of(row, b) -> history source firing of branch b (-1: carried state)
+//   sample(row, b, pf, i) -> sample i of branch b's history
+//   out(row) -> where the row's M-1 corrections go
+template <int M, int ROWS, class BOf, class SrcOf, class Sample, class Out>
+__device__ __forceinline__ void head_correction(cfloat2p hg, BOf B_of, SrcOf src_of, Sample sample, Out out) {
   constexpr int L = M - 1;
-  const int lane = threadIdx.x & 63;
-  const bool in = lane < L;
+  static_assert(L < 16, "one row of 16 lanes per firing");
+  const int lane = threadIdx.x & 63, row = lane >> 4, i = lane & 15;
+  const bool live = row < ROWS && i < L;
+  const int B = row < ROWS ? B_of(row) : 0;
+  int Bw = B;                                          // largest B of the wavefront
+#pragma unroll
+  for (int o = 16; o < 64; o <<= 1) Bw = max(Bw, __shfl_xor(Bw, o));
+  Bw = __builtin_amdgcn_readfirstlane(Bw);
   int64_t pf[kMaxBranches];
 #pragma unroll
-  for (int b = 0; b < kMaxBranches; ++b) pf[b] = (b < B && in) ? src_of(b) : -1;
+  for (int b = 0; b < kMaxBranches; ++b) pf[b] = (b < B && live) ? src_of(row, b) : -1;
   float2 xs[kMaxBranches];
 #pragma unroll
-  for (int b = 0; b < kMaxBranches; ++b) xs[b] = (b < B && in) ? sample(b, pf[b], lane) : make_float2(0.f, 0.f);
+  for (int b = 0; b < kMaxBranches; ++b) xs[b] = (b < B && live) ? sample(row, b, pf[b], i) : make_float2(0.f, 0.f);
   float cr = 0.f, ci = 0.f;
 #pragma unroll
   for (int b = 0; b < kMaxBranches; ++b) {
-    if (b >= B) continue;                              // uniform
+    if (b >= Bw) continue;                             // uniform
     const float pp = fmaf(xs[b].x, xs[b].x, xs[b].y * xs[b].y);
     float pb = 1.f;
     for (int e = 0; e < b; ++e) pb *= pp;
-    const float psr = pb * xs[b].x, psi = pb * xs[b].y;
     float sr = 0.f, si = 0.f;
-#pragma unroll
-    for (int m = 1; m < M; ++m) {
-      const float2 c = ldc(hg, b * M + m);
-      const int src = lane - m + L;                    // history sample q - m
-      const float vr = __shfl(psr, src), vi = __shfl(psi, src);
-      if (m > lane) {
-        sr = fmaf(c.x, vr, sr);
-        sr = fmaf(-c.y, vi, sr);
-        si = fmaf(c.x, vi, si);
-        si = fmaf(c.y, vr, si);
-      }
+    head_taps<M, 1>(hg, b, pb * xs[b].x, pb * xs[b].y, sr, si);
+    if (b < B) {
+      cr += sr;
+      ci += si;
     }
-    cr += sr;
-    ci += si;
   }
-  if (in) out[lane] = make_float2(cr, ci);
+  if (live && B > 0) out(row)[i] = make_float2(cr, ci);
 }
 
 // The tile pipeline.  A workgroup of NT threads computes tiles of K*NT

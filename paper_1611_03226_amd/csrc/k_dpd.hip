@@ -9,6 +9,8 @@
 // Only the first M-1 outputs of a firing reach back into branch histories,
 // which differ per branch (history source firing prev_b(g), or carried
 // state); those terms are added by a per-branch correction.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "dpd_tile.h"
 
@@ -59,25 +61,28 @@ __global__ __launch_bounds__(256) void k_dpd_generic(DpdArgs a) {
 }
 
 // ------------------------------------------------------------------ heads
-// Head corrections of every firing with B > 0 (one wavefront per firing);
-// corr[g][q], q < M-1.  Read by the tiled body.
+// Head corrections of every firing with B > 0 (four firings per
+// wavefront); corr[g][q], q < M-1.  Read by the tiled body.
 template <int M>
 __global__ __launch_bounds__(256) void k_dpd_heads(DpdArgs a) {
-  const int64_t g = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (g >= a.n_firings) return;                      // uniform per wavefront
-  const int B = a.B ? as_const(a.B)[g] : a.B_const;
-  if (B <= 0) return;
+  const int64_t g0 = ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * 4;
+  if (g0 >= a.n_firings) return;                     // uniform per wavefront
   const int64_t Rx = a.x_idx ? as_const(a.x_idx)[0] : 0;
-  head_correction<M>(
-      B, as_const(a.h), [&](int b) { return prev_of(a, b, g); },
-      [&](int b, int64_t pf, int i) { return hist_sample(a, Rx, b, g, pf, (int64_t)i - (M - 1)); },
-      a.corr + g * (M - 1));
+  head_correction<M, 4>(
+      as_const(a.h),
+      [&](int row) {
+        const int64_t g = g0 + row;
+        return g < a.n_firings ? (a.B ? a.B[g] : a.B_const) : 0;
+      },
+      [&](int row, int b) { return prev_of(a, b, g0 + row); },
+      [&](int row, int b, int64_t pf, int i) { return hist_sample(a, Rx, b, g0 + row, pf, (int64_t)i - (M - 1)); },
+      [&](int row) { return a.corr + (g0 + row) * (M - 1); });
 }
 
 // ------------------------------------------------------------------ tiled
 // Tile descriptors of a single actor's batch: tile k is tile k % tpf of the
-// (k / tpf)-th firing in processing order (pairs (firing, B) from
-// k_order_by_b, or firing order).
+// (k / tpf)-th firing in processing order (pairs (firing, B) from the
+// scan, or firing order).
 struct SingleSrc {
   const DpdArgs &a;
   int64_t Rx, Wy;
@@ -120,7 +125,7 @@ __global__ __launch_bounds__(256) void k_dpd_tiled(DpdArgs a) {
 }
 
 template <int M, int K, int BC>
-static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile) {
+static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile, const KTiming *t) {
   DpdArgs a = a0;
   a.tile = tile;
   a.tiles_per_firing = (int32_t)((a.r + tile - 1) / tile);
@@ -130,7 +135,11 @@ static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile) {
   if (items <= 0) return hipSuccess;
   const int64_t resident = resident_blocks((const void *)k_dpd_tiled<M, K, BC>, threads, lds);
   const int64_t blocks = items < resident ? items : resident;
-  hipLaunchKernelGGL((k_dpd_tiled<M, K, BC>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+  if (t)
+    hipExtLaunchKernelGGL((k_dpd_tiled<M, K, BC>), dim3((unsigned)blocks), dim3(threads), lds, s, t->start, t->stop,
+                          0, a);
+  else
+    hipLaunchKernelGGL((k_dpd_tiled<M, K, BC>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -139,33 +148,37 @@ bool dpd_tiled_shape(int M) { return M == 4 || M == 8 || M == 16; }
 hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s) {
   if (a.n_firings <= 0 || !dpd_tiled_shape(a.M)) return hipSuccess;
   if (!a.corr) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((a.n_firings + 3) / 4));
+  const dim3 grid((unsigned)((a.n_firings + 15) / 16));
   if (a.M == 16) hipLaunchKernelGGL(k_dpd_heads<16>, grid, dim3(256), 0, s, a);
   else if (a.M == 8) hipLaunchKernelGGL(k_dpd_heads<8>, grid, dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_dpd_heads<4>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread) {
+hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread, const KTiming *t) {
   if (a.n_firings <= 0) return hipSuccess;
   if (!dpd_tiled_shape(a.M)) {
     const int64_t total = a.n_firings * a.r;
-    hipLaunchKernelGGL(k_dpd_generic, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+    const dim3 grid((unsigned)((total + 255) / 256));
+    if (t)
+      hipExtLaunchKernelGGL(k_dpd_generic, grid, dim3(256), 0, s, t->start, t->stop, 0, a);
+    else
+      hipLaunchKernelGGL(k_dpd_generic, grid, dim3(256), 0, s, a);
     return hipGetLastError();
   }
   if (!a.corr) return hipErrorInvalidValue;          // launch_dpd_heads fills it first
   // Tile: a multiple of 64*K outputs, at most 256 threads, no larger than
   // needed for one firing.
   const int K = outputs_per_thread == 8 ? 8 : 4;
-  int t = tile > 0 ? tile : 1024;
+  int tl = tile > 0 ? tile : 1024;
   const int64_t rr = ((a.r + 64 * K - 1) / (64 * K)) * (64 * K);
-  if ((int64_t)t > rr) t = (int)rr;
-  t = (t / (64 * K)) * (64 * K);
-  if (t < 64 * K) t = 64 * K;
-  if (t / K > 256) t = 256 * K;
+  if ((int64_t)tl > rr) tl = (int)rr;
+  tl = (tl / (64 * K)) * (64 * K);
+  if (tl < 64 * K) tl = 64 * K;
+  if (tl / K > 256) tl = 256 * K;
   const bool small = a.B_max <= 10;
 #define DF_TILED(m, k)                                                                      \
-  if (a.M == m && K == k) return small ? launch_tiled<m, k, 10>(a, s, t) : launch_tiled<m, k, 16>(a, s, t);
+  if (a.M == m && K == k) return small ? launch_tiled<m, k, 10>(a, s, tl, t) : launch_tiled<m, k, 16>(a, s, tl, t);
   DF_TILED(16, 4) DF_TILED(16, 8) DF_TILED(8, 4) DF_TILED(8, 8) DF_TILED(4, 4) DF_TILED(4, 8)
 #undef DF_TILED
   return hipErrorInvalidValue;

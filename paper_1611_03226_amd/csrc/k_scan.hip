@@ -9,122 +9,162 @@
 //   last_b    = max{i < n : firing i feeds branch b}
 // where "feeds" is B_i > b (branch history) or always (shared history).
 //
-// One workgroup per segment of firings, which it walks in chunks of one
-// firing per thread.  Per chunk and branch, a wavefront ballot of the feed
-// flags gives the in-wavefront exclusive count (popcount of the bits below
-// the lane) and last feeder (highest bit below the lane); the per-wavefront
-// totals become exclusive prefixes in LDS, and the segment carries (count
-// and last feeder so far) advance once per chunk.
+// Two kernels.  k_scan: one workgroup per segment of firings; a pass
+// covers kScanChunks firings per thread (all control loads in flight at
+// once):
+//   A: per 64-firing group and branch, a ballot of the feed flags gives the
+//      group's count and last feeder (LDS table);
+//   B: one wavefront per branch scans that table (sum and max over the
+//      groups in firing order, lane shuffles) and writes, per group, the
+//      count and last feeder before it (global group table).
+// With order_out, the batch's firings (one segment) are also grouped by B,
+// largest first, as pairs (firing, B) for the body kernels (one unrolled
+// code path per B: grouping keeps resident workgroups on one or two paths,
+// so their instructions stay cached; the order never changes a result).
+// k_scan_tables: one wavefront per group (all groups in parallel) adds each
+// firing's in-group part (popcount / highest bit of the ballot bits below
+// its lane) and writes off_b, prev_b.
 #include "common.h"
 
 namespace dfh {
 
 constexpr int kScanThreads = 1024;
 constexpr int kScanWaves = kScanThreads / 64;
+constexpr int kScanChunks = 4;                 // kScanChunks * kScanWaves <= 64
 
 __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
-  __shared__ int wsum[kScanWaves][kMaxBranches], wlast[kScanWaves][kMaxBranches];
-  __shared__ int64_t carry_cnt[kMaxBranches], carry_last[kMaxBranches], chunk_cnt[kMaxBranches];
-  __shared__ int chunk_last[kMaxBranches];
+  __shared__ int tot[kScanChunks * kScanWaves][kMaxBranches], lst[kScanChunks * kScanWaves][kMaxBranches];
+  __shared__ int pass_cnt[kMaxBranches], pass_last[kMaxBranches];
+  __shared__ int64_t carry_cnt[kMaxBranches], carry_last[kMaxBranches];
+  __shared__ int hist[kMaxBranches + 1], cursor[kMaxBranches + 1];
   const int seg = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nw = blockDim.x >> 6;
   const int64_t R = a.ctrl_idx ? a.ctrl_idx[0] : 0;
   const int64_t g0 = (int64_t)seg * a.seg_firings;
-  const uint64_t below_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t gps = (a.seg_firings + 63) / 64;     // groups per segment
+  const int E = kScanChunks * nw;                    // groups per pass
   if (tid < a.B_max) carry_cnt[tid] = 0, carry_last[tid] = -1;
-  for (int64_t c0 = 0; c0 < a.seg_firings; c0 += blockDim.x) {
-    const int64_t j = c0 + tid;                       // segment-local firing
-    const bool in = j < a.seg_firings;
-    int Bv = 0;
-    if (in) {
-      Bv = a.ctrl[(R + g0 + j) & a.ctrl_mask];
-      if (Bv < 0 || Bv > a.B_max) {
-        if (a.err) atomicOr(a.err, (int32_t)kErrControl);
-        Bv = 0;
+  if (tid <= kMaxBranches) hist[tid] = 0;
+  const int64_t per_pass = (int64_t)kScanChunks * blockDim.x;
+  for (int64_t p0 = 0; p0 < a.seg_firings; p0 += per_pass) {
+    int Bv[kScanChunks];
+#pragma unroll
+    for (int c = 0; c < kScanChunks; ++c) {
+      const int64_t j = p0 + (int64_t)c * blockDim.x + tid;   // segment-local firing
+      int v = 0;
+      if (j < a.seg_firings) {
+        v = a.ctrl[(R + g0 + j) & a.ctrl_mask];
+        if (v < 0 || v > a.B_max) {
+          if (a.err) atomicOr(a.err, (int32_t)kErrControl);
+          v = 0;
+        }
       }
-      a.B_out[g0 + j] = Bv;
+      Bv[c] = v;
     }
-    // wavefront totals
-    for (int b = 0; b < a.B_max; ++b) {
-      const uint64_t bal = __ballot(in && (a.hist_mode == 1 || Bv > b));
-      if (lane == 0) {
-        wsum[wave][b] = __popcll(bal);
-        wlast[wave][b] = bal ? 64 * wave + 63 - __clzll((long long)bal) : -1;
+    __syncthreads();                            // carries and hist initialised / updated
+#pragma unroll
+    for (int c = 0; c < kScanChunks; ++c) {
+      const int64_t j = p0 + (int64_t)c * blockDim.x + tid;
+      if (j < a.seg_firings) {
+        a.B_out[g0 + j] = Bv[c];
+        if (a.order_out) atomicAdd(&hist[Bv[c]], 1);
+      }
+    }
+    // A: group counts and last feeders (pass-local index); row c*nw + wave
+    // is the 64-firing group starting at p0 + c*blockDim + 64*wave
+#pragma unroll
+    for (int c = 0; c < kScanChunks; ++c) {
+      const bool in = p0 + (int64_t)c * blockDim.x + tid < a.seg_firings;
+      for (int b = 0; b < a.B_max; ++b) {
+        const uint64_t bal = __ballot(in && (a.hist_mode == 1 || Bv[c] > b));
+        if (lane == 0) {
+          tot[c * nw + wave][b] = __popcll(bal);
+          lst[c * nw + wave][b] = bal ? c * (int)blockDim.x + 64 * wave + 63 - __clzll((long long)bal) : -1;
+        }
       }
     }
     __syncthreads();
-    // per branch: totals over the chunk into the carries, and the
-    // per-wavefront totals turned into exclusive prefixes (in place)
+    // B: exclusive scans over the groups, one wavefront per branch
+    if (wave < a.B_max) {
+      const int b = wave;
+      const int row = lane;                       // group c*nw + w
+      const int cnt = row < E ? tot[row][b] : 0;
+      const int lastv = row < E ? lst[row][b] : -1;
+      int cs = cnt, ls = lastv;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int tc = __shfl_up(cs, o), tl = __shfl_up(ls, o);
+        if (lane >= o) cs += tc, ls = max(ls, tl);
+      }
+      int lx = __shfl_up(ls, 1);
+      if (lane == 0) lx = -1;
+      if (row < E) {
+        const int c = row / nw, w = row - c * nw;
+        const int64_t gstart = p0 + (int64_t)c * blockDim.x + 64 * w;   // first firing of the group
+        if (gstart < a.seg_firings) {
+          const int64_t gi = ((int64_t)seg * gps + gstart / 64) * a.B_max + b;
+          const int64_t last = lx >= 0 ? p0 + lx : carry_last[b];
+          a.grp[2 * gi] = carry_cnt[b] + (cs - cnt);
+          a.grp[2 * gi + 1] = last >= 0 ? g0 + last : -1;
+        }
+      }
+      if (lane == 63) pass_cnt[b] = cs, pass_last[b] = ls;
+    }
+    __syncthreads();
     if (tid < a.B_max) {
-      int64_t cnt = 0;
-      int wl = -1;
-      for (int w = 0; w < nw; ++w) {
-        const int s_ = wsum[w][tid], l_ = wlast[w][tid];
-        wsum[w][tid] = (int)cnt;
-        wlast[w][tid] = wl;
-        cnt += s_;
-        wl = max(wl, l_);
-      }
-      chunk_cnt[tid] = cnt;
-      chunk_last[tid] = wl;
+      carry_cnt[tid] += pass_cnt[tid];
+      if (pass_last[tid] >= 0) carry_last[tid] = p0 + pass_last[tid];
     }
-    __syncthreads();
-    for (int b = 0; b < a.B_max; ++b) {
-      const uint64_t bal = __ballot(in && (a.hist_mode == 1 || Bv > b));
-      const uint64_t below = bal & below_mask;
-      const int64_t cnt = carry_cnt[b] + wsum[wave][b] + __popcll(below);
-      const int wl = below ? 64 * wave + 63 - __clzll((long long)below) : wlast[wave][b];
-      const int64_t last = wl >= 0 ? c0 + wl : carry_last[b];
-      if (in) {
-        const int64_t o = (int64_t)b * a.stride + g0 + j;
-        a.prev_out[o] = last >= 0 ? g0 + last : -1;
-        if (a.off_out) a.off_out[o] = a.r * cnt;
-      }
-    }
-    __syncthreads();
-    if (tid < a.B_max) {
-      carry_cnt[tid] += chunk_cnt[tid];
-      if (chunk_last[tid] >= 0) carry_last[tid] = c0 + chunk_last[tid];
-    }
-    __syncthreads();
   }
+  __syncthreads();
   if (tid < a.B_max && a.last_out)
     a.last_out[(int64_t)seg * a.B_max + tid] = carry_last[tid] >= 0 ? g0 + carry_last[tid] : -1;
-}
-
-// Processing order of a batch's firings, grouped by branch count B (largest
-// first), as pairs (firing, B).  The body kernels compile one fully unrolled
-// code path per B; grouping keeps the workgroups resident on a compute unit
-// on one or two paths, so their instructions stay cached.  The order inside
-// a group is irrelevant to the results (every firing's outputs are
-// independent).
-__global__ __launch_bounds__(1024) void k_order_by_b(const int32_t *B, int64_t n, int32_t B_max, int32_t *order) {
-  __shared__ int32_t hist[kMaxBranches + 1], cursor[kMaxBranches + 1];
-  if (threadIdx.x <= kMaxBranches) hist[threadIdx.x] = 0;
-  __syncthreads();
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) atomicAdd(&hist[B[j]], 1);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t run = 0;
-    for (int v = B_max; v >= 0; --v) {
+  if (!a.order_out) return;
+  // group by B, largest first: cursors from the histogram, then scatter
+  if (tid == 0) {
+    int run = 0;
+    for (int v = a.B_max; v >= 0; --v) {
       cursor[v] = run;
       run += hist[v];
     }
   }
   __syncthreads();
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-    const int v = B[j];
+  for (int64_t j = tid; j < a.seg_firings; j += blockDim.x) {
+    const int v = a.B_out[g0 + j];
     const int k = atomicAdd(&cursor[v], 1);
-    order[2 * k] = (int32_t)j;
-    order[2 * k + 1] = v;
+    a.order_out[2 * k] = (int32_t)j;
+    a.order_out[2 * k + 1] = v;
   }
 }
 
-hipError_t launch_order_by_b(const int32_t *B, int64_t n, int32_t B_max, int32_t *order, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_order_by_b, dim3(1), dim3(1024), 0, s, B, n, B_max, order);
-  return hipGetLastError();
+// One wavefront per 64-firing group: off_b and prev_b of its firings.
+__global__ __launch_bounds__(256) void k_scan_tables(ScanArgs a, int64_t n_groups) {
+  const int64_t G = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (G >= n_groups) return;                         // uniform per wavefront
+  const int lane = threadIdx.x & 63;
+  const int64_t gps = (a.seg_firings + 63) / 64;
+  const int64_t seg = G / gps, lg = G - seg * gps;
+  const int64_t g0 = seg * a.seg_firings;
+  const int64_t j = lg * 64 + lane;                  // segment-local firing
+  const bool in = j < a.seg_firings;
+  const int Bv = in ? a.B_out[g0 + j] : 0;
+  const uint64_t below_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int b = 0; b < a.B_max; ++b) {
+    const uint64_t bal = __ballot(in && (a.hist_mode == 1 || Bv > b));
+    const uint64_t below = bal & below_mask;
+    const int64_t gi = G * a.B_max + b;
+    const int64_t cnt = a.grp[2 * gi] + __popcll(below);
+    const int64_t last = below ? g0 + lg * 64 + 63 - __clzll((long long)below) : a.grp[2 * gi + 1];
+    if (in) {
+      const int64_t o = (int64_t)b * a.stride + g0 + j;
+      a.prev_out[o] = last;
+      if (a.off_out) a.off_out[o] = a.r * cnt;
+    }
+  }
 }
+
+int64_t scan_groups(int64_t n_segs, int64_t seg_firings) { return n_segs * ((seg_firings + 63) / 64); }
 
 int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes) {
   struct Entry {
@@ -151,11 +191,18 @@ int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes) {
 
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s) {
   if (a.n_segs <= 0 || a.seg_firings <= 0) return hipSuccess;
-  if (a.B_max < 1 || a.B_max > kMaxBranches) return hipErrorInvalidValue;
-  // one firing per thread; small segments take fewer wavefronts
-  int64_t waves = (a.seg_firings + 63) / 64;
+  if (a.B_max < 1 || a.B_max > kMaxBranches || !a.grp) return hipErrorInvalidValue;
+  if (a.order_out && a.n_segs != 1) return hipErrorInvalidValue;
+  // small segments take fewer wavefronts (kScanChunks firings per thread);
+  // the group scan needs a wavefront per branch
+  int64_t waves = (a.seg_firings + 64 * kScanChunks - 1) / (64 * kScanChunks);
   if (waves > kScanWaves) waves = kScanWaves;
+  if (waves < a.B_max) waves = a.B_max;
   hipLaunchKernelGGL(k_scan, dim3(a.n_segs), dim3(64 * (unsigned)waves), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t ng = scan_groups(a.n_segs, a.seg_firings);
+  hipLaunchKernelGGL(k_scan_tables, dim3((unsigned)((ng + 3) / 4)), dim3(256), 0, s, a, ng);
   return hipGetLastError();
 }
 

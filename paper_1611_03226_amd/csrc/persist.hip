@@ -12,6 +12,7 @@
 //   commit:   per-instance channel indices and carried branch histories
 // All counts live in device memory, so the chain can be captured once in a
 // HIP graph and replayed.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -71,28 +72,39 @@ struct PersArgs {
   int64_t cap;
   PItem *items;           // [items_cap]
   float2 *corr_all;       // [cap][M-1] head corrections
+  int64_t *head_base;     // [n_inst + 1] first head-pass wavefront of each instance
+  int32_t *head_inst;     // [heads] instance of each head-pass wavefront (4 firings each)
   int32_t M;
   int32_t *err;
   int32_t tile;
 };
 
-// One wavefront: exclusive scan of the firing counts (firing bases).
+// One wavefront: exclusive scans of the firing counts (firing bases) and of
+// the head-pass wavefronts (four firings each).
 __global__ __launch_bounds__(64) void k_pers_prep(PersArgs a) {
   const int lane = threadIdx.x;
-  int64_t cf = 0;
+  int64_t cf = 0, ch = 0;
   for (int c = 0; c < a.n_inst; c += 64) {
     const int i = c + lane;
     const int64_t nf = i < a.n_inst ? a.n_fire[i] : 0;
-    int64_t sf = nf;                               // inclusive wave scan
+    const int64_t nh = (nf + 3) / 4;
+    int64_t sf = nf, sh = nh;                      // inclusive wave scans
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-      const int64_t uf = __shfl_up(sf, d);
-      if (lane >= d) sf += uf;
+      const int64_t uf = __shfl_up(sf, d), uh = __shfl_up(sh, d);
+      if (lane >= d) sf += uf, sh += uh;
     }
-    if (i < a.n_inst) a.fire_base[i] = cf + sf - nf;
+    if (i < a.n_inst) {
+      a.fire_base[i] = cf + sf - nf;
+      a.head_base[i] = ch + sh - nh;
+    }
     cf += __shfl(sf, 63);
+    ch += __shfl(sh, 63);
   }
-  if (lane == 0) a.fire_base[a.n_inst] = cf;
+  if (lane == 0) {
+    a.fire_base[a.n_inst] = cf;
+    a.head_base[a.n_inst] = ch;
+  }
 }
 
 // Processing order of the instances, grouped by the branch count of their
@@ -180,6 +192,8 @@ __global__ __launch_bounds__(1024) void k_pers_scan(PersArgs a) {
     if (bal) lastw = c + 63 - __clzll((long long)bal);
   }
   if (lane == 0) a.last_all[(int64_t)i * a.Bg + b] = lastw;
+  if (b == 0)
+    for (int64_t k = lane; k < (n + 3) / 4; k += 64) a.head_inst[a.head_base[i] + k] = i;
 }
 
 // Work-item descriptors: item k (processing order) -> the last ordered
@@ -241,32 +255,29 @@ struct ItemSrc {
   }
 };
 
-// Head corrections of all instances' firings: wavefront w takes global
-// firings w, w + total wavefronts, ...; the instance of a firing is the last
-// one whose firing base is <= it.
+// Head corrections of all instances' firings: one wavefront per four
+// consecutive firings of one instance (rows), from the head-pass map.
 template <int M>
-__global__ __launch_bounds__(256) void k_pers_heads(PersArgs a) {
-  const int64_t total = a.fire_base[a.n_inst];
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t gf = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); gf < total;
-       gf += nwaves) {
-    int lo = 0, hi = a.n_inst - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (a.fire_base[mid] <= gf) lo = mid; else hi = mid - 1;
-    }
-    const InstDesc &d = a.inst[lo];
-    const int B = a.B_all[gf];
-    if (B <= 0) continue;
-    const int64_t Rx = d.x_idx[0];
-    head_correction<M>(
-        B, as_const(d.h), [&](int b) { return a.prev_all[(int64_t)b * a.cap + gf]; },
-        [&](int b, int64_t pf, int i) {
-          if (pf >= 0) return d.x[(Rx + pf * d.r + d.r - (M - 1) + i) & d.x_mask];
-          return d.hist[b * (M - 1) + i];
-        },
-        a.corr_all + gf * (M - 1));
-  }
+__global__ __launch_bounds__(256) void k_pers_heads(PersArgs a, int64_t n_heads) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= n_heads) return;                          // uniform per wavefront
+  const int i = as_const(a.head_inst)[w];
+  const auto *inst = as_const(a.inst) + i;
+  const int64_t j0 = 4 * (w - as_const(a.head_base)[i]);
+  const int64_t nf = as_const(a.n_fire)[i];
+  const int64_t f0 = as_const(a.fire_base)[i] + j0;   // global firing of row 0
+  const float2 *x = inst->x;
+  const float2 *hist = inst->hist;
+  const int64_t x_mask = inst->x_mask, r = inst->r;
+  const int64_t Rx = as_const(inst->x_idx)[0];
+  head_correction<M, 4>(
+      as_const(inst->h), [&](int row) { return j0 + row < nf ? a.B_all[f0 + row] : 0; },
+      [&](int row, int b) { return a.prev_all[(int64_t)b * a.cap + f0 + row]; },
+      [&](int, int b, int64_t pf, int q) {
+        if (pf >= 0) return x[(Rx + pf * r + r - (M - 1) + q) & x_mask];
+        return hist[b * (M - 1) + q];
+      },
+      [&](int row) { return a.corr_all + (f0 + row) * (M - 1); });
 }
 
 // Persistent body: a grid-stride walk over the work items (run_tiles).
@@ -311,7 +322,9 @@ struct Persistent {
   float2 *corr_all = nullptr;
   int32_t *B_all = nullptr, *inst_order = nullptr;
   PItem *items = nullptr;
-  int64_t cap = 0, items_cap = 0;
+  int64_t *head_base = nullptr;
+  int32_t *head_inst = nullptr;
+  int64_t cap = 0, items_cap = 0, heads_cap = 0, n_heads = 0;
   int tile = 0, K = 0, bpc = 0, ncu = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -338,6 +351,8 @@ void destroy_persistent(df_graph *g) {
   (void)hipFree(p->last_all);
   (void)hipFree(p->B_all);
   (void)hipFree(p->items);
+  (void)hipFree(p->head_base);
+  (void)hipFree(p->head_inst);
   (void)hipFree(p->inst_order);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
@@ -345,9 +360,12 @@ void destroy_persistent(df_graph *g) {
 }
 
 template <int M, int K, int BC>
-static hipError_t launch_pers_body(const PersArgs &a, int threads, int blocks, hipStream_t s) {
+static hipError_t launch_pers_body(const PersArgs &a, int threads, int blocks, hipStream_t s, const KTiming *t) {
   const size_t lds = (size_t)(lds_window(a.tile + M - 1) + lds_corr(M)) * sizeof(float2);
-  hipLaunchKernelGGL((k_pers_body<M, K, BC>), dim3(blocks), dim3(threads), lds, s, a);
+  if (t)
+    hipExtLaunchKernelGGL((k_pers_body<M, K, BC>), dim3(blocks), dim3(threads), lds, s, t->start, t->stop, 0, a);
+  else
+    hipLaunchKernelGGL((k_pers_body<M, K, BC>), dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -357,27 +375,32 @@ static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pers_scan, dim3(a.n_inst), dim3(64 * a.Bg), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (p->M == 16) hipLaunchKernelGGL(k_pers_heads<16>, dim3(4 * p->ncu), dim3(256), 0, s, a);
-  else if (p->M == 8) hipLaunchKernelGGL(k_pers_heads<8>, dim3(4 * p->ncu), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_pers_heads<4>, dim3(4 * p->ncu), dim3(256), 0, s, a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int64_t nh = p->n_heads;
+  if (nh > 0) {
+    const dim3 hg((unsigned)((nh + 3) / 4));
+    if (p->M == 16) hipLaunchKernelGGL(k_pers_heads<16>, hg, dim3(256), 0, s, a, nh);
+    else if (p->M == 8) hipLaunchKernelGGL(k_pers_heads<8>, hg, dim3(256), 0, s, a, nh);
+    else hipLaunchKernelGGL(k_pers_heads<4>, hg, dim3(256), 0, s, a, nh);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_pers_order, dim3(1), dim3(1024), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_pers_items, dim3(4 * p->ncu), dim3(256), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int threads = p->tile / p->K;
   const int blocks = p->bpc * p->ncu;
-  if (prof_g && (e = prof_begin(prof_g)) != hipSuccess) return e;
+  KTiming kt;
+  if (prof_g && (e = prof_pair(prof_g, &kt)) != hipSuccess) return e;
+  const KTiming *tp = (prof_g && prof_g->prof) ? &kt : nullptr;
   const bool small = a.Bg <= 10;
 #define DF_PERS(m, k)                                                                              \
   if (p->M == m && p->K == k)                                                                      \
-    e = small ? launch_pers_body<m, k, 10>(a, threads, blocks, s) : launch_pers_body<m, k, 16>(a, threads, blocks, s); \
+    e = small ? launch_pers_body<m, k, 10>(a, threads, blocks, s, tp) : launch_pers_body<m, k, 16>(a, threads, blocks, s, tp); \
   else
   DF_PERS(16, 4) DF_PERS(16, 8) DF_PERS(8, 4) DF_PERS(8, 8) DF_PERS(4, 4) DF_PERS(4, 8)
   return hipErrorInvalidValue;
 #undef DF_PERS
   if (e != hipSuccess) return e;
-  if (prof_g && (e = prof_end(prof_g)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_pers_commit, dim3(a.n_inst), dim3(256), 0, s, a, p->M);
   return hipGetLastError();
 }
@@ -454,6 +477,7 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
     HIPCHK(g, hipMalloc(&p->tile_base, sizeof(int64_t) * (n_actors + 1)));
     HIPCHK(g, hipMalloc(&p->last_all, sizeof(int64_t) * n_actors * Bg));
     HIPCHK(g, hipMalloc(&p->inst_order, sizeof(int32_t) * n_actors));
+    HIPCHK(g, hipMalloc(&p->head_base, sizeof(int64_t) * (n_actors + 1)));
   }
   // Tile configuration: a multiple of 64*K outputs, no larger than needed.
   const int K = g->outputs_per_thread == 8 ? 8 : 4;
@@ -494,6 +518,18 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
     p->items_cap = cap;
     rebuild = true;
   }
+  int64_t n_heads = 0;
+  for (int i = 0; i < n_actors; ++i) n_heads += (n_firings[i] + 3) / 4;
+  if (n_heads > p->heads_cap) {
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    int64_t cap = 1024;
+    while (cap < n_heads) cap <<= 1;
+    (void)hipFree(p->head_inst);
+    p->head_inst = nullptr;
+    HIPCHK(g, hipMalloc(&p->head_inst, sizeof(int32_t) * cap));
+    p->heads_cap = cap;
+    rebuild = true;
+  }
   if (rebuild) {
     HIPCHK(g, hipStreamSynchronize(g->stream));
     drop_graph(p);
@@ -528,10 +564,14 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
     p->n_host.clear();
   }
   if (p->n_host.size() != (size_t)n_actors || !std::equal(p->n_host.begin(), p->n_host.end(), n_firings)) {
-    // Counts changed: upload synchronously (the batch shape is normally stable).
+    // Counts changed: upload synchronously (the batch shape is normally
+    // stable); the head pass grid depends on the total, so a captured graph
+    // is rebuilt.
     HIPCHK(g, hipStreamSynchronize(g->stream));
+    drop_graph(p);
     HIPCHK(g, hipMemcpy(p->n_dev, n_firings, sizeof(int64_t) * n_actors, hipMemcpyHostToDevice));
     p->n_host.assign(n_firings, n_firings + n_actors);
+    p->n_heads = n_heads;
   }
   PersArgs pa{};
   pa.inst = p->inst;
@@ -546,6 +586,8 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
   pa.cap = p->cap;
   pa.items = p->items;
   pa.corr_all = p->corr_all;
+  pa.head_base = p->head_base;
+  pa.head_inst = p->head_inst;
   pa.M = p->M;
   pa.inst_order = p->inst_order;
   pa.err = g->err_dev;

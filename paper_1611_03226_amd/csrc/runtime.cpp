@@ -118,6 +118,7 @@ static void free_actor(Actor &a) {
   (void)hipFree(a.B);
   (void)hipFree(a.order);
   (void)hipFree(a.corr);
+  (void)hipFree(a.grp);
   (void)hipFree(a.prev);
   (void)hipFree(a.off);
   (void)hipFree(a.last);
@@ -452,7 +453,8 @@ df_status dfh::ensure_dpd_scratch(df_graph *g, Actor &a, int64_t n) {
       grow((void **)&a.order, 2 * sizeof(int32_t) * cap) != hipSuccess ||
       grow((void **)&a.prev, sizeof(int64_t) * bm * cap) != hipSuccess ||
       grow((void **)&a.off, sizeof(int64_t) * bm * cap) != hipSuccess ||
-      grow((void **)&a.corr, sizeof(float2) * std::max(a.dp.n_taps - 1, 1) * cap) != hipSuccess)
+      grow((void **)&a.corr, sizeof(float2) * std::max(a.dp.n_taps - 1, 1) * cap) != hipSuccess ||
+      grow((void **)&a.grp, 2 * sizeof(int64_t) * bm * scan_groups(1, cap)) != hipSuccess)
     return fail(g, DF_ENOMEM, "scratch allocation failed");
   a.scratch_n = cap;
   return DF_OK;
@@ -496,9 +498,10 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   sa.stride = a.scratch_n;
   sa.r = r;
   sa.err = g->err_dev;
-  HIPCHK(g, launch_scan(sa, g->stream));
   const bool ordered = n > 64;                       // grouping pays off only for many workgroups
-  if (ordered) HIPCHK(g, launch_order_by_b(a.B, n, bm, a.order, g->stream));
+  sa.order_out = ordered ? a.order : nullptr;
+  sa.grp = a.grp;
+  HIPCHK(g, launch_scan(sa, g->stream));
 
   DpdArgs da{};
   da.x = (const float2 *)fx.ring;
@@ -520,9 +523,9 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   da.M = M;
   da.corr = a.corr;
   HIPCHK(g, launch_dpd_heads(da, g->stream));
-  HIPCHK(g, prof_begin(g));
-  HIPCHK(g, launch_dpd_body(da, g->stream, g->tile, g->outputs_per_thread));
-  HIPCHK(g, prof_end(g));
+  KTiming kt;
+  HIPCHK(g, prof_pair(g, &kt));
+  HIPCHK(g, launch_dpd_body(da, g->stream, g->tile, g->outputs_per_thread, g->prof ? &kt : nullptr));
 
   DpdCommitArgs ca{};
   ca.x = (const float2 *)fx.ring;
@@ -703,7 +706,18 @@ static hipError_t take_event(df_graph *g, hipEvent_t *ev) {
     g->prof_pool.pop_back();
     return hipSuccess;
   }
-  return hipEventCreate(ev);
+  // timing-only events: no system-scope fence on record (df_profile_read
+  // synchronizes the stream before reading them)
+  return hipEventCreateWithFlags(ev, hipEventDisableSystemFence);
+}
+
+hipError_t dfh::prof_pair(df_graph *g, KTiming *t) {
+  if (!g->prof) return hipSuccess;
+  hipError_t e = take_event(g, &t->start);
+  if (e == hipSuccess) e = take_event(g, &t->stop);
+  if (e != hipSuccess) return e;
+  g->prof_pending.push_back({t->start, t->stop});
+  return hipSuccess;
 }
 
 hipError_t dfh::prof_begin(df_graph *g) {

@@ -43,6 +43,7 @@ struct Actor {
   int32_t *B = nullptr;      // [scratch_n]
   int32_t *order = nullptr;  // [scratch_n][2] (firing, B) grouped by B
   float2 *corr = nullptr;    // [scratch_n][M-1] head corrections
+  int64_t *grp = nullptr;    // scan group table
   int64_t *prev = nullptr;   // [B_max][scratch_n]
   int64_t *off = nullptr;    // [B_max][scratch_n]
   int64_t *last = nullptr;   // [B_max]
@@ -88,5 +89,6 @@ df_status dpd_enqueue(df_graph *g, Actor &a, int64_t n);
 void destroy_persistent(df_graph *g);
 // Event pair around body kernels when profiling is enabled (no-op otherwise).
 hipError_t prof_begin(df_graph *g);
+hipError_t prof_pair(df_graph *g, KTiming *t);   // events for one timed launch (none if profiling is off)
 hipError_t prof_end(df_graph *g);
 }  // namespace dfh

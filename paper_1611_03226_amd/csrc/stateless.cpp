@@ -28,6 +28,7 @@ df_status check_dpd_shape(int64_t S, int64_t len, int64_t r, int32_t B_max, int3
 struct Tables {
   int32_t *B = nullptr;
   int64_t *prev = nullptr;
+  int64_t *grp = nullptr;
   int64_t n = 0;
 };
 
@@ -37,6 +38,8 @@ hipError_t make_tables(const int32_t *ctrl, int64_t S, int64_t nf, int64_t r, in
   hipError_t e = hipMallocAsync((void **)&t->B, sizeof(int32_t) * std::max<int64_t>(t->n, 1), s);
   if (e != hipSuccess) return e;
   e = hipMallocAsync((void **)&t->prev, sizeof(int64_t) * std::max<int64_t>(t->n, 1) * B_max, s);
+  if (e != hipSuccess) return e;
+  e = hipMallocAsync((void **)&t->grp, 2 * sizeof(int64_t) * B_max * std::max<int64_t>(scan_groups(S, nf), 1), s);
   if (e != hipSuccess) return e;
   ScanArgs sa{};
   sa.ctrl = ctrl;
@@ -48,6 +51,7 @@ hipError_t make_tables(const int32_t *ctrl, int64_t S, int64_t nf, int64_t r, in
   sa.hist_mode = hist;
   sa.B_out = t->B;
   sa.prev_out = t->prev;
+  sa.grp = t->grp;
   sa.stride = t->n;
   sa.r = r;
   return launch_scan(sa, s);
@@ -56,6 +60,7 @@ hipError_t make_tables(const int32_t *ctrl, int64_t S, int64_t nf, int64_t r, in
 void free_tables(Tables *t, hipStream_t s) {
   if (t->B) (void)hipFreeAsync(t->B, s);
   if (t->prev) (void)hipFreeAsync(t->prev, s);
+  if (t->grp) (void)hipFreeAsync(t->grp, s);
 }
 
 int adj_chunk(int64_t r) { return (int)std::min<int64_t>(1024, r); }
