@@ -25,6 +25,23 @@ enum : int32_t { kErrControl = 1, kErrIndex = 2 };
 // (-1: carried state `hist` [b][M-1], nullptr history = zeros).  With
 // prev == nullptr the history firing is g-1 inside its segment of
 // seg_firings firings and -1 at a segment start.
+// Batch commit of a single actor: advance the channel indices by the
+// batch's token counts and carry each branch's history (the last M-1 input
+// samples of its last feeding firing).
+struct DpdCommitArgs {
+  const float2 *x;
+  int64_t *x_idx;
+  int64_t x_mask;
+  int64_t *ctrl_idx;
+  int64_t *y_idx;
+  float2 *hist;           // [B_max][M-1]
+  const int64_t *last;    // [B_max]
+  int64_t n_firings;
+  int64_t r;
+  int32_t B_max;
+  int32_t M;
+};
+
 struct DpdArgs {
   const float2 *x;
   const int64_t *x_idx;   // device [read, write] or nullptr (position 0)
@@ -47,6 +64,8 @@ struct DpdArgs {
   int32_t tiles_per_firing;
   const int32_t *order;   // processing order, pairs (firing, B) grouped by B, or nullptr
   float2 *corr;           // [n_firings][M-1] head corrections (tiled kernels)
+  int32_t *ticket;        // tiled kernel: the last workgroup to finish runs `commit` (nullptr: none)
+  DpdCommitArgs commit;
 };
 
 // Control intake + offset scan over segments of firings (one workgroup per
@@ -70,19 +89,6 @@ struct ScanArgs {
   int32_t *err;           // sticky error word (may be nullptr)
 };
 
-struct DpdCommitArgs {
-  const float2 *x;
-  int64_t *x_idx;
-  int64_t x_mask;
-  int64_t *ctrl_idx;
-  int64_t *y_idx;
-  float2 *hist;           // [B_max][M-1]
-  const int64_t *last;    // [B_max]
-  int64_t n_firings;
-  int64_t r;
-  int32_t B_max;
-  int32_t M;
-};
 
 // ---------------------------------------------------------------- motion
 struct MotionArgs {

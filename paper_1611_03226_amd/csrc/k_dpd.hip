@@ -60,6 +60,27 @@ __global__ __launch_bounds__(256) void k_dpd_generic(DpdArgs a) {
   a.y[(Wy + t) & a.y_mask] = make_float2(ar, ai);
 }
 
+// ------------------------------------------------------------------ commit
+// Advance the channel indices by the batch's token counts and carry each
+// branch's history: the last M-1 input samples of its last feeding firing.
+// One workgroup (a kernel of its own, or the body's last workgroup).
+__device__ __forceinline__ void dpd_commit_block(const DpdCommitArgs &a) {
+  const int64_t Rx = a.x_idx[0];
+  __syncthreads();
+  const int L = a.M - 1;
+  for (int t = threadIdx.x; t < a.B_max * L; t += blockDim.x) {
+    const int b = t / L, k = t - b * L;
+    const int64_t lf = a.last[b];
+    if (lf >= 0) a.hist[b * L + k] = a.x[(Rx + lf * a.r + a.r - L + k) & a.x_mask];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.x_idx[0] = Rx + a.n_firings * a.r;
+    a.ctrl_idx[0] += a.n_firings;
+    a.y_idx[1] += a.n_firings * a.r;
+  }
+}
+
 // ------------------------------------------------------------------ heads
 // Head corrections of every firing with B > 0 (four firings per
 // wavefront); corr[g][q], q < M-1.  Read by the tiled body.
@@ -122,6 +143,21 @@ __global__ __launch_bounds__(256) void k_dpd_tiled(DpdArgs a) {
   float2 *sc = lds, *sx = sc + lds_corr(M);
   SingleSrc src{a, a.x_idx ? as_const(a.x_idx)[0] : 0, a.y_idx ? as_const(a.y_idx)[1] : 0};
   run_tiles<M, K, BC>(sx, sc, a.n_firings * a.tiles_per_firing, src);
+  if (!a.ticket) return;
+  // The last workgroup to finish commits the batch: every other workgroup
+  // has read the channel indices by then (it read them before finishing),
+  // and the commit reads nothing another workgroup wrote, so a relaxed
+  // counter suffices (a device-scope fence here would write back the L2).
+  __shared__ int last_block;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last_block = __hip_atomic_fetch_add(a.ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                 (int)gridDim.x - 1;
+  __syncthreads();
+  if (last_block) {
+    dpd_commit_block(a.commit);
+    if (threadIdx.x == 0) *a.ticket = 0;              // ready for the next batch
+  }
 }
 
 template <int M, int K, int BC>
@@ -184,25 +220,7 @@ hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int output
   return hipErrorInvalidValue;
 }
 
-// ------------------------------------------------------------------ commit
-// Advance the channel indices by the batch's token counts and carry each
-// branch's history: the last M-1 input samples of its last feeding firing.
-__global__ __launch_bounds__(1024) void k_dpd_commit(DpdCommitArgs a) {
-  const int64_t Rx = a.x_idx[0];
-  __syncthreads();
-  const int L = a.M - 1;
-  for (int t = threadIdx.x; t < a.B_max * L; t += blockDim.x) {
-    const int b = t / L, k = t - b * L;
-    const int64_t lf = a.last[b];
-    if (lf >= 0) a.hist[b * L + k] = a.x[(Rx + lf * a.r + a.r - L + k) & a.x_mask];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    a.x_idx[0] = Rx + a.n_firings * a.r;
-    a.ctrl_idx[0] += a.n_firings;
-    a.y_idx[1] += a.n_firings * a.r;
-  }
-}
+__global__ __launch_bounds__(1024) void k_dpd_commit(DpdCommitArgs a) { dpd_commit_block(a); }
 
 hipError_t launch_dpd_commit(const DpdCommitArgs &a, hipStream_t s) {
   int threads = a.B_max * (a.M - 1);

@@ -47,8 +47,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
   if (tid < a.B_max) carry_cnt[tid] = 0, carry_last[tid] = -1;
   if (tid <= kMaxBranches) hist[tid] = 0;
   const int64_t per_pass = (int64_t)kScanChunks * blockDim.x;
+  int Bv[kScanChunks];
   for (int64_t p0 = 0; p0 < a.seg_firings; p0 += per_pass) {
-    int Bv[kScanChunks];
 #pragma unroll
     for (int c = 0; c < kScanChunks; ++c) {
       const int64_t j = p0 + (int64_t)c * blockDim.x + tid;   // segment-local firing
@@ -130,6 +130,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
     }
   }
   __syncthreads();
+  if (a.seg_firings <= per_pass) {                   // one pass: the tokens are still in registers
+#pragma unroll
+    for (int c = 0; c < kScanChunks; ++c) {
+      const int64_t j = (int64_t)c * blockDim.x + tid;
+      if (j < a.seg_firings) {
+        const int k = atomicAdd(&cursor[Bv[c]], 1);
+        a.order_out[2 * k] = (int32_t)j;
+        a.order_out[2 * k + 1] = Bv[c];
+      }
+    }
+    return;
+  }
   for (int64_t j = tid; j < a.seg_firings; j += blockDim.x) {
     const int v = a.B_out[g0 + j];
     const int k = atomicAdd(&cursor[v], 1);

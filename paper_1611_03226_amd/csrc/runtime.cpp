@@ -119,6 +119,7 @@ static void free_actor(Actor &a) {
   (void)hipFree(a.order);
   (void)hipFree(a.corr);
   (void)hipFree(a.grp);
+  (void)hipFree(a.ticket);
   (void)hipFree(a.prev);
   (void)hipFree(a.off);
   (void)hipFree(a.last);
@@ -257,12 +258,14 @@ extern "C" df_status df_actor_create(df_graph *g, df_actor_kind kind, const void
     const size_t hb = sizeof(float2) * p.n_branches_max * p.n_taps;
     const size_t sb = sizeof(float2) * p.n_branches_max * std::max(p.n_taps - 1, 1);
     if ((e = hipMalloc(&a.h, hb)) != hipSuccess || (e = hipMalloc(&a.hist, sb)) != hipSuccess ||
-        (e = hipMalloc(&a.last, sizeof(int64_t) * p.n_branches_max)) != hipSuccess) {
+        (e = hipMalloc(&a.last, sizeof(int64_t) * p.n_branches_max)) != hipSuccess ||
+        (e = hipMalloc(&a.ticket, sizeof(int32_t))) != hipSuccess) {
       free_actor(a);
       return fail(g, DF_ENOMEM, "actor allocation failed");
     }
     e = hipMemcpy(a.h, p.coeffs, hb, p.coeffs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(a.hist, 0, sb);
+    if (e == hipSuccess) e = hipMemset(a.ticket, 0, sizeof(int32_t));
     if (e != hipSuccess) {
       free_actor(a);
       return fail_hip(g, e, "actor init");
@@ -523,10 +526,6 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   da.M = M;
   da.corr = a.corr;
   HIPCHK(g, launch_dpd_heads(da, g->stream));
-  KTiming kt;
-  HIPCHK(g, prof_pair(g, &kt));
-  HIPCHK(g, launch_dpd_body(da, g->stream, g->tile, g->outputs_per_thread, g->prof ? &kt : nullptr));
-
   DpdCommitArgs ca{};
   ca.x = (const float2 *)fx.ring;
   ca.x_idx = fx.idx;
@@ -539,7 +538,17 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   ca.r = r;
   ca.B_max = bm;
   ca.M = M;
-  HIPCHK(g, launch_dpd_commit(ca, g->stream));
+  // the tiled body's last workgroup commits the batch; the generic body
+  // leaves it to a kernel of its own
+  const bool fused = dpd_tiled_shape(M);
+  if (fused) {
+    da.ticket = a.ticket;
+    da.commit = ca;
+  }
+  KTiming kt;
+  HIPCHK(g, prof_pair(g, &kt));
+  HIPCHK(g, launch_dpd_body(da, g->stream, g->tile, g->outputs_per_thread, g->prof ? &kt : nullptr));
+  if (!fused) HIPCHK(g, launch_dpd_commit(ca, g->stream));
 
   fc.read_h += n;
   fx.read_h += n * r;

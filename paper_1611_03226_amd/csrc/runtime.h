@@ -47,6 +47,7 @@ struct Actor {
   int64_t *prev = nullptr;   // [B_max][scratch_n]
   int64_t *off = nullptr;    // [B_max][scratch_n]
   int64_t *last = nullptr;   // [B_max]
+  int32_t *ticket = nullptr; // finished-workgroup counter of the body (commit by the last one)
   // motion
   df_motion_params mp{};
   uint8_t *state = nullptr;  // previous frame (self-delay form)
