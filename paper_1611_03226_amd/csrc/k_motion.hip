@@ -60,6 +60,16 @@ __device__ __forceinline__ void load_word(const uint8_t *frame, int y, int x0, i
 
 typedef short i16x2 __attribute__((ext_vector_type(2)));
 
+// Word of the neighbouring lane, one DPP move each (no LDS round trip):
+// lane l receives lane l-1 (lane 0: 0) / lane l+1 (lane 63: 0).  Lanes 0
+// and 63 are halo words whose results are discarded.
+__device__ __forceinline__ uint32_t from_lower_lane(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, true);   // wave_shr:1
+}
+__device__ __forceinline__ uint32_t from_upper_lane(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true);   // wave_shl:1
+}
+
 // Bit i of the result: |cur_i - prev_i| > thr for the 32 pixels of a word.
 // Even and odd bytes are spread into 16-bit lanes (byte permutes); with
 // d = cur - prev, the pixel is unchanged iff d - (thr+1) and -(thr+1) - d are
@@ -88,15 +98,13 @@ __device__ __forceinline__ uint32_t thresh_bits(const uint32_t (&c)[8], const ui
 // frame f and buf[f+1] its current frame (self-delay form: frames j0-1 ..
 // j0+F-1 of the input channel, the first from the state for j0 = 0; the
 // two-channel form has F = 1: buf[0] from the PREV channel, buf[1] from CUR).
+// Every load is unconditional: callers clamp y into the frame and point the
+// frames past the batch at its last frame (those results are masked).
 template <int F, bool FAST>
-__device__ __forceinline__ void load_rows(const uint8_t *const (&fr)[F + 1], int nfr, int y, int x0, int W,
-                                          bool active, uint32_t (&buf)[F + 1][8]) {
-  if (!active) return;
+__device__ __forceinline__ void load_rows(const uint8_t *const (&fr)[F + 1], int y, int x0, int W,
+                                          uint32_t (&buf)[F + 1][8]) {
 #pragma unroll
-  for (int f = 0; f <= F; ++f) {
-    if (f > nfr) break;
-    load_word(fr[f], y, x0, W, FAST, buf[f]);
-  }
+  for (int f = 0; f <= F; ++f) load_word(fr[f], y, x0, W, FAST, buf[f]);
 }
 
 template <int F, bool FAST>
@@ -128,8 +136,8 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
       if (a.prev) {
         fr[f] = f == 0 ? a.prev + ((a.prev_idx[0] + j0) & a.prev_mask) * wh : a.cur + ((Rc + j0) & a.cur_mask) * wh;
       } else {
-        const int64_t j = j0 + f - 1;
-        fr[f] = j < 0 ? a.state : a.cur + ((Rc + min(j, a.n - 1)) & a.cur_mask) * wh;
+        const int64_t j = j0 + min(f, nfr) - 1;            // past the batch: its last frame
+        fr[f] = j < 0 ? a.state : a.cur + ((Rc + j) & a.cur_mask) * wh;
       }
     }
   }
@@ -148,10 +156,10 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
       const uint32_t th = thresh_bits(buf[f + 1], buf[f], t1, nt1);
       const uint32_t m0 = in ? (th | ~valid) : 0xFFFFFFFFu; // outside the frame: set
       // horizontal AND with the neighbour words' edge bits
-      const uint32_t lw = __shfl_up(m0, 1), rw = __shfl_down(m0, 1);
+      const uint32_t lw = from_lower_lane(m0), rw = from_upper_lane(m0);
       const uint32_t hm = m0 & ((m0 << 1) | (lw >> 31)) & ((m0 >> 1) | (rw << 31));
       const uint32_t e = e_in ? (hm2[f] & hm1[f] & hm & valid) : 0u;   // e(y-1); outside: clear
-      const uint32_t le = __shfl_up(e, 1), re = __shfl_down(e, 1);
+      const uint32_t le = from_lower_lane(e), re = from_upper_lane(e);
       const uint32_t he = e | ((e << 1) | (le >> 31)) | ((e >> 1) | (re << 31));
       const uint32_t o = (he3[f] | he2[f] | he) & valid;    // o(y-2)
       const int yo = y - 2;
@@ -174,9 +182,7 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
 #pragma unroll
     for (int k = 0; k < 8; ++k) A[f][k] = Bf[f][k] = 0;
   const int ylast = y1 + 1;
-  auto rowload = [&](int y, uint32_t (&buf)[F + 1][8]) {
-    load_rows<F, FAST>(fr, nfr, y, x0, W, word_in && y >= 0 && y < H, buf);
-  };
+  auto rowload = [&](int y, uint32_t (&buf)[F + 1][8]) { load_rows<F, FAST>(fr, min(max(y, 0), H - 1), x0, W, buf); };
   rowload(y0 - 2, A);
   for (int y = y0 - 2; y <= ylast; y += 2) {
     if (y + 1 <= ylast) rowload(y + 1, Bf);
