@@ -31,6 +31,22 @@ __device__ __forceinline__ int64_t adj_prev(const AdjArgs &a, int b, int64_t g) 
 // chunk's window.  For its sample a lane forms p^b once and accumulates
 // G[s+m] conj(x_s) p^b into 4 taps x BM branches of independent registers;
 // the wavefront then reduces over lanes (fixed shuffle order).
+// One reduce-scatter step of the lane butterfly: lanes with bit 2*HALF set
+// keep the upper HALF values, the others the lower HALF, each adding the
+// partner's copy of the kept half.
+template <int HALF>
+__device__ __forceinline__ void butterfly_step(float (&v)[32], int lane) {
+  constexpr int off = 2 * HALF;
+  const bool upper = (lane & off) != 0;
+#pragma unroll
+  for (int i = 0; i < HALF; ++i) {
+    const float send = upper ? v[i] : v[i + HALF];
+    const float keep = upper ? v[i + HALF] : v[i];
+    v[i] = keep + __shfl_xor(send, off);
+  }
+  if constexpr (HALF > 1) butterfly_step<HALF / 2>(v, lane);
+}
+
 template <int BM>
 __global__ __launch_bounds__(512) void k_adj_partial(AdjArgs a) {
   extern __shared__ float2 lds[];
@@ -81,18 +97,25 @@ __global__ __launch_bounds__(512) void k_adj_partial(AdjArgs a) {
       }
     }
   }
+  // Lane sums of the 2*BM values of each tap by a butterfly reduce-scatter
+  // (fixed order): every step halves the values a lane holds, exchanging
+  // the other half with the lane `off` apart; after the steps 32..2 lane l
+  // holds value 16*b5 + 8*b4 + 4*b3 + 2*b2 + b1 (bits of l), summed over the
+  // lanes that share bit 0, and a last exchange adds the pair.
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 4; ++q) {
+    float v[32];
 #pragma unroll
-    for (int b = 0; b < BM; ++b) {
-      float vr = accr[q][b], vi = acci[q][b];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        vr += __shfl_xor(vr, off);
-        vi += __shfl_xor(vi, off);
-      }
-      if (lane == 0 && m0 + q < M) red[b * M + m0 + q] = make_float2(vr, vi);
+    for (int i = 0; i < 32; ++i) v[i] = i < 2 * BM ? ((i & 1) ? acci[q][i >> 1] : accr[q][i >> 1]) : 0.f;
+    butterfly_step<16>(v, lane);
+    const float tot = v[0] + __shfl_xor(v[0], 1);
+    const int idx = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
+                    ((lane >> 1) & 1);
+    if ((lane & 1) == 0 && idx < 2 * BM && m0 + q < M) {
+      float *dst = reinterpret_cast<float *>(&red[(idx >> 1) * M + m0 + q]);
+      dst[idx & 1] = tot;
     }
+  }
   // taps before the firing start read branch b's history source: the last
   // M-1 samples of its previous feeding firing (zeros if none), staged in
   // LDS by all threads at once
