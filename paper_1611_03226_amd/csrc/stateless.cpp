@@ -63,7 +63,8 @@ void free_tables(Tables *t, hipStream_t s) {
   if (t->grp) (void)hipFreeAsync(t->grp, s);
 }
 
-int adj_chunk(int64_t r) { return (int)std::min<int64_t>(1024, r); }
+// outputs per adjoint workgroup (2048 balances the lane reduction against occupancy)
+int adj_chunk(int64_t r) { return (int)std::min<int64_t>(2048, r); }
 
 }  // namespace
 
