@@ -45,7 +45,7 @@ VALU_PEAK_PACKED = 2 * VALU_PEAK
 # kernel; reported only while the kernel's sources are the ones profiled.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dpd_tiled_dpd_scale_2p24_traffic.md")
 KERNEL_SOURCES = ("paper_1611_03226_amd/csrc/k_dpd.hip", "paper_1611_03226_amd/csrc/dpd_tile.h",
-                  "paper_1611_03226_amd/csrc/common.h", "paper_1611_03226_amd/csrc/k_scan.hip")
+                  "paper_1611_03226_amd/csrc/common.h")
 
 
 def kernel_sources_sha256() -> str:
@@ -361,7 +361,9 @@ def bench_adaptation(D, torch, steps=10, warmup=2):
 
 
 def cpu_baseline(budget_s=12.0):
-    """The oracle network on a prefix of the same workload, one host core."""
+    """The oracle network on the same workload, one host core: a prefix of
+    the batch sized to about budget_s, or whole batches repeated until
+    budget_s has elapsed."""
     from oracle import dpd as odpd
     from workloads import dpd_scale
     w = dpd_scale()
@@ -371,12 +373,19 @@ def cpu_baseline(budget_s=12.0):
     odpd.run_dpd(w.x[:n * r], w.ctrl[:n], w.h, r)
     dt = time.perf_counter() - t0
     n = int(min(w.n_firings, max(16, n * budget_s / max(dt, 1e-3))))
+    reps, samples = 0, 0
     t0 = time.perf_counter()
-    odpd.run_dpd(w.x[:n * r], w.ctrl[:n], w.h, r)
-    dt = time.perf_counter() - t0
-    return dict(value=round(n * r / dt / 1e6, 4), unit="Msamples/s", cores=1, kind="oracle",
-                sample=f"first {n} firings ({n * r} samples) of the 2^24-sample workload, "
-                       f"FP64 sequential dataflow scheduler, {dt:.1f} s")
+    while True:
+        odpd.run_dpd(w.x[:n * r], w.ctrl[:n], w.h, r)
+        reps += 1
+        samples += n * r
+        dt = time.perf_counter() - t0
+        if n < w.n_firings or dt >= budget_s:
+            break
+    what = (f"first {n} firings ({n * r} samples) of the 2^24-sample workload" if n < w.n_firings
+            else f"the whole 2^24-sample batch (4096 firings), {reps} passes")
+    return dict(value=round(samples / dt / 1e6, 4), unit="Msamples/s", cores=1, kind="oracle",
+                sample=f"{what}, FP64 sequential dataflow scheduler, {dt:.1f} s")
 
 
 def summarize_pmc(fetch_csv, write_csv, bench_json):
@@ -391,7 +400,7 @@ def summarize_pmc(fetch_csv, write_csv, bench_json):
                 if row["Counter_Name"] != counter:
                     continue
                 name = row["Kernel_Name"]
-                key = "copy" if "k_stream_copy" in name else ("dpd" if "k_dpd_tiled<16, 4>" in name else None)
+                key = "copy" if "k_stream_copy" in name else ("dpd" if "k_dpd_tiled<16, 4, 10>" in name else None)
                 if key:
                     vals.setdefault(key, {}).setdefault(row["Dispatch_Id"], 0.0)
                     vals[key][row["Dispatch_Id"]] += float(row["Counter_Value"])
@@ -409,7 +418,7 @@ def summarize_pmc(fetch_csv, write_csv, bench_json):
     rd = f["dpd"][0] * 1024 / fr
     wr = w["dpd"][0] * 1024 / fw
     lines = [
-        "# HBM traffic of k_dpd_tiled<16,4>, 2^24-sample workload (4096 firings of 4096, B 1..10, M 16)",
+        "# HBM traffic of k_dpd_tiled<16,4,10>, 2^24-sample workload (4096 firings of 4096, B 1..10, M 16)",
         "",
         "Commands (on the GPU host, from the repository root; `cd /tmp && export TMPDIR=/tmp` first):",
         "",
@@ -426,7 +435,7 @@ def summarize_pmc(fetch_csv, write_csv, bench_json):
         f"FETCH_SIZE {f['copy'][0]:.1f} KiB, WRITE_SIZE {w['copy'][0]:.1f} KiB per dispatch; "
         f"scale factors {fr:.4f} (read) and {fw:.4f} (write) counter bytes per byte moved.",
         "",
-        f"k_dpd_tiled<16,4> ({f['dpd'][1]} / {w['dpd'][1]} dispatches): FETCH_SIZE {f['dpd'][0]:.1f} KiB, "
+        f"k_dpd_tiled<16,4,10> ({f['dpd'][1]} / {w['dpd'][1]} dispatches): FETCH_SIZE {f['dpd'][0]:.1f} KiB, "
         f"WRITE_SIZE {w['dpd'][0]:.1f} KiB per dispatch.",
         "",
         f"- hbm_read_bytes_per_launch: {rd:.0f}",
@@ -484,7 +493,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK / 1e12, 1),
                      "unit": "TFLOP/s", "frac": round(achieved * 1e12 / VALU_PEAK, 4), "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": m["bytes"], "kernel_sources_sha256": kernel_sources_sha256(),
-                     "kernel": "k_dpd_tiled<16,4>", "kernel_ms": round(m["body_ms"], 4),
+                     "kernel": "k_dpd_tiled<16,4,10>", "kernel_ms": round(m["body_ms"], 4),
                      "algorithmic_flops_per_launch": m["flops"],
                      "frac_of_packed_peak": round(achieved * 1e12 / VALU_PEAK_PACKED, 4),
                      "hbm_frac": round(m["bytes"] / body_s / HBM_PEAK, 4)},
