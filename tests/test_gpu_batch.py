@@ -151,3 +151,41 @@ def test_fire_many_validation():
             G.fire_many([a.actor], [2], persistent=True)                 # 1 firing of input
         assert e.value.code == D.DF_EAGAIN
         assert G.status(a.ctrl)[:2] == (0, 2)
+
+
+def test_graph_replay_with_changing_firing_counts():
+    """Persistent graph mode when the firing counts change between batches
+    (the captured chain is rebuilt) equals per-actor launches bit for bit."""
+    from paper_1611_03226_amd.graph import Graph
+    r = 256
+    insts = _instances(62, 10, r, 5)
+    rng = np.random.default_rng(3)
+    plans = [[d["nf"] for d in insts], [max(1, d["nf"] - 1) for d in insts], [d["nf"] for d in insts]]
+    plans[1][0] = 0                                   # one instance idle in the second batch
+    outs = {}
+    for mode in ("many", "graph"):
+        say(f"batch changing counts {mode}")
+        with Graph(0) as G:
+            chains = []
+            for d in insts:
+                cap = _pow2(3 * d["nf"] * r)
+                chains.append(G.dpd_chain(d["h"], r, history=d["hist"], cap_x=cap, cap_ctrl=_pow2(3 * d["nf"]),
+                                          cap_y=cap))
+            for d, ch in zip(insts, chains):
+                G.push(ch.x, d["x"])
+                G.push(ch.ctrl, d["ctrl"])
+            ys = [[] for _ in insts]
+            for nfs in plans:
+                G.fire_many([c.actor for c in chains], nfs, persistent=mode == "graph", graph=mode == "graph")
+                for i, (nf, ch) in enumerate(zip(nfs, chains)):
+                    y = np.zeros(nf * r, np.complex64)
+                    assert G.pop(ch.y, y) == len(y)
+                    ys[i].append(y)
+            G.sync()
+        outs[mode] = [np.concatenate(v) for v in ys]
+    for a, b in zip(outs["many"], outs["graph"]):
+        assert np.array_equal(a.view(np.float32), b.view(np.float32))
+    for d, y in zip(insts, outs["graph"]):
+        k = len(y) // r
+        ref = odpd.run_dpd(d["x"][:k * r], d["ctrl"][:k], d["h"], r, hist=d["hist"])
+        assert rel_rms_per_firing(y, ref, r)[0] <= DPD_TOL

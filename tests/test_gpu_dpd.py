@@ -212,3 +212,23 @@ def test_scale_workload_full_size_sampled(G):
     err = np.abs(y[idx] - ref) / rms
     print(f"dpd scale 2^24: max |err|/RMS over {len(idx)} samples {err.max():.3e}")
     assert err.max() <= DPD_TOL
+
+
+@pytest.mark.parametrize("hist", ["branch", "shared"])
+def test_tables_and_outputs_many_firings(G, hist):
+    """A batch of 9000 firings: the scan takes three passes of 4096 firings
+    with carries, the grouped order is rebuilt from memory; tables bit-exact,
+    outputs within tolerance."""
+    from paper_1611_03226_amd import dfhip as D
+    say(f"dpd 9000 firings {hist}")
+    n = 9000
+    w = dpd_random(55, n_firings=n, r=16, n_branches_max=7, n_taps=8, ctrl_low=0)
+    y, ch = run_dpd_chain(G, w, hist=hist)
+    rates, offs, prev = D.df_debug_last_batch(G.g, ch.actor, 7, n)
+    r_ref, o_ref, p_ref, _ = odpd.firing_tables(w.ctrl, 7, w.r, hist)
+    assert np.array_equal(rates, r_ref)
+    assert np.array_equal(offs, o_ref)
+    assert np.array_equal(prev, p_ref)
+    ref = odpd.run_dpd(w.x, w.ctrl, w.h, w.r, hist=hist)
+    worst, _, bad0 = rel_rms_per_firing(y, ref, w.r)
+    assert worst <= DPD_TOL and bad0 == 0
