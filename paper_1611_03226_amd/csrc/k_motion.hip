@@ -40,8 +40,9 @@ constexpr int MW_CHUNK = 62;   // output words per wavefront
 __device__ __forceinline__ void load_word(const uint8_t *frame, int y, int x0, int W, bool fast, uint32_t (&v)[8]) {
   const uint8_t *p = frame + (int64_t)y * W + x0;
   if (fast) {
-    const uint4 a = *reinterpret_cast<const uint4 *>(p);
-    const uint4 b = *reinterpret_cast<const uint4 *>(p + 16);
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 a = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    const u32x4 b = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p + 16));
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
     v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
   } else {
@@ -227,7 +228,9 @@ __global__ __launch_bounds__(256) void k_motion_expand(MotionArgs a) {
     v[k] = ((nib * 0x00204081u) & 0x01010101u) * 0xFFu;  // bit i -> byte i
   }
   if (FAST) {
-    *reinterpret_cast<uint4 *>(dst) = make_uint4(v[0], v[1], v[2], v[3]);
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 val = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(val, reinterpret_cast<u32x4 *>(dst));
   } else {
     const int n = min(16, W - x);
     for (int i = 0; i < n; ++i) dst[i] = (uint8_t)(v[i >> 2] >> (8 * (i & 3)));
