@@ -64,6 +64,12 @@ struct DpdArgs {
   int32_t tiles_per_firing;
   const int32_t *order;   // processing order, pairs (firing, B) grouped by B, or nullptr
   float2 *corr;           // [n_firings][M-1] head corrections (tiled kernels)
+  // With grp set (one segment), the head pass derives each firing's history
+  // sources from the scan's group table and writes the prev/off tables itself.
+  const int64_t *grp;     // [groups][B_max][2] from k_scan, or nullptr
+  int64_t *tab_prev;      // [B_max][prev_stride]
+  int64_t *tab_off;       // [B_max][prev_stride] or nullptr
+  int32_t hist_mode;
   int32_t *ticket;        // tiled kernel: the last workgroup to finish runs `commit` (nullptr: none)
   DpdCommitArgs commit;
 };
@@ -140,7 +146,7 @@ int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes);
 
 // ---------------------------------------------------------------- launchers
 int64_t scan_groups(int64_t n_segs, int64_t seg_firings);   // 64-firing groups of a scan
-hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s, bool tables = true);
 // Optional start/stop events of one kernel launch (timing rides on the
 // dispatch itself: hipExtLaunchKernel), or none.
 struct KTiming {

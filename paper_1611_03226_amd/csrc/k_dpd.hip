@@ -83,21 +83,53 @@ __device__ __forceinline__ void dpd_commit_block(const DpdCommitArgs &a) {
 
 // ------------------------------------------------------------------ heads
 // Head corrections of every firing with B > 0 (four firings per
-// wavefront); corr[g][q], q < M-1.  Read by the tiled body.
-template <int M>
+// wavefront); corr[g][q], q < M-1.  Read by the tiled body.  With a group
+// table (one segment) the wavefront also derives the history sources of its
+// four firings and writes their prev/off table entries: the four firings lie
+// in one 64-firing group, so a ballot of the group's feed flags per branch
+// plus the group's entry (count and last feeder before it) gives them.
+template <int M, bool TABLES>
 __global__ __launch_bounds__(256) void k_dpd_heads(DpdArgs a) {
   const int64_t g0 = ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * 4;
   if (g0 >= a.n_firings) return;                     // uniform per wavefront
   const int64_t Rx = a.x_idx ? as_const(a.x_idx)[0] : 0;
+  const int lane = threadIdx.x & 63, row = lane >> 4, i = lane & 15;
+  const int64_t g = g0 + row;                         // this lane's firing
+  int64_t pf[kMaxBranches];
+  if constexpr (TABLES) {
+    const int64_t G = g0 >> 6;
+    const int64_t gl = G * 64 + lane;                 // lane's firing of the group
+    const bool gin = gl < a.n_firings;
+    const int Bl = gin ? (a.B ? a.B[gl] : a.B_const) : 0;
+    const uint64_t below_mask = (1ull << ((g0 & 63) + row)) - 1;
+#pragma unroll
+    for (int b = 0; b < kMaxBranches; ++b) {
+      pf[b] = -1;
+      if (b >= a.B_max) continue;                     // uniform
+      const uint64_t bal = __ballot(gin && (a.hist_mode == 1 || Bl > b));
+      const int64_t gi = 2 * (G * a.B_max + b);
+      const int64_t cnt0 = as_const(a.grp)[gi], last0 = as_const(a.grp)[gi + 1];
+      const uint64_t below = bal & below_mask;
+      pf[b] = below ? G * 64 + 63 - __clzll((long long)below) : last0;
+      if (i == b && g < a.n_firings) {
+        const int64_t o = (int64_t)b * a.prev_stride + g;
+        a.tab_prev[o] = pf[b];
+        if (a.tab_off) a.tab_off[o] = a.r * (cnt0 + __popcll(below));
+      }
+    }
+  }
   head_correction<M, 4>(
       as_const(a.h),
-      [&](int row) {
-        const int64_t g = g0 + row;
-        return g < a.n_firings ? (a.B ? a.B[g] : a.B_const) : 0;
+      [&](int r) {
+        const int64_t gr = g0 + r;
+        return gr < a.n_firings ? (a.B ? a.B[gr] : a.B_const) : 0;
       },
-      [&](int row, int b) { return prev_of(a, b, g0 + row); },
-      [&](int row, int b, int64_t pf, int i) { return hist_sample(a, Rx, b, g0 + row, pf, (int64_t)i - (M - 1)); },
-      [&](int row) { return a.corr + (g0 + row) * (M - 1); });
+      [&](int r, int b) {
+        if constexpr (TABLES) return pf[b];              // this lane's row
+        else return prev_of(a, b, g0 + r);
+      },
+      [&](int r, int b, int64_t p, int q) { return hist_sample(a, Rx, b, g0 + r, p, (int64_t)q - (M - 1)); },
+      [&](int r) { return a.corr + (g0 + r) * (M - 1); });
 }
 
 // ------------------------------------------------------------------ tiled
@@ -184,10 +216,17 @@ bool dpd_tiled_shape(int M) { return M == 4 || M == 8 || M == 16; }
 hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s) {
   if (a.n_firings <= 0 || !dpd_tiled_shape(a.M)) return hipSuccess;
   if (!a.corr) return hipErrorInvalidValue;
+  if (a.grp && (a.seg_firings != a.n_firings || !a.tab_prev)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((a.n_firings + 15) / 16));
-  if (a.M == 16) hipLaunchKernelGGL(k_dpd_heads<16>, grid, dim3(256), 0, s, a);
-  else if (a.M == 8) hipLaunchKernelGGL(k_dpd_heads<8>, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_dpd_heads<4>, grid, dim3(256), 0, s, a);
+#define DF_HEADS(m)                                                                     \
+  if (a.M == m) {                                                                       \
+    if (a.grp)                                                                          \
+      hipLaunchKernelGGL((k_dpd_heads<m, true>), grid, dim3(256), 0, s, a);             \
+    else                                                                                \
+      hipLaunchKernelGGL((k_dpd_heads<m, false>), grid, dim3(256), 0, s, a);            \
+  }
+  DF_HEADS(16) else DF_HEADS(8) else DF_HEADS(4)
+#undef DF_HEADS
   return hipGetLastError();
 }
 

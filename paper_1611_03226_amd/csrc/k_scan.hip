@@ -201,7 +201,7 @@ int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes) {
   return n;
 }
 
-hipError_t launch_scan(const ScanArgs &a, hipStream_t s) {
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s, bool tables) {
   if (a.n_segs <= 0 || a.seg_firings <= 0) return hipSuccess;
   if (a.B_max < 1 || a.B_max > kMaxBranches || !a.grp) return hipErrorInvalidValue;
   if (a.order_out && a.n_segs != 1) return hipErrorInvalidValue;
@@ -213,6 +213,7 @@ hipError_t launch_scan(const ScanArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(a.n_segs), dim3(64 * (unsigned)waves), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (!tables) return hipSuccess;                    // the head pass fills them
   const int64_t ng = scan_groups(a.n_segs, a.seg_firings);
   hipLaunchKernelGGL(k_scan_tables, dim3((unsigned)((ng + 3) / 4)), dim3(256), 0, s, a, ng);
   return hipGetLastError();

@@ -504,7 +504,9 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   const bool ordered = n > 64;                       // grouping pays off only for many workgroups
   sa.order_out = ordered ? a.order : nullptr;
   sa.grp = a.grp;
-  HIPCHK(g, launch_scan(sa, g->stream));
+  // tiled bodies: the head pass fills the prev/off tables from the group table
+  const bool heads_tables = dpd_tiled_shape(M);
+  HIPCHK(g, launch_scan(sa, g->stream, !heads_tables));
 
   DpdArgs da{};
   da.x = (const float2 *)fx.ring;
@@ -525,6 +527,12 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   da.B_max = bm;
   da.M = M;
   da.corr = a.corr;
+  if (heads_tables) {
+    da.grp = a.grp;
+    da.tab_prev = a.prev;
+    da.tab_off = a.off;
+    da.hist_mode = a.dp.history_mode;
+  }
   HIPCHK(g, launch_dpd_heads(da, g->stream));
   DpdCommitArgs ca{};
   ca.x = (const float2 *)fx.ring;
