@@ -1,8 +1,8 @@
 """Tile autotuner for the persistent multi-instance predistortion launch.
 
 Candidates are (tile_outputs, outputs_per_thread, blocks_per_cu) triples.
-Each is timed on the GPU (HIP-graph replay of the persistent chain, wall
-clock between stream synchronisations) over a subset of the instances, and
+Each is timed on the GPU (HIP events around every HIP-graph replay of the
+persistent chain, mean over the replays) over a subset of the instances, and
 the fastest is cached in a JSON file keyed by device architecture, taps,
 largest branch count, firing size and length class.
 
@@ -13,7 +13,6 @@ from __future__ import annotations
 import json
 import math
 import os
-import time
 
 import numpy as np
 
@@ -62,10 +61,11 @@ def _pow2(n):
     return p
 
 
-def tune_instances(w, candidates=None, subset_stride: int = 4, reps: int = 2, force: bool = False, log=None):
+def tune_instances(w, candidates=None, subset_stride: int = 4, reps: int = 4, force: bool = False, log=None):
     """Best (tile_outputs, outputs_per_thread, blocks_per_cu) for a workload of
     independent instances (workloads.InstancesWorkload)."""
     import torch
+    from . import dfhip as D
     from .graph import Graph
 
     r, M = w.r, w.n_taps
@@ -97,11 +97,14 @@ def tune_instances(w, candidates=None, subset_stride: int = 4, reps: int = 2, fo
             G.set_tile(*cand)
             G.fire_many(actors, nfs, persistent=True, graph=True)      # capture + warm
             G.sync()
-            t0 = time.perf_counter()
+            D.df_profile_enable(G.g, True)
+            D.df_profile_read(G.g)
             for _ in range(reps):
                 G.fire_many(actors, nfs, persistent=True, graph=True)
             G.sync()
-            timings[cand] = (time.perf_counter() - t0) / reps
+            ms, n = D.df_profile_read(G.g)
+            D.df_profile_enable(G.g, False)
+            timings[cand] = ms * 1e-3 / max(n, 1)
             # drain outputs so the output rings never fill
             for ch, nf in zip(chains, nfs):
                 y = torch.empty((reps + 1) * nf * r, dtype=torch.complex64, device="cuda")
