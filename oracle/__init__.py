@@ -15,8 +15,8 @@ Modules:
     dataflow  FIFO channel, actor base class, scheduler (Sec. 2.2, 3.1)
     dpd       the predistortion network P -> FIR_b -> A (Sec. 4.2)
     motion    the motion-detection network Detect -> Gate (Sec. 4.1 idiom)
+    md_paper  the paper's motion-detection pipeline Gauss -> Thres -> Med (Sec. 4.1)
     pa        memory-polynomial PA, Wirtinger adjoints, finite differences
-    fifo_layout  channel capacity of Eq. (1) and the delay-token buffer of Fig. 2
 
 Every function's docstring names the passage it follows.  Functions whose
 result is not pinned by a test say "parity unpinned" (none at present).
