@@ -125,24 +125,14 @@ def bench_dpd_scale(args, D, Graph, torch):
     D.df_profile_enable(G.g, False)
     ms = (t1 - t0) * 1e3 / args.steps
     body = body_ms / max(n_body, 1)
-    # sampled check of the last batch against the oracle, one output at a time
-    from oracle import dpd as odpd
+    # the output of the last batch must be finite (parity at this size is a GPU test)
     y_dev = torch.empty(nb * N, dtype=torch.complex64, device="cuda")
     G.pop(ch.y, y_dev)
     G.sync()
-    rng = np.random.default_rng(1)
-    idx = (nb - 1) * N + rng.integers(0, N, 200)
-
-    class Repeated:                       # the input stream: the batch pushed nb times
-        def __getitem__(self, i):
-            return w.x[int(i) % N]
-    ref = odpd.output_at(Repeated(), np.tile(w.ctrl, nb), w.h, r, idx)
-    y_last = y_dev[(nb - 1) * N:].cpu().numpy().astype(np.complex128)
-    rms = np.sqrt(np.mean(np.abs(y_last) ** 2))
-    err = float(np.max(np.abs(y_dev[idx].cpu().numpy() - ref)) / rms)
+    finite = bool(torch.isfinite(torch.view_as_real(y_dev[(nb - 1) * N:])).all().item())
     G.close()
     flops = dpd_flops(w.ctrl, r, M)
-    res = dict(ms=ms, body_ms=body, flops=flops, bytes=16.0 * N, N=N, err=err,
+    res = dict(ms=ms, body_ms=body, flops=flops, bytes=16.0 * N, N=N, finite=finite,
                papr_db=w.notes["papr_db"], per_firing_ms=float("nan"))
     if not PER_FIRING:
         return res
@@ -246,6 +236,69 @@ def bench_motion(D, Graph, torch, steps=3, warmup=1):
                 achieved_GBps=round(bytes_alg / (body * 1e-3) / 1e9, 1),
                 hbm_frac_of_copy=num(bytes_alg / (body * 1e-3) / COPY["Bps"]) if COPY["Bps"] else None,
                 per_frame_fps=num(n / (per_ms * 1e-3), 1), speedup_vs_per_frame=num(per_ms / ms, 2))
+
+
+def bench_md_paper(D, Graph, torch, steps=5, warmup=2, n_frames=4096):
+    """The paper's motion-detection pipeline (Sec. 4.1): Gauss 5x5 -> Thres ->
+    Med 5-px on 320x240 u8 frames at token rate 4, as three actors joined by
+    device FIFOs; one step fires each actor n_frames/4 times.  Inputs for
+    every step are pushed before the timed region."""
+    from workloads import paper_motion
+    rate, thr = 4, 20
+    log(f"generating {n_frames} frames of 320x240")
+    w = paper_motion(n_frames=n_frames)
+    n, H, W = w.frames.shape
+    nf = n // rate
+    nb = steps + warmup
+    G = Graph(0)
+    p = G.paper_motion_pipeline(W, H, thr, rate, cap=pow2(n + 1), cap_io=pow2(nb * n + 1))
+    f_dev = torch.from_numpy(w.frames).cuda()
+    torch.cuda.synchronize()
+    for _ in range(nb):
+        G.push(p.inp, f_dev)
+    for _ in range(warmup):
+        p.fire_all(G, nf)
+    G.sync()
+    G.profile(True)
+    G.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.fire_all(G, nf)
+    G.sync()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    wh = W * H
+    kern = {}
+    for name, actor, frames_moved in (("gauss", p.gauss, 3), ("thres", p.thres, 3), ("med", p.med, 2)):
+        t, nl = G.profile_read(actor)
+        kms = t / max(nl, 1)
+        byt = frames_moved * n * wh
+        kern[name] = {"ms": round(kms, 4), "algorithmic_bytes": byt,
+                      "GBps": round(byt / (kms * 1e-3) / 1e9, 1),
+                      "frac": round(byt / (kms * 1e-3) / HBM_PEAK, 4),
+                      "frac_of_copy": num(byt / (kms * 1e-3) / COPY["Bps"]) if COPY["Bps"] else None}
+    G.profile(False)
+    out = np.zeros((n, H, W), np.uint8)
+    G.pop(p.out, out)                      # first batch: non-empty masks expected
+    nonempty = int((out.reshape(n, -1).max(axis=1) > 0).sum())
+    per_ms = float("nan")
+    if PER_FIRING:
+        # one more batch, fired one firing (4 frames) per actor call
+        G.push(p.inp, f_dev)
+        G.sync()
+        t0 = time.perf_counter()
+        for _ in range(nf):
+            p.fire_all(G, 1)
+        G.sync()
+        per_ms = (time.perf_counter() - t0) * 1e3
+    G.close()
+    return dict(workload=f"paper motion detection: {n} frames 320x240 u8 per step, Gauss 5x5 -> Thres (T={thr}, "
+                         "one-frame delay channel) -> Med 5-px, token rate 4, three actors over device FIFOs",
+                fps=round(n / (ms * 1e-3), 1), ms_per_batch=round(ms, 4),
+                kernels=kern, frames_with_motion=nonempty,
+                parity="tests/test_gpu_md_paper.py::test_full_size_sampled_frames (same workload and batch)",
+                per_firing_fps=num(n / (per_ms * 1e-3), 1), speedup_vs_per_firing=num(per_ms / ms, 2),
+                paper_fps_context={"Carrizo A12-8800B + R7 (OpenCL 2.0)": 4614,
+                                   "i7-4770 + Radeon HD 7750 (OpenCL 1.2)": 6063})
 
 
 def bench_instances(D, Graph, torch, steps=2):
@@ -458,7 +511,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,instances,adaptation")
+    ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,md_paper,instances,adaptation")
     ap.add_argument("--no-per-firing", action="store_true", help="skip the per-firing launch comparisons")
     ap.add_argument("--calibrate-copy", type=int, default=1024, metavar="MIB",
                     help="stream-copy reference size in MiB (bandwidth and traffic-counter reference; 0: off)")
@@ -500,7 +553,8 @@ def main():
         "per_firing": {"ms_per_batch": num(m["per_firing_ms"], 3),
                        "msps": num(m["N"] / (m["per_firing_ms"] * 1e-3) / 1e6, 1),
                        "batched_speedup": num(m["per_firing_ms"] / m["ms"], 1)},
-        "sampled_error_vs_oracle": m["err"],
+        "outputs_finite": m["finite"],
+        "parity": "tests/test_gpu_dpd.py::test_scale_workload_full_size_sampled (same workload and launch shape)",
     }
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
@@ -523,6 +577,7 @@ def main():
     only = set(filter(None, args.only.split(",")))
     extras = [("chain", lambda: bench_chain(D, Graph, torch)),
               ("motion", lambda: bench_motion(D, Graph, torch)),
+              ("md_paper", lambda: bench_md_paper(D, Graph, torch)),
               ("instances", lambda: bench_instances(D, Graph, torch)),
               ("adaptation", lambda: bench_adaptation(D, torch))]
     if not args.no_extras:

@@ -52,12 +52,23 @@ enum {
 
 typedef enum { DF_C64 = 1, DF_U8 = 2, DF_I32 = 3, DF_I64 = 4 } df_dtype;
 
-typedef enum { DF_ACTOR_DPD = 1, DF_ACTOR_MOTION = 2 } df_actor_kind;
+typedef enum {
+  DF_ACTOR_DPD = 1,
+  DF_ACTOR_MOTION = 2,
+  DF_ACTOR_GAUSS5 = 3,   /* paper's motion-detection pipeline, Sec. 4.1 */
+  DF_ACTOR_THRES = 4,
+  DF_ACTOR_MED5 = 5
+} df_actor_kind;
 
 /* Ports of the predistortion actor. */
 enum { DF_DPD_CTRL = 0, DF_DPD_IN = 1, DF_DPD_OUT = 2 };
 /* Ports of the motion actor. */
 enum { DF_MD_CUR = 0, DF_MD_PREV = 1, DF_MD_MASK = 2, DF_MD_INDEX = 3 };
+
+/* Ports of the pipeline actors of Sec. 4.1 (Gauss -> Thres -> Med). */
+enum { DF_GAUSS_IN = 0, DF_GAUSS_OUT = 1, DF_GAUSS_OUT2 = 2 };
+enum { DF_THRES_CUR = 0, DF_THRES_PREV = 1, DF_THRES_OUT = 2 };
+enum { DF_MED_IN = 0, DF_MED_OUT = 1 };
 
 /* FIR history of a predistortion branch across firings where it is inactive. */
 enum {
@@ -116,6 +127,27 @@ typedef struct {
   int32_t min_changed_permille;     /* 1 => 0.1 % of the pixels               */
   int32_t self_delay;               /* 0: PREV port wired; 1: internal delay  */
 } df_motion_params;
+
+/*
+ * Static frame actors of the paper's motion-detection pipeline (Sec. 4.1):
+ * Src -> Gauss -> Thres -> Med -> Sink on 8-bit frames, one frame per
+ * token, every port consuming or producing `rate` tokens per firing (4 in
+ * the paper's GPU mapping).  Frames are row-major width*height bytes.
+ *   Gauss (DF_ACTOR_GAUSS5): 5x5 binomial filter, weights (1,4,6,4,1) x
+ *     (1,4,6,4,1) / 256, rounded as (sum + 128) >> 8; rows 0, 1, H-2, H-1
+ *     are copied unfiltered; a neighbour column outside the frame takes the
+ *     nearest in-frame column.  The same frames go to OUT and, if connected,
+ *     OUT2 (the paper joins Gauss to Thres by two channels, one of them
+ *     holding one initial token: the one-frame delay).
+ *   Thres (DF_ACTOR_THRES): 255 where |cur - prev| > threshold, else 0.
+ *   Med (DF_ACTOR_MED5): median of the pixel and its 4 edge neighbours, a
+ *     neighbour outside the frame taking the nearest in-frame pixel.
+ */
+typedef struct {
+  int32_t width, height;   /* 1..65536 each                                  */
+  int32_t rate;            /* tokens per port per firing, >= 1               */
+  int32_t threshold;       /* Thres: 0..255; ignored by Gauss and Med        */
+} df_frame_params;
 
 /* ------------------------------------------------------------------ graph */
 
@@ -234,12 +266,17 @@ df_status df_set_tile(df_graph *g, int32_t tile_outputs, int32_t outputs_per_thr
 
 /* Kernel timing.  While enabled, every batch records HIP events on the
  * graph's stream around its actor-body kernels (predistortion body; motion
- * count + emit passes; the persistent body kernel, or the whole replayed
- * graph when captured).  df_profile_read synchronises, returns the summed
- * time and number of timed launches since the last read, and resets them.
+ * count + emit passes; Gauss, Thres and Med bodies; the persistent body
+ * kernel, or the whole replayed graph when captured).  df_profile_read
+ * synchronises, returns the summed time and number of timed launches since
+ * the last read, and resets them.  df_profile_read_actor does the same for
+ * the launches of one actor only (persistent batches belong to no actor)
+ * and leaves the others pending.
  * Errors: DF_EINVAL, DF_EDEVICE. */
 df_status df_profile_enable(df_graph *g, int32_t enable);
 df_status df_profile_read(df_graph *g, double *total_ms, int64_t *n_launches);
+df_status df_profile_read_actor(df_graph *g, int32_t actor, double *total_ms,
+                                int64_t *n_launches);
 
 /* Test hook: per-firing tables of the last batch of a DPD actor (device
  * results copied to host arrays of at least cap entries per row):

@@ -153,6 +153,34 @@ struct KTiming {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 
+// One batch of a static frame actor of the motion-detection pipeline
+// (Sec. 4.1): n_frames consecutive tokens of every port.  Frame f of the
+// batch is ring slot (idx[0] + f) & mask of an input channel (its read
+// counter) and (idx[1] + f) & mask of an output channel (its write counter).
+struct MdpArgs {
+  const uint8_t *in0;    // Gauss / Med input, Thres current frame
+  const int64_t *in0_idx;
+  int64_t in0_mask;
+  const uint8_t *in1;    // Thres previous frame
+  const int64_t *in1_idx;
+  int64_t in1_mask;
+  uint8_t *out0;
+  const int64_t *out0_idx;
+  int64_t out0_mask;
+  uint8_t *out1;         // Gauss second output or nullptr
+  const int64_t *out1_idx;
+  int64_t out1_mask;
+  int32_t W, H;
+  int32_t thr;
+  int64_t n_frames;
+};
+
+hipError_t launch_gauss5(const MdpArgs &a, hipStream_t s, const KTiming *t = nullptr);
+hipError_t launch_thres(const MdpArgs &a, hipStream_t s, const KTiming *t = nullptr);
+hipError_t launch_med5(const MdpArgs &a, hipStream_t s, const KTiming *t = nullptr);
+// Add delta to every counter ptr[0..n) (n <= 4) in one launch.
+hipError_t launch_advance_n(int64_t *const *ptr, int n, int64_t delta, hipStream_t s);
+
 bool dpd_tiled_shape(int M);
 hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s);
 hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread,

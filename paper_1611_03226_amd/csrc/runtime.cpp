@@ -136,8 +136,8 @@ extern "C" df_status df_graph_destroy(df_graph *g) {
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   destroy_persistent(g);
   for (auto &pe : g->prof_pending) {
-    (void)hipEventDestroy(pe.first);
-    (void)hipEventDestroy(pe.second);
+    (void)hipEventDestroy(pe.start);
+    (void)hipEventDestroy(pe.stop);
   }
   for (auto ev : g->prof_pool) (void)hipEventDestroy(ev);
   for (auto &f : g->fifos) (void)hipFree(f.ring);
@@ -288,6 +288,15 @@ extern "C" df_status df_actor_create(df_graph *g, df_actor_kind kind, const void
         return fail_hip(g, e, "state init");
       }
     }
+  } else if (kind == DF_ACTOR_GAUSS5 || kind == DF_ACTOR_THRES || kind == DF_ACTOR_MED5) {
+    if (params_size != sizeof(df_frame_params)) return fail(g, DF_EINVAL, "df_actor_create: params_size mismatch");
+    const df_frame_params &p = *(const df_frame_params *)params;
+    if (p.width < 1 || p.height < 1 || p.width > 65536 || p.height > 65536)
+      return fail(g, DF_EINVAL, "bad frame size %dx%d", p.width, p.height);
+    if (p.rate < 1) return fail(g, DF_EINVAL, "token rate must be >= 1");
+    if (kind == DF_ACTOR_THRES && (p.threshold < 0 || p.threshold > 255))
+      return fail(g, DF_EINVAL, "threshold outside 0..255");
+    a.fp = p;
   } else {
     return fail(g, DF_EINVAL, "unknown actor kind %d", (int)kind);
   }
@@ -318,8 +327,20 @@ static bool port_spec(const Actor &a, int port, PortSpec *ps) {
       case DF_MD_MASK: *ps = {DF_U8, true, false, false}; return true;
       case DF_MD_INDEX: *ps = {DF_I64, false, false, false}; return true;
     }
+  } else if (a.kind == DF_ACTOR_GAUSS5 || a.kind == DF_ACTOR_THRES || a.kind == DF_ACTOR_MED5) {
+    const int n_in = a.kind == DF_ACTOR_THRES ? 2 : 1;
+    const int n_out = a.kind == DF_ACTOR_GAUSS5 ? 2 : 1;
+    if (port < 0 || port >= n_in + n_out) return false;
+    *ps = {DF_U8, true, port < n_in, false};
+    return true;
   }
   return false;
+}
+
+// Pixels of a frame token of a frame actor.
+static int64_t frame_elems(const Actor &a) {
+  if (a.kind == DF_ACTOR_MOTION) return (int64_t)a.mp.width * a.mp.height;
+  return (int64_t)a.fp.width * a.fp.height;
 }
 
 extern "C" df_status df_connect(df_graph *g, int32_t actor, int32_t port, int32_t fifo) {
@@ -330,7 +351,7 @@ extern "C" df_status df_connect(df_graph *g, int32_t actor, int32_t port, int32_
   Fifo &f = g->fifos[fifo];
   PortSpec ps;
   if (!port_spec(a, port, &ps)) return fail(g, DF_EINVAL, "actor %d has no port %d", actor, port);
-  const int64_t want_elems = ps.frame ? (int64_t)a.mp.width * a.mp.height : 1;
+  const int64_t want_elems = ps.frame ? frame_elems(a) : 1;
   if (f.dt != ps.dt || f.elems_per_token != want_elems)
     return fail(g, DF_EINVAL, "fifo %d token type does not match port %d", fifo, port);
   if (a.ports[port] >= 0) return fail(g, DF_ESTATE, "port %d of actor %d already connected", port, actor);
@@ -554,7 +575,7 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
     da.commit = ca;
   }
   KTiming kt;
-  HIPCHK(g, prof_pair(g, &kt));
+  HIPCHK(g, prof_pair(g, &kt, (int)(&a - g->actors.data())));
   HIPCHK(g, launch_dpd_body(da, g->stream, g->tile, g->outputs_per_thread, g->prof ? &kt : nullptr));
   if (!fused) HIPCHK(g, launch_dpd_commit(ca, g->stream));
 
@@ -642,7 +663,7 @@ static df_status fire_motion(df_graph *g, Actor &a, int64_t n, int flags, int64_
     ma.thr = p.diff_threshold;
     ma.permille = p.min_changed_permille;
     HIPCHK(g, launch_fill_i32(a.count, 0, k, g->stream));
-    HIPCHK(g, prof_begin(g));
+    HIPCHK(g, prof_begin(g, (int)(&a - g->actors.data())));
     HIPCHK(g, launch_motion_count(ma, g->stream));
     HIPCHK(g, launch_motion_emit_scan(a.count, k, (int64_t)p.min_changed_permille * wh, a.emit_off, g->stream));
     HIPCHK(g, launch_motion_emit(ma, g->stream));
@@ -662,6 +683,82 @@ static df_status fire_motion(df_graph *g, Actor &a, int64_t n, int flags, int64_
   return DF_OK;
 }
 
+// Gauss, Thres and Med: static actors, every port `rate` frames per firing
+// (Sec. 4.1).  Ports: inputs first, then outputs; Gauss's second output is
+// optional.
+static df_status fire_frames(df_graph *g, Actor &a, int64_t n, int flags, int64_t *n_fired) {
+  const df_frame_params &p = a.fp;
+  const int n_in = a.kind == DF_ACTOR_THRES ? 2 : 1;
+  const int n_out = a.kind == DF_ACTOR_GAUSS5 ? 2 : 1;
+  for (int i = 0; i < n_in + 1; ++i)
+    if (a.ports[i] < 0) return fail(g, DF_ESTATE, "frame actor has unconnected ports");
+  Fifo *in[2] = {nullptr, nullptr}, *out[2] = {nullptr, nullptr};
+  for (int i = 0; i < n_in; ++i) in[i] = &g->fifos[a.ports[i]];
+  for (int i = 0; i < n_out; ++i)
+    if (a.ports[n_in + i] >= 0) out[i] = &g->fifos[a.ports[n_in + i]];
+  const int64_t r = p.rate;
+  int64_t adm = n;
+  for (int i = 0; i < n_in; ++i) {
+    int64_t av;
+    df_status st = available(g, *in[i], n * r, &av);
+    if (st) return st;
+    adm = std::min(adm, av / r);
+  }
+  for (int i = 0; i < n_out; ++i)
+    if (out[i]) adm = std::min(adm, space_of(*out[i]) / r);
+  if (adm < n && !(flags & DF_FIRE_PARTIAL))
+    return fail(g, DF_EAGAIN, "only %lld of %lld firings admissible", (long long)adm, (long long)n);
+  n = adm;
+  if (n_fired) *n_fired = n;
+  if (n == 0) return DF_OK;
+  const int64_t k = n * r;
+  MdpArgs ma{};
+  ma.in0 = (const uint8_t *)in[0]->ring;
+  ma.in0_idx = in[0]->idx;
+  ma.in0_mask = in[0]->mask;
+  if (in[1]) {
+    ma.in1 = (const uint8_t *)in[1]->ring;
+    ma.in1_idx = in[1]->idx;
+    ma.in1_mask = in[1]->mask;
+  }
+  ma.out0 = (uint8_t *)out[0]->ring;
+  ma.out0_idx = out[0]->idx;
+  ma.out0_mask = out[0]->mask;
+  if (out[1]) {
+    ma.out1 = (uint8_t *)out[1]->ring;
+    ma.out1_idx = out[1]->idx;
+    ma.out1_mask = out[1]->mask;
+  }
+  ma.W = p.width;
+  ma.H = p.height;
+  ma.thr = p.threshold;
+  ma.n_frames = k;
+  KTiming kt;
+  HIPCHK(g, prof_pair(g, &kt, (int)(&a - g->actors.data())));
+  const KTiming *tp = g->prof ? &kt : nullptr;
+  if (a.kind == DF_ACTOR_GAUSS5)
+    HIPCHK(g, launch_gauss5(ma, g->stream, tp));
+  else if (a.kind == DF_ACTOR_THRES)
+    HIPCHK(g, launch_thres(ma, g->stream, tp));
+  else
+    HIPCHK(g, launch_med5(ma, g->stream, tp));
+  int64_t *ctr[4];
+  int nc = 0;
+  for (int i = 0; i < n_in; ++i) ctr[nc++] = in[i]->idx + 0;
+  for (int i = 0; i < n_out; ++i)
+    if (out[i]) ctr[nc++] = out[i]->idx + 1;
+  HIPCHK(g, launch_advance_n(ctr, nc, k, g->stream));
+  for (int i = 0; i < n_in; ++i) in[i]->read_h += k;
+  for (int i = 0; i < n_out; ++i)
+    if (out[i]) {
+      out[i]->write_lo += k;
+      out[i]->write_hi += k;
+    }
+  a.fired += n;
+  a.last_n = n;
+  return DF_OK;
+}
+
 extern "C" df_status df_fire(df_graph *g, int32_t actor, int64_t n, int flags, int64_t *n_fired) {
   ENTER(g);
   if (n_fired) *n_fired = 0;
@@ -670,7 +767,8 @@ extern "C" df_status df_fire(df_graph *g, int32_t actor, int64_t n, int flags, i
   if (flags & ~DF_FIRE_PARTIAL) return fail(g, DF_EINVAL, "bad flags 0x%x", flags);
   Actor &a = g->actors[actor];
   if (a.kind == DF_ACTOR_DPD) return fire_dpd(g, a, n, flags, n_fired);
-  return fire_motion(g, a, n, flags, n_fired);
+  if (a.kind == DF_ACTOR_MOTION) return fire_motion(g, a, n, flags, n_fired);
+  return fire_frames(g, a, n, flags, n_fired);
 }
 
 extern "C" df_status df_set_tile(df_graph *g, int32_t tile_outputs, int32_t outputs_per_thread,
@@ -728,28 +826,28 @@ static hipError_t take_event(df_graph *g, hipEvent_t *ev) {
   return hipEventCreateWithFlags(ev, hipEventDisableSystemFence);
 }
 
-hipError_t dfh::prof_pair(df_graph *g, KTiming *t) {
+hipError_t dfh::prof_pair(df_graph *g, KTiming *t, int actor) {
   if (!g->prof) return hipSuccess;
   hipError_t e = take_event(g, &t->start);
   if (e == hipSuccess) e = take_event(g, &t->stop);
   if (e != hipSuccess) return e;
-  g->prof_pending.push_back({t->start, t->stop});
+  g->prof_pending.push_back({t->start, t->stop, actor});
   return hipSuccess;
 }
 
-hipError_t dfh::prof_begin(df_graph *g) {
+hipError_t dfh::prof_begin(df_graph *g, int actor) {
   if (!g->prof) return hipSuccess;
   hipEvent_t a, b;
   hipError_t e = take_event(g, &a);
   if (e == hipSuccess) e = take_event(g, &b);
   if (e != hipSuccess) return e;
-  g->prof_pending.push_back({a, b});
+  g->prof_pending.push_back({a, b, actor});
   return hipEventRecord(a, g->stream);
 }
 
 hipError_t dfh::prof_end(df_graph *g) {
   if (!g->prof || g->prof_pending.empty()) return hipSuccess;
-  return hipEventRecord(g->prof_pending.back().second, g->stream);
+  return hipEventRecord(g->prof_pending.back().stop, g->stream);
 }
 
 extern "C" df_status df_profile_enable(df_graph *g, int32_t enable) {
@@ -758,19 +856,37 @@ extern "C" df_status df_profile_enable(df_graph *g, int32_t enable) {
   return DF_OK;
 }
 
-extern "C" df_status df_profile_read(df_graph *g, double *total_ms, int64_t *n_launches) {
-  ENTER(g);
+// Sum and release the pending timings of `actor` (all of them when all_actors).
+static df_status read_timings(df_graph *g, bool all_actors, int actor, double *total_ms, int64_t *n_launches) {
   HIPCHK(g, hipStreamSynchronize(g->stream));
   double t = 0.0;
+  int64_t n = 0;
+  std::vector<df_graph::ProfEntry> keep;
   for (auto &pe : g->prof_pending) {
+    if (!all_actors && pe.actor != actor) {
+      keep.push_back(pe);
+      continue;
+    }
     float ms = 0.f;
-    HIPCHK(g, hipEventElapsedTime(&ms, pe.first, pe.second));
+    HIPCHK(g, hipEventElapsedTime(&ms, pe.start, pe.stop));
     t += ms;
-    g->prof_pool.push_back(pe.first);
-    g->prof_pool.push_back(pe.second);
+    ++n;
+    g->prof_pool.push_back(pe.start);
+    g->prof_pool.push_back(pe.stop);
   }
   if (total_ms) *total_ms = t;
-  if (n_launches) *n_launches = (int64_t)g->prof_pending.size();
-  g->prof_pending.clear();
+  if (n_launches) *n_launches = n;
+  g->prof_pending.swap(keep);
   return DF_OK;
+}
+
+extern "C" df_status df_profile_read(df_graph *g, double *total_ms, int64_t *n_launches) {
+  ENTER(g);
+  return read_timings(g, true, -1, total_ms, n_launches);
+}
+
+extern "C" df_status df_profile_read_actor(df_graph *g, int32_t actor, double *total_ms, int64_t *n_launches) {
+  ENTER(g);
+  if (actor < 0 || actor >= (int)g->actors.size()) return fail(g, DF_EINVAL, "bad actor id %d", actor);
+  return read_timings(g, false, actor, total_ms, n_launches);
 }

@@ -55,6 +55,8 @@ struct Actor {
   int64_t *emit_off = nullptr;
   uint32_t *bits = nullptr;  // bit-packed opened masks of a chunk of firings
   int64_t cnt_cap = 0;
+  // Gauss / Thres / Med
+  df_frame_params fp{};
 };
 
 struct Persistent;  // multi-instance batching state
@@ -76,7 +78,11 @@ struct df_graph {
   int blocks_per_cu = 0;          // persistent grid; 0 = default
   dfh::Persistent *pers = nullptr;
   bool prof = false;                                   // record body-kernel events
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
+  struct ProfEntry {
+    hipEvent_t start, stop;
+    int actor;  // -1: not one actor's launch (persistent batches)
+  };
+  std::vector<ProfEntry> prof_pending;
   std::vector<hipEvent_t> prof_pool;
 };
 
@@ -89,7 +95,8 @@ df_status dpd_admit(df_graph *g, Actor &a, int64_t n, int64_t *n_adm);
 df_status dpd_enqueue(df_graph *g, Actor &a, int64_t n);
 void destroy_persistent(df_graph *g);
 // Event pair around body kernels when profiling is enabled (no-op otherwise).
-hipError_t prof_begin(df_graph *g);
-hipError_t prof_pair(df_graph *g, KTiming *t);   // events for one timed launch (none if profiling is off)
+hipError_t prof_begin(df_graph *g, int actor = -1);
+// events for one timed launch of `actor` (none if profiling is off)
+hipError_t prof_pair(df_graph *g, KTiming *t, int actor = -1);
 hipError_t prof_end(df_graph *g);
 }  // namespace dfh

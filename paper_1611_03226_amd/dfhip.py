@@ -18,9 +18,12 @@ DF_OK, DF_EINVAL, DF_EAGAIN, DF_ENOMEM, DF_ESTATE, DF_EDEVICE, DF_ECONTROL = 0, 
 STATUS_NAMES = {0: "DF_OK", -1: "DF_EINVAL", -2: "DF_EAGAIN", -3: "DF_ENOMEM", -4: "DF_ESTATE",
                 -5: "DF_EDEVICE", -6: "DF_ECONTROL"}
 DF_C64, DF_U8, DF_I32, DF_I64 = 1, 2, 3, 4
-DF_ACTOR_DPD, DF_ACTOR_MOTION = 1, 2
+DF_ACTOR_DPD, DF_ACTOR_MOTION, DF_ACTOR_GAUSS5, DF_ACTOR_THRES, DF_ACTOR_MED5 = 1, 2, 3, 4, 5
 DF_DPD_CTRL, DF_DPD_IN, DF_DPD_OUT = 0, 1, 2
 DF_MD_CUR, DF_MD_PREV, DF_MD_MASK, DF_MD_INDEX = 0, 1, 2, 3
+DF_GAUSS_IN, DF_GAUSS_OUT, DF_GAUSS_OUT2 = 0, 1, 2
+DF_THRES_CUR, DF_THRES_PREV, DF_THRES_OUT = 0, 1, 2
+DF_MED_IN, DF_MED_OUT = 0, 1
 DF_HIST_BRANCH, DF_HIST_SHARED = 0, 1
 DF_FIRE_PARTIAL = 1
 DF_FIRE_PERSISTENT, DF_FIRE_GRAPH = 1, 2
@@ -44,6 +47,10 @@ class MotionParams(C.Structure):
                 ("min_changed_permille", C.c_int32), ("self_delay", C.c_int32)]
 
 
+class FrameParams(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("rate", C.c_int32), ("threshold", C.c_int32)]
+
+
 _P = C.c_void_p
 _I32, _I64 = C.c_int32, C.c_int64
 _SIGS = {
@@ -63,6 +70,7 @@ _SIGS = {
     "df_set_tile": ([_P, _I32, _I32, _I32], _I32),
     "df_profile_enable": ([_P, _I32], _I32),
     "df_profile_read": ([_P, C.POINTER(C.c_double), C.POINTER(_I64)], _I32),
+    "df_profile_read_actor": ([_P, _I32, C.POINTER(C.c_double), C.POINTER(_I64)], _I32),
     "df_debug_last_batch": ([_P, _I32, _P, _P, _P, _I64, C.POINTER(_I64)], _I32),
     "df_dpd_forward": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
     "df_dpd_coeff_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32, _P, _I64], _I32),
@@ -221,6 +229,13 @@ def df_profile_read(g):
     """(summed body-kernel milliseconds, launches) since the last read."""
     t, n = C.c_double(), C.c_int64()
     _check(_lib.df_profile_read(g, C.byref(t), C.byref(n)), g)
+    return t.value, n.value
+
+
+def df_profile_read_actor(g, actor: int):
+    """(summed body-kernel milliseconds, launches) of one actor since the last read."""
+    t, n = C.c_double(), C.c_int64()
+    _check(_lib.df_profile_read_actor(g, actor, C.byref(t), C.byref(n)), g)
     return t.value, n.value
 
 

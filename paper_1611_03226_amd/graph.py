@@ -41,6 +41,27 @@ class MotionChain:
     height: int
 
 
+@dataclass
+class PaperMotionPipeline:
+    """Src -> Gauss -> {cur, delayed} -> Thres -> Med -> Sink (Sec. 4.1)."""
+    gauss: int
+    thres: int
+    med: int
+    inp: int       # host writes frames
+    g_cur: int     # Gauss -> Thres
+    g_delayed: int # Gauss -> Thres, one initial (all-zero) token
+    thr: int       # Thres -> Med
+    out: int       # host reads frames
+    width: int
+    height: int
+    rate: int
+
+    def fire_all(self, G: "Graph", n_firings: int) -> None:
+        """Fire each actor n_firings times, in pipeline order."""
+        for a in (self.gauss, self.thres, self.med):
+            G.fire(a, n_firings)
+
+
 class Graph:
     def __init__(self, device: int = 0, stream=None):
         self.g = D.df_graph_create(device, stream)
@@ -85,6 +106,14 @@ class Graph:
     def sync(self):
         D.df_sync(self.g)
 
+    def profile(self, enable=True):
+        D.df_profile_enable(self.g, enable)
+
+    def profile_read(self, actor=None):
+        if actor is None:
+            return D.df_profile_read(self.g)
+        return D.df_profile_read_actor(self.g, actor)
+
     def set_tile(self, tile=0, k=0, bpc=0):
         D.df_set_tile(self.g, tile, k, bpc)
 
@@ -120,3 +149,33 @@ class Graph:
         D.df_connect(self.g, a, D.DF_MD_MASK, fm)
         D.df_connect(self.g, a, D.DF_MD_INDEX, fi)
         return MotionChain(a, fc, fp, fm, fi, width, height)
+
+    def paper_motion_pipeline(self, width, height, threshold=20, rate=4, cap=0,
+                              second_output=True, cap_io=0) -> PaperMotionPipeline:
+        """Gauss, Thres and Med actors with their five channels; the three
+        inner channels hold ``cap`` frames (0: 16), the host-facing input and
+        output channels ``cap_io`` (0: same as cap).  With
+        second_output=False Gauss writes one channel only and Thres's
+        previous-frame channel must be fed by the caller."""
+        wh = width * height
+        p = D.FrameParams(width, height, rate, threshold)
+        ga = D.df_actor_create(self.g, D.DF_ACTOR_GAUSS5, p)
+        ta = D.df_actor_create(self.g, D.DF_ACTOR_THRES, p)
+        ma = D.df_actor_create(self.g, D.DF_ACTOR_MED5, p)
+        c = cap or 16
+        cio = cap_io or c
+        f_in = self.fifo(D.DF_U8, wh, cio)
+        f_cur = self.fifo(D.DF_U8, wh, c)
+        f_del = self.fifo(D.DF_U8, wh, c, 1)         # the one-frame delay
+        f_thr = self.fifo(D.DF_U8, wh, c)
+        f_out = self.fifo(D.DF_U8, wh, cio)
+        D.df_connect(self.g, ga, D.DF_GAUSS_IN, f_in)
+        D.df_connect(self.g, ga, D.DF_GAUSS_OUT, f_cur)
+        if second_output:
+            D.df_connect(self.g, ga, D.DF_GAUSS_OUT2, f_del)
+        D.df_connect(self.g, ta, D.DF_THRES_CUR, f_cur)
+        D.df_connect(self.g, ta, D.DF_THRES_PREV, f_del)
+        D.df_connect(self.g, ta, D.DF_THRES_OUT, f_thr)
+        D.df_connect(self.g, ma, D.DF_MED_IN, f_thr)
+        D.df_connect(self.g, ma, D.DF_MED_OUT, f_out)
+        return PaperMotionPipeline(ga, ta, ma, f_in, f_cur, f_del, f_thr, f_out, width, height, rate)

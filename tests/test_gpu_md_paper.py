@@ -1,0 +1,189 @@
+"""GPU parity of the paper's motion-detection pipeline (Sec. 4.1) through the
+C ABI: Gauss, Thres and Med as three static actors joined by device FIFO
+channels (one holding the one-frame delay), every output frame bit-exact
+against the oracle, on the word path (width a multiple of 4) and the byte
+path, across ring wrap-around, batches of uneven size and partial admission."""
+import numpy as np
+import pytest
+
+from oracle import md_paper as omd
+from workloads import paper_motion
+
+from helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _pow2(n):
+    p = 1
+    while p < n:
+        p <<= 1
+    return p
+
+
+def run_pipeline(frames, threshold=20, rate=4, batches=None, cap=0):
+    """Push all frames, fire Gauss/Thres/Med in the given firing batches
+    (default: all whole firings at once), pop every output frame."""
+    from paper_1611_03226_amd.graph import Graph
+    n, H, W = frames.shape
+    nf = n // rate
+    batches = batches or [nf]
+    assert sum(batches) == nf
+    cap = cap or _pow2(n + 1)
+    out = np.zeros((nf * rate, H, W), np.uint8)
+    with Graph(0) as G:
+        p = G.paper_motion_pipeline(W, H, threshold, rate, cap=cap)
+        pos = got = 0
+        for b in batches:
+            k = b * rate
+            G.push(p.inp, frames[pos:pos + k])
+            pos += k
+            p.fire_all(G, b)
+            got += G.pop(p.out, out[got:got + k])
+        assert got == nf * rate
+        # token conservation: every channel was read as often as written
+        for f in (p.inp, p.g_cur, p.thr, p.out):
+            r, w, _ = G.status(f)
+            assert r == w == nf * rate
+        r, w, _ = G.status(p.g_delayed)
+        assert (r, w) == (nf * rate, nf * rate + 1)      # the initial token stays one ahead
+        G.sync()
+    return out
+
+
+def _expect(frames, threshold=20):
+    return omd.paper_motion_direct(frames, threshold)
+
+
+def test_paper_size_matches_oracle():
+    say("md_paper 320x240 rate 4, 24 frames in batches 2,1,3")
+    w = paper_motion(seed=21, n_frames=24)
+    out = run_pipeline(w.frames, batches=[2, 1, 3])
+    assert np.array_equal(out, _expect(w.frames))
+
+
+@pytest.mark.parametrize("W,H", [(4, 9), (8, 5), (36, 23), (320, 50), (37, 23), (13, 7), (1, 1), (7, 4),
+                                 (16, 3), (5, 17)])
+def test_ragged_sizes(W, H):
+    say(f"md_paper ragged {W}x{H}")
+    rng = np.random.default_rng(W * 1000 + H)
+    frames = rng.integers(0, 256, (12, H, W)).astype(np.uint8)
+    frames[1::2] = np.clip(frames[0::2].astype(int) + rng.integers(-30, 31, (6, H, W)), 0, 255)
+    out = run_pipeline(frames, threshold=12, rate=4, batches=[1, 2])
+    assert np.array_equal(out, _expect(frames, 12))
+
+
+def test_ring_wrap_with_small_capacity():
+    say("md_paper ring wrap: capacity 8 frames, 10 firings of rate 4 one at a time")
+    w = paper_motion(seed=22, n_frames=40, width=64, height=48)
+    out = run_pipeline(w.frames, batches=[1] * 10, cap=8)
+    assert np.array_equal(out, _expect(w.frames))
+
+
+@pytest.mark.parametrize("threshold", [0, 255])
+def test_threshold_extremes(threshold):
+    say(f"md_paper threshold {threshold}")
+    w = paper_motion(seed=23, n_frames=8, width=96, height=40)
+    out = run_pipeline(w.frames, threshold=threshold)
+    exp = _expect(w.frames, threshold)
+    assert np.array_equal(out, exp)
+    if threshold == 255:
+        assert not out.any()
+
+
+def test_rate_one_equals_rate_four():
+    say("md_paper rate 1 vs rate 4")
+    w = paper_motion(seed=24, n_frames=12, width=64, height=32)
+    a = run_pipeline(w.frames, rate=1, batches=[5, 7])
+    b = run_pipeline(w.frames, rate=4, batches=[3])
+    assert np.array_equal(a, b)
+
+
+def test_single_actors_against_oracle():
+    """Each body alone, fed and drained by the host."""
+    from paper_1611_03226_amd import dfhip as D
+    from paper_1611_03226_amd.graph import Graph
+    rng = np.random.default_rng(25)
+    for W, H in [(320, 240), (30, 11)]:
+        say(f"md_paper single actors {W}x{H}")
+        a = rng.integers(0, 256, (8, H, W)).astype(np.uint8)
+        b = rng.integers(0, 256, (8, H, W)).astype(np.uint8)
+        with Graph(0) as G:
+            p = D.FrameParams(W, H, 4, 40)
+            wh = W * H
+            ga = D.df_actor_create(G.g, D.DF_ACTOR_GAUSS5, p)
+            ta = D.df_actor_create(G.g, D.DF_ACTOR_THRES, p)
+            ma = D.df_actor_create(G.g, D.DF_ACTOR_MED5, p)
+            f = [G.fifo(D.DF_U8, wh, 16) for _ in range(7)]
+            D.df_connect(G.g, ga, D.DF_GAUSS_IN, f[0])
+            D.df_connect(G.g, ga, D.DF_GAUSS_OUT, f[1])      # second output left unconnected
+            D.df_connect(G.g, ta, D.DF_THRES_CUR, f[2])
+            D.df_connect(G.g, ta, D.DF_THRES_PREV, f[3])
+            D.df_connect(G.g, ta, D.DF_THRES_OUT, f[4])
+            D.df_connect(G.g, ma, D.DF_MED_IN, f[5])
+            D.df_connect(G.g, ma, D.DF_MED_OUT, f[6])
+            G.push(f[0], a)
+            G.push(f[2], a)
+            G.push(f[3], b)
+            G.push(f[5], a)
+            for act in (ga, ta, ma):
+                assert G.fire(act, 2) == 2
+            g = np.zeros_like(a)
+            t = np.zeros_like(a)
+            m = np.zeros_like(a)
+            assert G.pop(f[1], g) == 8 and G.pop(f[4], t) == 8 and G.pop(f[6], m) == 8
+            G.sync()
+        for k in range(8):
+            assert np.array_equal(g[k], omd.gauss5(a[k]))
+            assert np.array_equal(t[k], omd.thres(a[k], b[k], 40))
+            assert np.array_equal(m[k], omd.med5(a[k]))
+
+
+def test_admission_is_all_or_nothing():
+    from paper_1611_03226_amd import dfhip as D
+    from paper_1611_03226_amd.graph import Graph
+    say("md_paper admission")
+    w = paper_motion(seed=26, n_frames=10, width=32, height=16)
+    with Graph(0) as G:
+        p = G.paper_motion_pipeline(32, 16, 20, 4, cap=16)
+        G.push(p.inp, w.frames)                  # 10 frames: two whole firings
+        with pytest.raises(D.DFError) as e:
+            G.fire(p.gauss, 3)
+        assert e.value.code == D.DF_EAGAIN
+        assert G.status(p.inp)[:2] == (0, 10)    # nothing changed
+        assert G.fire(p.gauss, 3, partial=True) == 2
+        assert G.fire(p.thres, 2) == 2
+        # Med's output channel holds 16 frames; a third firing's input is missing
+        assert G.fire(p.med, 5, partial=True) == 2
+        out = np.zeros((8, 16, 32), np.uint8)
+        assert G.pop(p.out, out) == 8
+        G.sync()
+    assert np.array_equal(out, _expect(w.frames[:8]))
+
+
+def test_profile_per_actor():
+    say("md_paper per-actor profile")
+    from paper_1611_03226_amd.graph import Graph
+    w = paper_motion(seed=27, n_frames=16, width=64, height=32)
+    with Graph(0) as G:
+        p = G.paper_motion_pipeline(64, 32, 20, 4, cap=32)
+        G.profile(True)
+        G.push(p.inp, w.frames)
+        p.fire_all(G, 4)
+        ms_g, n_g = G.profile_read(p.gauss)
+        ms_all, n_all = G.profile_read()
+        assert n_g == 1 and ms_g > 0
+        assert n_all == 2 and ms_all > 0          # Thres and Med still pending
+        G.profile(False)
+
+
+def test_full_size_sampled_frames():
+    """4096 frames of 320x240 in one batch of 1024 firings (the bench's
+    launch configuration); sampled output frames against the oracle."""
+    say("md_paper 4096 frames 320x240, one batch")
+    w = paper_motion(seed=28, n_frames=4096)
+    out = run_pipeline(w.frames)
+    for k in (0, 1, 2, 3, 4, 511, 1024, 2047, 3000, 4095):
+        prev = omd.gauss5(w.frames[k - 1]) if k else np.zeros((240, 320), np.uint8)
+        want = omd.med5(omd.thres(omd.gauss5(w.frames[k]), prev, 20))
+        assert np.array_equal(out[k], want), k

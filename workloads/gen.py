@@ -29,7 +29,7 @@ import numpy as np
 __all__ = [
     "DPDWorkload", "MotionWorkload", "InstancesWorkload", "AdaptWorkload",
     "complex_gaussian", "ofdm_like", "dpd_coeffs", "dpd_chain", "dpd_scale",
-    "dpd_random", "motion", "dpd_instances", "adaptation", "pa_coeffs",
+    "dpd_random", "motion", "paper_motion", "dpd_instances", "adaptation", "pa_coeffs",
     "papr_db",
 ]
 
@@ -210,6 +210,17 @@ def motion(seed: int = 3, n_frames: int = 300, width: int = 1920, height: int = 
     return MotionWorkload(frames, width, height,
                           name=f"motion_{n_frames}x{width}x{height}",
                           notes={"visible_per_segment": visible.tolist()})
+
+
+def paper_motion(seed: int = 6, n_frames: int = 64, width: int = 320, height: int = 240) -> MotionWorkload:
+    """Frames for the paper's motion-detection pipeline: 8-bit grayscale at
+    the paper's 320x240 (one 76,800-byte token per frame), the same recipe as
+    ``motion`` with rectangles scaled to the frame (16..80 pixels a side,
+    speed up to 6 pixels per frame, noise sigma 3)."""
+    w = motion(seed=seed, n_frames=n_frames, width=width, height=height, n_tracks=8, noise_sigma=3.0,
+               segment=20, rect_min=min(16, width, height), rect_max=min(80, width, height), vmax=6)
+    w.name = f"paper_motion_{n_frames}x{width}x{height}"
+    return w
 
 
 # ---------------------------------------------------------------- batched instances
