@@ -504,6 +504,69 @@ def summarize_pmc(fetch_csv, write_csv, bench_json):
     print("\n".join(lines))
 
 
+MD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "md_paper_pipeline_traffic.md")
+MD_KERNELS = (("gauss", "k_gauss5_w<4, true, true>"), ("thres", "k_thres_v"), ("med", "k_med5_w<4, true>"))
+
+
+def summarize_pmc_md(fetch_csv, write_csv, bench_json):
+    """Traffic summary of the paper-pipeline kernels (Gauss, Thres, Med) from
+    two rocprofv3 --pmc runs, scaled by the stream copy like summarize_pmc."""
+    import csv
+
+    def per_dispatch(path, counter):
+        vals = {}
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                name = row["Kernel_Name"]
+                key = "copy" if "k_stream_copy" in name else None
+                for k, pat in MD_KERNELS:
+                    if pat in name:
+                        key = k
+                if key:
+                    vals.setdefault(key, {}).setdefault(row["Dispatch_Id"], 0.0)
+                    vals[key][row["Dispatch_Id"]] += float(row["Counter_Value"])
+        return {k: (sum(v.values()) / len(v), len(v)) for k, v in vals.items()}
+
+    with open(bench_json) as fh:
+        line = [ln for ln in fh if ln.startswith("{")][-1]
+    b = json.loads(line)
+    copy_bytes = b["hbm_copy"]["bytes_read"]
+    f = per_dispatch(fetch_csv, "FETCH_SIZE")
+    w = per_dispatch(write_csv, "WRITE_SIZE")
+    fr = f["copy"][0] * 1024 / copy_bytes
+    fw = w["copy"][0] * 1024 / copy_bytes
+    cmd = ("rocprofv3 --pmc {c} --kernel-include-regex 'k_gauss5|k_thres|k_med5|k_stream_copy' -d pmc_{l} -o {l} "
+           "--output-format csv -- python3 /root/repo/bench.py --no-cpu --only md_paper --no-per-firing --steps 5 "
+           "--warmup 2 > {l}.json")
+    lines = [
+        "# HBM traffic of the paper's motion-detection pipeline kernels, 4096 frames of 320x240 per launch",
+        "",
+        "Commands (on the GPU host, from the repository root; `cd /tmp && export TMPDIR=/tmp` first):",
+        "",
+        "    " + cmd.format(c="FETCH_SIZE", l="fetch"),
+        "    " + cmd.format(c="WRITE_SIZE", l="write"),
+        "    python3 /root/repo/bench.py --summarize-pmc-md pmc_fetch/fetch_counter_collection.csv "
+        "pmc_write/write_counter_collection.csv fetch.json",
+        "",
+        f"Stream copy of {copy_bytes} bytes: FETCH_SIZE {f['copy'][0]:.1f} KiB, WRITE_SIZE {w['copy'][0]:.1f} KiB "
+        f"per dispatch; scale factors {fr:.4f} (read) and {fw:.4f} (write) counter bytes per byte moved.",
+        "",
+        "| kernel | dispatches | HBM read B/launch | HBM write B/launch | algorithmic B/launch | traffic / algorithmic |",
+        "|---|---|---|---|---|---|",
+    ]
+    for k, pat in MD_KERNELS:
+        rd = f[k][0] * 1024 / fr
+        wr = w[k][0] * 1024 / fw
+        alg = b["md_paper"]["kernels"][k]["algorithmic_bytes"]
+        lines.append(f"| {pat} | {f[k][1]} / {w[k][1]} | {rd:.0f} | {wr:.0f} | {alg} | {(rd + wr) / alg:.4f} |")
+    lines.append("")
+    with open(MD_TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -517,9 +580,14 @@ def main():
                     help="stream-copy reference size in MiB (bandwidth and traffic-counter reference; 0: off)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
                     help="write the traffic summary from two rocprofv3 --pmc runs of this script (no GPU)")
+    ap.add_argument("--summarize-pmc-md", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="same for the paper-pipeline kernels (runs with --only md_paper)")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
+        return
+    if args.summarize_pmc_md:
+        summarize_pmc_md(*args.summarize_pmc_md)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on one "

@@ -4,14 +4,15 @@
 // threshold) and Med (5-pixel median).  Each batch covers n_frames
 // consecutive tokens of the actor's channels; see MdpArgs.
 //
-// Word path (width a multiple of 4): a work item is one 4-pixel word column
-// of kRun consecutive output rows of one frame; consecutive lanes take
-// consecutive columns, so every row load of a wave is one contiguous run of
-// words.  The vertical window slides down the item in registers; the two
-// neighbouring words give the horizontal halo, with the nearest in-frame
-// pixel replicated at the left and right frame edges.  Pixels are processed
-// four per word in 16-bit lanes (md_swar.h).  Any other width takes the byte
-// path: one thread per pixel.
+// Word path (width a multiple of 4): a work item is a strip of V words (4V
+// pixels; V = 4 when the width is a multiple of 16, else 1) of kRun
+// consecutive output rows of one frame; consecutive lanes take consecutive
+// strips, so every row load of a wave is one contiguous run.  The vertical
+// window slides down the item in registers; the words left and right of the
+// strip give the horizontal halo, with the nearest in-frame pixel repeated
+// at the left and right frame edges.  Pixels are processed four per word in
+// 16-bit lanes (md_swar.h).  Any other width takes the byte path: one thread
+// per pixel.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -22,6 +23,7 @@ namespace dfh {
 namespace {
 
 constexpr int kMdThreads = 256;
+constexpr int kWordThreads = 64;           // word-path workgroup: one wave, little padding per frame
 constexpr int kRun = 16;                   // output rows per word-path work item
 constexpr int64_t kMaxBlocks = 1 << 23;    // per launch: threads stay below 2^31
 
@@ -34,59 +36,134 @@ __device__ inline uint8_t *out_frame(uint8_t *ring, const int64_t *idx, int64_t 
   return ring + ((idx[1] + f) & mask) * WH;
 }
 
-// Word column `cx` of row `row` with its left and right neighbour words; at
-// a frame edge the missing neighbour repeats the edge pixel.
-struct Nbr {
-  uint32_t l, m, r;
+typedef __attribute__((address_space(1))) uint32_t gu32;
+
+// A global pointer that is the same in every lane, held in scalar registers,
+// so that loads and stores use the scalar base + 32-bit vector offset form.
+__device__ inline gu32 *uniform_ptr(const void *p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (gu32 *)(((uint64_t)hi << 32) | lo);
+}
+
+// Frame and part of a word-path workgroup.  Workgroups are dispatched to the
+// 8 XCDs round robin (workgroup b to XCD b % 8), each XCD with its own L2.
+// Groups of 8 frames are laid out so that all bpf workgroups of a frame get
+// the same b % 8: the rows two neighbouring parts of a frame share (the
+// vertical halo) are then read through one L2.  A last group of fewer than
+// 8 frames keeps the plain order.
+struct FramePart {
+  uint32_t frame, part;
 };
 
-__device__ inline Nbr load_nbr(const uint32_t *row, int cx, int Wq) {
-  Nbr n;
-  n.m = row[cx];
-  n.l = cx > 0 ? row[cx - 1] : (n.m & 0xFFu) * 0x01010101u;
-  n.r = cx < Wq - 1 ? row[cx + 1] : (n.m >> 24) * 0x01010101u;
-  return n;
+__device__ inline FramePart frame_part(uint32_t b, uint32_t bpf) {
+  const uint32_t nf = gridDim.x / bpf, group = 8 * bpf;
+  const uint32_t g = b / group, rem = b % group;
+  if (8 * (g + 1) <= nf) return {8 * g + rem % 8, rem / 8};
+  return {b / bpf, b % bpf};
 }
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) u32x4 gu32x4;
+
+// Word columns of a word-path strip: its first word c0, V words, and the
+// clamped neighbour words; at a frame edge the perm selectors repeat the
+// edge pixel instead of using the missing neighbour, so every load is
+// unconditional.
+template <int V>
+struct Strip {
+  uint32_t c0, cl, cr;
+  bool left_edge, right_edge;
+  __device__ Strip(int s, int Wq) {
+    c0 = (uint32_t)(s * V);
+    left_edge = s == 0;
+    right_edge = (s + 1) * V == Wq;
+    cl = left_edge ? c0 : c0 - 1;
+    cr = right_edge ? c0 + V - 1 : c0 + V;
+  }
+  // w[0] = left neighbour word, w[1..V] = the strip, w[V+1] = right neighbour
+  __device__ void load(const gu32 *src, uint32_t row, uint32_t (&w)[V + 2]) const {
+    if constexpr (V == 4) {
+      const u32x4 m = *(const gu32x4 *)(src + row + c0);
+      w[1] = m.x;
+      w[2] = m.y;
+      w[3] = m.z;
+      w[4] = m.w;
+    } else {
+      w[1] = src[row + c0];
+    }
+    w[0] = src[row + cl];
+    w[V + 1] = src[row + cr];
+  }
+  __device__ void store(gu32 *dst, uint32_t row, const uint32_t (&v)[V]) const {
+    if constexpr (V == 4) {
+      u32x4 m;
+      m.x = v[0];
+      m.y = v[1];
+      m.z = v[2];
+      m.w = v[3];
+      __builtin_nontemporal_store(m, (gu32x4 *)(dst + row + c0));
+    } else {
+      __builtin_nontemporal_store(v[0], dst + row + c0);
+    }
+  }
+};
 
 // ------------------------------------------------------------------ Gauss
 
-__global__ __launch_bounds__(kMdThreads) void k_gauss5_w(MdpArgs a, int64_t f0, int32_t n_runs, int32_t bpf) {
-  const int64_t f = f0 + blockIdx.x / (uint32_t)bpf;
-  const int32_t local = (int32_t)(blockIdx.x % (uint32_t)bpf) * kMdThreads + (int32_t)threadIdx.x;
-  const int32_t Wq = a.W >> 2;
-  const int32_t cx = local % Wq, run = local / Wq;
+// FULL: H >= kRun, and the last run of a strip column starts at H - kRun
+// (overlapping its predecessor, whose rows it rewrites with the same
+// values), so no row of the loop is guarded.  TWO: write both outputs.
+template <int V, bool TWO, bool FULL>
+__global__ __launch_bounds__(kWordThreads) void k_gauss5_w(MdpArgs a, int64_t f0, int32_t n_runs, int32_t bpf) {
+  const FramePart fp = frame_part(blockIdx.x, (uint32_t)bpf);
+  const int64_t f = f0 + __builtin_amdgcn_readfirstlane(fp.frame);
+  const int32_t local = (int32_t)__builtin_amdgcn_readfirstlane(fp.part) * kWordThreads + (int32_t)threadIdx.x;
+  const int32_t Wq = a.W >> 2, Ws = Wq / V;
+  const int32_t sx = local % Ws, run = local / Ws;
   if (run >= n_runs) return;
   const int64_t WH = (int64_t)a.W * a.H;
-  const uint32_t *src = (const uint32_t *)in_frame(a.in0, a.in0_idx, a.in0_mask, f, WH);
-  uint32_t *dst = (uint32_t *)out_frame(a.out0, a.out0_idx, a.out0_mask, f, WH);
-  uint32_t *dst2 = a.out1 ? (uint32_t *)out_frame(a.out1, a.out1_idx, a.out1_mask, f, WH) : nullptr;
+  const gu32 *src = uniform_ptr(in_frame(a.in0, a.in0_idx, a.in0_mask, f, WH));
+  gu32 *dst = uniform_ptr(out_frame(a.out0, a.out0_idx, a.out0_mask, f, WH));
+  gu32 *dst2 = TWO ? uniform_ptr(out_frame(a.out1, a.out1_idx, a.out1_mask, f, WH)) : nullptr;
   const int H = a.H;
-  const int y0 = run * kRun;
+  const int y0 = FULL ? min(run * kRun, H - kRun) : run * kRun;
   const int yend = min(y0 + kRun, H);
-  uint32_t he[5] = {0, 0, 0, 0, 0}, ho[5] = {0, 0, 0, 0, 0}, mid[5] = {0, 0, 0, 0, 0};
+  const Strip<V> st(sx, Wq);
+  const uint32_t sel_l0 = swar::win2_left(st.left_edge), sel_rV = swar::win2_right(st.right_edge);
+  const uint32_t sel_l = swar::win2_left(false), sel_r = swar::win2_right(false);
+  uint32_t he[V][5] = {}, ho[V][5] = {}, mid[V][5] = {};
 #pragma unroll
   for (int r = 0; r < kRun + 4; ++r) {
-    const int yy = min(max(y0 - 2 + r, 0), H - 1);
-    const Nbr n = load_nbr(src + (int64_t)yy * Wq, cx, Wq);
+    uint32_t w[V + 2];
+    st.load(src, (uint32_t)(min(max(y0 - 2 + r, 0), H - 1) * Wq), w);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      he[k] = he[k + 1];
-      ho[k] = ho[k + 1];
-      mid[k] = mid[k + 1];
+    for (int j = 0; j < V; ++j) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        he[j][k] = he[j][k + 1];
+        ho[j][k] = ho[j][k + 1];
+        mid[j][k] = mid[j][k + 1];
+      }
+      // window bytes (p-2, p-1, p0, p1 | p2, p3, p4, p5) of word j
+      swar::hsum5(swar::perm(w[j + 1], w[j], j == 0 ? sel_l0 : sel_l),
+                  swar::perm(w[j + 2], w[j + 1], j == V - 1 ? sel_rV : sel_r), &he[j][4], &ho[j][4]);
+      mid[j][4] = w[j + 1];
     }
-    // window bytes (p-2, p-1, p0, p1 | p2, p3, p4, p5)
-    swar::hsum5(swar::funnel(n.m, n.l, 16), swar::funnel(n.r, n.m, 16), &he[4], &ho[4]);
-    mid[4] = n.m;
     if (r >= 4) {
       const int y = y0 + r - 4;
-      if (y < yend) {
-        uint32_t v = mid[2];
-        if (y >= 2 && y < H - 2)
-          v = swar::interleave(swar::vround5(he[0], he[1], he[2], he[3], he[4]),
-                               swar::vround5(ho[0], ho[1], ho[2], ho[3], ho[4]));
-        const int64_t o = (int64_t)y * Wq + cx;
-        __builtin_nontemporal_store(v, dst + o);
-        if (dst2) __builtin_nontemporal_store(v, dst2 + o);
+      if (FULL || y < yend) {
+        const bool filtered = y >= 2 && y < H - 2;
+        uint32_t v[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          const uint32_t filt = swar::interleave(swar::vround5(he[j][0], he[j][1], he[j][2], he[j][3], he[j][4]),
+                                                 swar::vround5(ho[j][0], ho[j][1], ho[j][2], ho[j][3], ho[j][4]));
+          v[j] = filtered ? filt : mid[j][2];
+        }
+        st.store(dst, (uint32_t)(y * Wq), v);
+        if (TWO) st.store(dst2, (uint32_t)(y * Wq), v);
       }
     }
   }
@@ -117,8 +194,7 @@ __global__ __launch_bounds__(kMdThreads) void k_gauss5_b(MdpArgs a, int64_t f0, 
 // ------------------------------------------------------------------ Thres
 
 __global__ __launch_bounds__(kMdThreads) void k_thres_v(MdpArgs a, int64_t f0, int32_t bpf) {
-  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-  const int64_t f = f0 + blockIdx.x / (uint32_t)bpf;
+  const int64_t f = f0 + __builtin_amdgcn_readfirstlane(blockIdx.x / (uint32_t)bpf);
   const int64_t q = (int64_t)(blockIdx.x % (uint32_t)bpf) * kMdThreads + threadIdx.x;
   const int64_t WH = (int64_t)a.W * a.H;
   if (q >= WH / 16) return;
@@ -146,36 +222,47 @@ __global__ __launch_bounds__(kMdThreads) void k_thres_b(MdpArgs a, int64_t f0, i
 
 // ------------------------------------------------------------------ Med
 
-__global__ __launch_bounds__(kMdThreads) void k_med5_w(MdpArgs a, int64_t f0, int32_t n_runs, int32_t bpf) {
-  const int64_t f = f0 + blockIdx.x / (uint32_t)bpf;
-  const int32_t local = (int32_t)(blockIdx.x % (uint32_t)bpf) * kMdThreads + (int32_t)threadIdx.x;
-  const int32_t Wq = a.W >> 2;
-  const int32_t cx = local % Wq, run = local / Wq;
+template <int V, bool FULL>
+__global__ __launch_bounds__(kWordThreads) void k_med5_w(MdpArgs a, int64_t f0, int32_t n_runs, int32_t bpf) {
+  const FramePart fp = frame_part(blockIdx.x, (uint32_t)bpf);
+  const int64_t f = f0 + __builtin_amdgcn_readfirstlane(fp.frame);
+  const int32_t local = (int32_t)__builtin_amdgcn_readfirstlane(fp.part) * kWordThreads + (int32_t)threadIdx.x;
+  const int32_t Wq = a.W >> 2, Ws = Wq / V;
+  const int32_t sx = local % Ws, run = local / Ws;
   if (run >= n_runs) return;
   const int64_t WH = (int64_t)a.W * a.H;
-  const uint32_t *src = (const uint32_t *)in_frame(a.in0, a.in0_idx, a.in0_mask, f, WH);
-  uint32_t *dst = (uint32_t *)out_frame(a.out0, a.out0_idx, a.out0_mask, f, WH);
+  const gu32 *src = uniform_ptr(in_frame(a.in0, a.in0_idx, a.in0_mask, f, WH));
+  gu32 *dst = uniform_ptr(out_frame(a.out0, a.out0_idx, a.out0_mask, f, WH));
   const int H = a.H;
-  const int y0 = run * kRun;
+  const int y0 = FULL ? min(run * kRun, H - kRun) : run * kRun;
   const int yend = min(y0 + kRun, H);
-  uint32_t up = 0, lc = 0, mc = 0, rc = 0;   // row above; centre row and its neighbour words
+  const Strip<V> st(sx, Wq);
+  const uint32_t sel_l0 = swar::win1_left(st.left_edge), sel_rV = swar::win1_right(st.right_edge);
+  const uint32_t sel_l = swar::win1_left(false), sel_r = swar::win1_right(false);
+  uint32_t up[V] = {}, cen[V + 2] = {};   // row above the centre row; centre row with its neighbour words
 #pragma unroll
   for (int r = 0; r < kRun + 2; ++r) {
-    const int yy = min(max(y0 - 1 + r, 0), H - 1);
-    const Nbr n = load_nbr(src + (int64_t)yy * Wq, cx, Wq);
+    uint32_t w[V + 2];
+    st.load(src, (uint32_t)(min(max(y0 - 1 + r, 0), H - 1) * Wq), w);
     if (r >= 2) {
       const int y = y0 + r - 2;
-      if (y < yend) {
-        // left neighbours (p-1, p0, p1, p2), right neighbours (p1, p2, p3, p4)
-        const uint32_t L = swar::funnel(mc, lc, 24), R = swar::funnel(rc, mc, 8);
-        __builtin_nontemporal_store(swar::med5_bytes(mc, up, n.m, L, R), dst + (int64_t)y * Wq + cx);
+      if (FULL || y < yend) {
+        uint32_t v[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          // left neighbours (p-1, p0, p1, p2), right neighbours (p1, p2, p3, p4) of word j
+          const uint32_t L = swar::perm(cen[j + 1], cen[j], j == 0 ? sel_l0 : sel_l);
+          const uint32_t R = swar::perm(cen[j + 2], cen[j + 1], j == V - 1 ? sel_rV : sel_r);
+          v[j] = swar::med5_bytes(cen[j + 1], up[j], w[j + 1], L, R);
+        }
+        st.store(dst, (uint32_t)(y * Wq), v);
       }
     }
     // the current centre row is the row above the next one
-    up = mc;
-    lc = n.l;
-    mc = n.m;
-    rc = n.r;
+#pragma unroll
+    for (int j = 0; j < V; ++j) up[j] = cen[j + 1];
+#pragma unroll
+    for (int j = 0; j < V + 2; ++j) cen[j] = w[j];
   }
 }
 
@@ -200,17 +287,18 @@ __global__ __launch_bounds__(kMdThreads) void k_med5_b(MdpArgs a, int64_t f0, in
 // Launch `kern` over all frames in chunks of at most kMaxBlocks workgroups,
 // bpf workgroups per frame; timing events bracket the first and last chunk.
 template <class K, class... Extra>
-hipError_t launch_frames(K kern, const MdpArgs &a, int32_t bpf, hipStream_t s, const KTiming *t, Extra... extra) {
+hipError_t launch_frames(K kern, int threads, const MdpArgs &a, int32_t bpf, hipStream_t s, const KTiming *t,
+                         Extra... extra) {
   const int64_t per_launch = kMaxBlocks / bpf > 0 ? kMaxBlocks / bpf : 1;
   for (int64_t f0 = 0; f0 < a.n_frames; f0 += per_launch) {
     const int64_t nf = a.n_frames - f0 < per_launch ? a.n_frames - f0 : per_launch;
     const dim3 grid((unsigned)(nf * bpf));
     const bool first = f0 == 0, last = f0 + per_launch >= a.n_frames;
     if (t && (first || last))
-      hipExtLaunchKernelGGL(kern, grid, dim3(kMdThreads), 0, s, first ? t->start : nullptr,
+      hipExtLaunchKernelGGL(kern, grid, dim3(threads), 0, s, first ? t->start : nullptr,
                             last ? t->stop : nullptr, 0, a, f0, extra..., bpf);
     else
-      hipLaunchKernelGGL(kern, grid, dim3(kMdThreads), 0, s, a, f0, extra..., bpf);
+      hipLaunchKernelGGL(kern, grid, dim3(threads), 0, s, a, f0, extra..., bpf);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -230,29 +318,49 @@ __global__ void k_advance_n(int64_t *p0, int64_t *p1, int64_t *p2, int64_t *p3, 
 
 }  // namespace
 
+namespace {
+
+template <int V>
+hipError_t launch_gauss5_words(const MdpArgs &a, hipStream_t s, const KTiming *t) {
+  const int32_t n_runs = div_up32(a.H, kRun);
+  const int32_t bpf = div_up32((int64_t)n_runs * (a.W / (4 * V)), kWordThreads);
+  const bool full = a.H >= kRun;
+  if (a.out1)
+    return full ? launch_frames(k_gauss5_w<V, true, true>, kWordThreads, a, bpf, s, t, n_runs)
+                : launch_frames(k_gauss5_w<V, true, false>, kWordThreads, a, bpf, s, t, n_runs);
+  return full ? launch_frames(k_gauss5_w<V, false, true>, kWordThreads, a, bpf, s, t, n_runs)
+              : launch_frames(k_gauss5_w<V, false, false>, kWordThreads, a, bpf, s, t, n_runs);
+}
+
+template <int V>
+hipError_t launch_med5_words(const MdpArgs &a, hipStream_t s, const KTiming *t) {
+  const int32_t n_runs = div_up32(a.H, kRun);
+  const int32_t bpf = div_up32((int64_t)n_runs * (a.W / (4 * V)), kWordThreads);
+  return a.H >= kRun ? launch_frames(k_med5_w<V, true>, kWordThreads, a, bpf, s, t, n_runs)
+                     : launch_frames(k_med5_w<V, false>, kWordThreads, a, bpf, s, t, n_runs);
+}
+
+}  // namespace
+
 hipError_t launch_gauss5(const MdpArgs &a, hipStream_t s, const KTiming *t) {
   if (a.n_frames <= 0) return hipSuccess;
-  if (a.W % 4 == 0) {
-    const int32_t n_runs = div_up32(a.H, kRun);
-    return launch_frames(k_gauss5_w, a, div_up32((int64_t)n_runs * (a.W / 4), kMdThreads), s, t, n_runs);
-  }
-  return launch_frames(k_gauss5_b, a, div_up32((int64_t)a.W * a.H, kMdThreads), s, t);
+  if (a.W % 16 == 0) return launch_gauss5_words<4>(a, s, t);
+  if (a.W % 4 == 0) return launch_gauss5_words<1>(a, s, t);
+  return launch_frames(k_gauss5_b, kMdThreads, a, div_up32((int64_t)a.W * a.H, kMdThreads), s, t);
 }
 
 hipError_t launch_thres(const MdpArgs &a, hipStream_t s, const KTiming *t) {
   if (a.n_frames <= 0) return hipSuccess;
   const int64_t WH = (int64_t)a.W * a.H;
-  if (WH % 16 == 0) return launch_frames(k_thres_v, a, div_up32(WH / 16, kMdThreads), s, t);
-  return launch_frames(k_thres_b, a, div_up32(WH, kMdThreads), s, t);
+  if (WH % 16 == 0) return launch_frames(k_thres_v, kMdThreads, a, div_up32(WH / 16, kMdThreads), s, t);
+  return launch_frames(k_thres_b, kMdThreads, a, div_up32(WH, kMdThreads), s, t);
 }
 
 hipError_t launch_med5(const MdpArgs &a, hipStream_t s, const KTiming *t) {
   if (a.n_frames <= 0) return hipSuccess;
-  if (a.W % 4 == 0) {
-    const int32_t n_runs = div_up32(a.H, kRun);
-    return launch_frames(k_med5_w, a, div_up32((int64_t)n_runs * (a.W / 4), kMdThreads), s, t, n_runs);
-  }
-  return launch_frames(k_med5_b, a, div_up32((int64_t)a.W * a.H, kMdThreads), s, t);
+  if (a.W % 16 == 0) return launch_med5_words<4>(a, s, t);
+  if (a.W % 4 == 0) return launch_med5_words<1>(a, s, t);
+  return launch_frames(k_med5_b, kMdThreads, a, div_up32((int64_t)a.W * a.H, kMdThreads), s, t);
 }
 
 hipError_t launch_advance_n(int64_t *const *ptr, int n, int64_t delta, hipStream_t s) {

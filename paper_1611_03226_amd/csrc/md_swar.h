@@ -24,6 +24,32 @@ __host__ __device__ inline uint32_t funnel(uint32_t hi, uint32_t lo, int s) {
   return (uint32_t)((((uint64_t)hi << 32) | lo) >> s);
 }
 
+// Byte permute: byte i of the result is byte sel[i] (0..7) of the 8-byte
+// pool lo (bytes 0..3) : hi (bytes 4..7).
+__host__ __device__ inline uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_perm(hi, lo, sel);
+#else
+  const uint64_t pool = ((uint64_t)hi << 32) | lo;
+  uint32_t r = 0;
+  for (int i = 0; i < 4; ++i) r |= (uint32_t)((pool >> (8 * ((sel >> (8 * i)) & 7))) & 0xFF) << (8 * i);
+  return r;
+#endif
+}
+
+// Selectors for perm() building horizontal windows of the 4 pixels p0..p3
+// of word m from its neighbour words l and r.  With `edge` set the pixels
+// beyond the frame edge repeat the edge pixel (p-1 = p-2 = p0 on the left,
+// p4 = p5 = p3 on the right).
+//   perm(m, l, win2_left(e))  = (p-2, p-1, p0, p1)
+//   perm(r, m, win2_right(e)) = (p2, p3, p4, p5)
+//   perm(m, l, win1_left(e))  = (p-1, p0, p1, p2)
+//   perm(r, m, win1_right(e)) = (p1, p2, p3, p4)
+__host__ __device__ inline uint32_t win2_left(bool edge) { return edge ? 0x05040404u : 0x05040302u; }
+__host__ __device__ inline uint32_t win2_right(bool edge) { return edge ? 0x03030302u : 0x05040302u; }
+__host__ __device__ inline uint32_t win1_left(bool edge) { return edge ? 0x06050404u : 0x06050403u; }
+__host__ __device__ inline uint32_t win1_right(bool edge) { return edge ? 0x03030201u : 0x04030201u; }
+
 // Horizontal 5-tap binomial sums (1,4,6,4,1) of four pixels p0..p3 given
 // the 8-byte window X = (p-2, p-1, p0, p1, p2, p3, p4, p5) as lo (bytes
 // 0..3) and hi (bytes 4..7).  Returns the sums of (p0, p2) in *even and of
