@@ -240,45 +240,55 @@ def bench_motion(D, Graph, torch, steps=3, warmup=1):
 
 def bench_md_paper(D, Graph, torch, steps=5, warmup=2, n_frames=4096):
     """The paper's motion-detection pipeline (Sec. 4.1): Gauss 5x5 -> Thres ->
-    Med 5-px on 320x240 u8 frames at token rate 4, as three actors joined by
-    device FIFOs; one step fires each actor n_frames/4 times.  Inputs for
-    every step are pushed before the timed region."""
+    Med 5-px on 320x240 u8 frames at token rate 4.  One step fires each actor
+    n_frames/4 times, first as three actors over device FIFOs (three
+    launches), then as one df_fire_pipeline call (one fused launch).  Inputs
+    for every step are pushed before the timed regions."""
     from workloads import paper_motion
     rate, thr = 4, 20
     log(f"generating {n_frames} frames of 320x240")
     w = paper_motion(n_frames=n_frames)
     n, H, W = w.frames.shape
     nf = n // rate
-    nb = steps + warmup
+    nb = 2 * (steps + warmup)
     G = Graph(0)
     p = G.paper_motion_pipeline(W, H, thr, rate, cap=pow2(n + 1), cap_io=pow2(nb * n + 1))
     f_dev = torch.from_numpy(w.frames).cuda()
     torch.cuda.synchronize()
     for _ in range(nb):
         G.push(p.inp, f_dev)
-    for _ in range(warmup):
-        p.fire_all(G, nf)
-    G.sync()
-    G.profile(True)
-    G.profile_read()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        p.fire_all(G, nf)
-    G.sync()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
     wh = W * H
+
+    def timed(fire):
+        for _ in range(warmup):
+            fire()
+        G.sync()
+        G.profile(True)
+        G.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fire()
+        G.sync()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    def kernel_entry(t_ms, byt):
+        return {"ms": round(t_ms, 4), "algorithmic_bytes": byt, "GBps": round(byt / (t_ms * 1e-3) / 1e9, 1),
+                "frac": round(byt / (t_ms * 1e-3) / HBM_PEAK, 4),
+                "frac_of_copy": num(byt / (t_ms * 1e-3) / COPY["Bps"]) if COPY["Bps"] else None}
+
+    ms_sep = timed(lambda: p.fire_all(G, nf))
     kern = {}
     for name, actor, frames_moved in (("gauss", p.gauss, 3), ("thres", p.thres, 3), ("med", p.med, 2)):
         t, nl = G.profile_read(actor)
-        kms = t / max(nl, 1)
-        byt = frames_moved * n * wh
-        kern[name] = {"ms": round(kms, 4), "algorithmic_bytes": byt,
-                      "GBps": round(byt / (kms * 1e-3) / 1e9, 1),
-                      "frac": round(byt / (kms * 1e-3) / HBM_PEAK, 4),
-                      "frac_of_copy": num(byt / (kms * 1e-3) / COPY["Bps"]) if COPY["Bps"] else None}
+        kern[name] = kernel_entry(t / max(nl, 1), frames_moved * n * wh)
+    ms_fused = timed(lambda: p.fire_chain(G, nf))
+    t, nl = G.profile_read(p.gauss)
+    # fused launch: every input frame read, every output frame written, plus
+    # the delay channel's token read and rewritten once per batch
+    kern["fused"] = kernel_entry(t / max(nl, 1), 2 * n * wh + 2 * wh)
     G.profile(False)
     out = np.zeros((n, H, W), np.uint8)
-    G.pop(p.out, out)                      # first batch: non-empty masks expected
+    G.pop(p.out, out)
     nonempty = int((out.reshape(n, -1).max(axis=1) > 0).sum())
     per_ms = float("nan")
     if PER_FIRING:
@@ -292,11 +302,13 @@ def bench_md_paper(D, Graph, torch, steps=5, warmup=2, n_frames=4096):
         per_ms = (time.perf_counter() - t0) * 1e3
     G.close()
     return dict(workload=f"paper motion detection: {n} frames 320x240 u8 per step, Gauss 5x5 -> Thres (T={thr}, "
-                         "one-frame delay channel) -> Med 5-px, token rate 4, three actors over device FIFOs",
-                fps=round(n / (ms * 1e-3), 1), ms_per_batch=round(ms, 4),
+                         "one-frame delay channel) -> Med 5-px, token rate 4",
+                fps_three_actors=round(n / (ms_sep * 1e-3), 1), ms_per_batch_three_actors=round(ms_sep, 4),
+                fps_fused=round(n / (ms_fused * 1e-3), 1), ms_per_batch_fused=round(ms_fused, 4),
                 kernels=kern, frames_with_motion=nonempty,
-                parity="tests/test_gpu_md_paper.py::test_full_size_sampled_frames (same workload and batch)",
-                per_firing_fps=num(n / (per_ms * 1e-3), 1), speedup_vs_per_firing=num(per_ms / ms, 2),
+                parity="tests/test_gpu_md_paper.py::test_full_size_sampled_frames and "
+                       "::test_chain_full_size_sampled_frames (same workload and batch)",
+                per_firing_fps=num(n / (per_ms * 1e-3), 1), speedup_vs_per_firing=num(per_ms / ms_sep, 2),
                 paper_fps_context={"Carrizo A12-8800B + R7 (OpenCL 2.0)": 4614,
                                    "i7-4770 + Radeon HD 7750 (OpenCL 1.2)": 6063})
 

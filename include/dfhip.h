@@ -256,6 +256,24 @@ df_status df_fire(df_graph *g, int32_t actor, int64_t n_firings, int flags,
 df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *actors,
                        const int64_t *n_firings, int flags);
 
+/* Fire the chain Gauss -> Thres -> Med of Sec. 4.1 n_firings times: the same
+ * as df_fire(gauss, n), df_fire(thres, n), df_fire(med, n) in that order
+ * (same output tokens, same channel counters and pending tokens afterwards),
+ * with admission over the whole chain (DF_EAGAIN, or the admissible prefix
+ * with DF_FIRE_PARTIAL).  When the chain is wired as in the paper (Gauss OUT
+ * and OUT2 to Thres CUR and PREV, Thres OUT to Med IN, equal frame
+ * parameters), the Gauss->Thres current and Thres->Med channels are empty,
+ * the delay channel holds exactly one token and the width is a multiple of
+ * 4, one fused kernel fires the batch: the frames of the inner channels stay
+ * on chip, and only the delay channel's one pending token (the last Gauss
+ * frame) is written.  Otherwise, or with DF_PIPE_SEPARATE in flags, the three
+ * actors fire one after the other.  A fused launch is timed as the Gauss
+ * actor's.  *n_fired (may be NULL) receives the firings per actor.
+ * Errors: DF_EINVAL (not such a chain), DF_ESTATE, DF_EAGAIN. */
+enum { DF_PIPE_SEPARATE = 2 };
+df_status df_fire_pipeline(df_graph *g, int32_t gauss, int32_t thres, int32_t med,
+                           int64_t n_firings, int flags, int64_t *n_fired);
+
 /* Tile configuration of the DPD body kernels: tile_outputs samples per
  * workgroup work item (a multiple of 64*outputs_per_thread, at most
  * 512*outputs_per_thread), outputs_per_thread (4 or 8), and the persistent

@@ -175,10 +175,33 @@ struct MdpArgs {
   int64_t n_frames;
 };
 
+// One fused batch of the chain Gauss -> Thres -> Med (n_frames frames):
+// input frames from `in` (read counter), the previous Gauss frame of the
+// batch's first frame from the delay channel's read slot, output frames to
+// `out` (write counter), and the Gauss frame of the batch's last frame to the
+// delay channel's slot write counter + n_frames - 1.
+struct MdpFusedArgs {
+  const uint8_t *in;
+  const int64_t *in_idx;
+  int64_t in_mask;
+  uint8_t *delay;           // Gauss -> Thres delay channel
+  const int64_t *delay_idx;
+  int64_t delay_mask;
+  uint8_t *out;
+  const int64_t *out_idx;
+  int64_t out_mask;
+  int32_t W, H;
+  int32_t thr;
+  int64_t n_frames;
+};
+// The fused form needs W % 4 == 0 (returns hipErrorInvalidValue otherwise).
+hipError_t launch_mdp_fused(const MdpFusedArgs &a, hipStream_t s, const KTiming *t = nullptr);
+bool mdp_fused_supported(int32_t W, int32_t H);
+
 hipError_t launch_gauss5(const MdpArgs &a, hipStream_t s, const KTiming *t = nullptr);
 hipError_t launch_thres(const MdpArgs &a, hipStream_t s, const KTiming *t = nullptr);
 hipError_t launch_med5(const MdpArgs &a, hipStream_t s, const KTiming *t = nullptr);
-// Add delta to every counter ptr[0..n) (n <= 4) in one launch.
+// Add delta to every counter ptr[0..n) (n <= 8) in one launch.
 hipError_t launch_advance_n(int64_t *const *ptr, int n, int64_t delta, hipStream_t s);
 
 bool dpd_tiled_shape(int M);

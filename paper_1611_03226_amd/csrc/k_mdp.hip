@@ -282,6 +282,140 @@ __global__ __launch_bounds__(kMdThreads) void k_med5_b(MdpArgs a, int64_t f0, in
   out_frame(a.out0, a.out0_idx, a.out0_mask, f, WH)[i] = (uint8_t)swar::med5_bytes(c, u, d, l, rr);
 }
 
+// ------------------------------------------------------------------ fused chain
+//
+// Gauss -> Thres -> Med in one pass over a batch: the frames of the two
+// inner channels stay in registers.  A wavefront owns 62 consecutive words
+// (lanes 1..62) of the flattened (row band, word column) sequence of a
+// frame, plus one halo lane on each side, for kFuseRun output rows, and
+// walks kFuseFrames consecutive frames: for each it computes the Gauss words
+// of its band (rows y0-1 .. y0+R, sliding 5-row window; the 2 neighbour bytes
+// on each side come from the adjacent lanes by DPP wave shifts), thresholds
+// them against the previous frame's Gauss words kept in registers, and takes
+// the 5-pixel median with the row above and below and the neighbour lanes'
+// threshold words.  The previous Gauss frame of the first frame of a wave's
+// range comes from the delay channel (first frame of the batch) or is
+// recomputed from the previous input frame.  A band boundary inside a
+// wavefront falls on a frame edge, where the perm selectors ignore the
+// neighbour lane.  Lanes past the frame's words load clamped addresses and do
+// not store; whole wavefronts past the range exit.
+constexpr int kFuseRun = 16;
+constexpr int kFuseOut = 62;
+constexpr int kFuseFrames = 8;
+
+__device__ __forceinline__ uint32_t lane_below(uint32_t v) {   // value of lane l-1 (0 in lane 0)
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t lane_above(uint32_t v) {   // value of lane l+1 (0 in lane 63)
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true);
+}
+
+// One frame of a wavefront's band.  Gauss words of rows clamp(y0-1+j),
+// j = 0..R+1, at word `col` are produced one per row step (sliding 5-row
+// window).  WARM: only store them in gp (previous frame of the range).
+// Otherwise each is thresholded against gp[j] (then replaces it), and once
+// three threshold rows are known the median of the middle one is stored;
+// with `keep` the Gauss words of rows y0..yend-1 also go to `dg` (the delay
+// channel's token).
+struct FuseLane {
+  int y0, yend, H, Wq;
+  uint32_t col, s2l, s2r, s1l, s1r, thr;
+  bool store;
+};
+
+template <int R, bool WARM>
+__device__ inline void fused_frame(const FuseLane &q, const uint32_t *src, uint32_t *dst, uint32_t *dg,
+                                   uint32_t (&gp)[R + 2]) {
+  uint32_t he[5] = {}, ho[5] = {}, mid[5] = {};
+  uint32_t t_up = 0, t_c = 0;
+  // recompute the row offsets per frame instead of holding them across the
+  // frame loop (they would take ~40 registers)
+  int y0 = q.y0;
+  uint32_t col = q.col;
+  asm volatile("" : "+v"(y0), "+v"(col));
+#pragma unroll
+  for (int r = 0; r < R + 6; ++r) {
+    const uint32_t w = src[(uint32_t)(min(max(y0 - 3 + r, 0), q.H - 1) * q.Wq) + col];
+    const uint32_t wl = lane_below(w), wr = lane_above(w);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      he[k] = he[k + 1];
+      ho[k] = ho[k + 1];
+      mid[k] = mid[k + 1];
+    }
+    swar::hsum5(swar::perm(w, wl, q.s2l), swar::perm(wr, w, q.s2r), &he[4], &ho[4]);
+    mid[4] = w;
+    if (r < 4) continue;
+    const int j = r - 4;                          // Gauss / threshold row index
+    const int t = y0 - 1 + j;                     // its frame row (clamped when used)
+    const uint32_t filt = swar::interleave(swar::vround5(he[0], he[1], he[2], he[3], he[4]),
+                                           swar::vround5(ho[0], ho[1], ho[2], ho[3], ho[4]));
+    const uint32_t g = (t >= 2 && t < q.H - 2) ? filt : mid[2];
+    if (WARM) {
+      gp[j] = g;
+      continue;
+    }
+    const uint32_t t_dn = swar::absdiff_gt(g, gp[j], q.thr);
+    gp[j] = g;
+    if (dg && j >= 1 && j <= R && t < q.yend && q.store) dg[(uint32_t)(t * q.Wq) + col] = g;
+    if (j >= 2) {
+      // median of threshold row j-1 (frame row y0 + j - 2)
+      const uint32_t L = swar::perm(t_c, lane_below(t_c), q.s1l), Rt = swar::perm(lane_above(t_c), t_c, q.s1r);
+      const int y = y0 + j - 2;
+      if (q.store && y < q.yend)
+        __builtin_nontemporal_store(swar::med5_bytes(t_c, t_up, t_dn, L, Rt), dst + (uint32_t)(y * q.Wq) + col);
+    }
+    t_up = t_c;
+    t_c = t_dn;
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_mdp_fused(MdpFusedArgs a, int32_t waves_per_chunk, int32_t bpc) {
+  const FramePart cp = frame_part(blockIdx.x, (uint32_t)bpc);   // (frame chunk, block of the chunk)
+  const int32_t seg = (int32_t)cp.part * 4 + (int32_t)(threadIdx.x >> 6);
+  if (seg >= waves_per_chunk) return;                            // whole wavefront
+  const int lane = (int)(threadIdx.x & 63);
+  FuseLane q;
+  q.H = a.H;
+  q.Wq = a.W >> 2;
+  const int n_bands = (a.H + R - 1) / R;
+  const int32_t N = n_bands * q.Wq;
+  const int32_t i = seg * kFuseOut - 1 + lane;
+  q.store = lane >= 1 && lane <= kFuseOut && i < N;
+  const int32_t ic = min(max(i, 0), N - 1);
+  const int cx = ic % q.Wq;
+  q.y0 = (ic / q.Wq) * R;
+  q.yend = min(q.y0 + R, a.H);
+  q.col = (uint32_t)cx;
+  q.s2l = swar::win2_left(cx == 0);
+  q.s2r = swar::win2_right(cx == q.Wq - 1);
+  q.s1l = swar::win1_left(cx == 0);
+  q.s1r = swar::win1_right(cx == q.Wq - 1);
+  q.thr = (uint32_t)a.thr;
+  const int64_t WH = (int64_t)a.W * a.H;
+  const int64_t f_begin = (int64_t)cp.frame * kFuseFrames;
+  const int64_t f_end = min(f_begin + kFuseFrames, a.n_frames);
+  const int64_t in0 = a.in_idx[0], out0 = a.out_idx[1], d_read = a.delay_idx[0], d_write = a.delay_idx[1];
+
+  uint32_t gp[R + 2];   // Gauss words of the previous frame, rows clamp(y0-1+j)
+  if (f_begin == 0) {
+    const uint32_t *pg = (const uint32_t *)(a.delay + (d_read & a.delay_mask) * WH);
+#pragma unroll
+    for (int j = 0; j < R + 2; ++j) gp[j] = pg[(uint32_t)(min(max(q.y0 - 1 + j, 0), a.H - 1) * q.Wq) + q.col];
+  } else {
+    fused_frame<R, true>(q, (const uint32_t *)(a.in + ((in0 + f_begin - 1) & a.in_mask) * WH), nullptr, nullptr,
+                         gp);
+  }
+  for (int64_t f = f_begin; f < f_end; ++f) {
+    // the delay channel keeps the last frame's Gauss output as its one token
+    uint32_t *dg = f == a.n_frames - 1 ? (uint32_t *)(a.delay + ((d_write + a.n_frames - 1) & a.delay_mask) * WH)
+                                       : nullptr;
+    fused_frame<R, false>(q, (const uint32_t *)(a.in + ((in0 + f) & a.in_mask) * WH),
+                          (uint32_t *)(a.out + ((out0 + f) & a.out_mask) * WH), dg, gp);
+  }
+}
+
 // ------------------------------------------------------------------ launch
 
 // Launch `kern` over all frames in chunks of at most kMaxBlocks workgroups,
@@ -307,13 +441,13 @@ hipError_t launch_frames(K kern, int threads, const MdpArgs &a, int32_t bpf, hip
 
 int32_t div_up32(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 
-__global__ void k_advance_n(int64_t *p0, int64_t *p1, int64_t *p2, int64_t *p3, int64_t delta) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (p0) *p0 += delta;
-    if (p1) *p1 += delta;
-    if (p2) *p2 += delta;
-    if (p3) *p3 += delta;
-  }
+struct Counters {
+  int64_t *p[8];
+};
+
+__global__ void k_advance_n(Counters c, int n, int64_t delta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    for (int i = 0; i < n; ++i) *c.p[i] += delta;
 }
 
 }  // namespace
@@ -364,10 +498,29 @@ hipError_t launch_med5(const MdpArgs &a, hipStream_t s, const KTiming *t) {
 }
 
 hipError_t launch_advance_n(int64_t *const *ptr, int n, int64_t delta, hipStream_t s) {
-  if (n < 1 || n > 4) return hipErrorInvalidValue;
-  int64_t *p[4] = {nullptr, nullptr, nullptr, nullptr};
-  for (int i = 0; i < n; ++i) p[i] = ptr[i];
-  hipLaunchKernelGGL(k_advance_n, dim3(1), dim3(64), 0, s, p[0], p[1], p[2], p[3], delta);
+  if (n < 1 || n > 8) return hipErrorInvalidValue;
+  Counters c{};
+  for (int i = 0; i < n; ++i) c.p[i] = ptr[i];
+  hipLaunchKernelGGL(k_advance_n, dim3(1), dim3(64), 0, s, c, n, delta);
+  return hipGetLastError();
+}
+
+bool mdp_fused_supported(int32_t W, int32_t H) { return W % 4 == 0 && W >= 4 && H >= 1; }
+
+hipError_t launch_mdp_fused(const MdpFusedArgs &a, hipStream_t s, const KTiming *t) {
+  if (!mdp_fused_supported(a.W, a.H)) return hipErrorInvalidValue;
+  if (a.n_frames <= 0) return hipSuccess;
+  const int64_t n_bands = (a.H + kFuseRun - 1) / kFuseRun;
+  const int64_t words = n_bands * (a.W / 4);
+  const int32_t waves = (int32_t)((words + kFuseOut - 1) / kFuseOut);
+  const int32_t bpc = (waves + 3) / 4;
+  const int64_t chunks = (a.n_frames + kFuseFrames - 1) / kFuseFrames;
+  if (chunks * bpc > kMaxBlocks) return hipErrorInvalidValue;   // > 2^23 workgroups: not supported
+  const dim3 grid((unsigned)(chunks * bpc));
+  if (t)
+    hipExtLaunchKernelGGL(k_mdp_fused<kFuseRun>, grid, dim3(256), 0, s, t->start, t->stop, 0, a, waves, bpc);
+  else
+    hipLaunchKernelGGL(k_mdp_fused<kFuseRun>, grid, dim3(256), 0, s, a, waves, bpc);
   return hipGetLastError();
 }
 

@@ -759,6 +759,92 @@ static df_status fire_frames(df_graph *g, Actor &a, int64_t n, int flags, int64_
   return DF_OK;
 }
 
+extern "C" df_status df_fire_pipeline(df_graph *g, int32_t gauss, int32_t thres, int32_t med, int64_t n, int flags,
+                                      int64_t *n_fired) {
+  ENTER(g);
+  if (n_fired) *n_fired = 0;
+  const int na = (int)g->actors.size();
+  if (gauss < 0 || gauss >= na || thres < 0 || thres >= na || med < 0 || med >= na)
+    return fail(g, DF_EINVAL, "bad actor id");
+  if (n < 0) return fail(g, DF_EINVAL, "negative firing count");
+  if (flags & ~(DF_FIRE_PARTIAL | DF_PIPE_SEPARATE)) return fail(g, DF_EINVAL, "bad flags 0x%x", flags);
+  Actor &ga = g->actors[gauss], &ta = g->actors[thres], &ma = g->actors[med];
+  if (ga.kind != DF_ACTOR_GAUSS5 || ta.kind != DF_ACTOR_THRES || ma.kind != DF_ACTOR_MED5)
+    return fail(g, DF_EINVAL, "df_fire_pipeline takes a Gauss, a Thres and a Med actor");
+  const int p_in = ga.ports[DF_GAUSS_IN], p_cur = ga.ports[DF_GAUSS_OUT], p_del = ga.ports[DF_GAUSS_OUT2];
+  const int p_thr = ta.ports[DF_THRES_OUT], p_out = ma.ports[DF_MED_OUT];
+  if (p_in < 0 || p_cur < 0 || p_thr < 0 || p_out < 0 || ta.ports[DF_THRES_CUR] < 0 || ta.ports[DF_THRES_PREV] < 0 ||
+      ma.ports[DF_MED_IN] < 0)
+    return fail(g, DF_ESTATE, "pipeline actors have unconnected ports");
+  if (ta.ports[DF_THRES_CUR] != p_cur || ma.ports[DF_MED_IN] != p_thr)
+    return fail(g, DF_EINVAL, "actors are not chained Gauss -> Thres -> Med");
+  const df_frame_params &gp = ga.fp, &tp = ta.fp, &mp = ma.fp;
+  if (gp.width != tp.width || gp.width != mp.width || gp.height != tp.height || gp.height != mp.height ||
+      gp.rate != tp.rate || gp.rate != mp.rate)
+    return fail(g, DF_EINVAL, "pipeline actors differ in frame size or rate");
+  const int64_t r = gp.rate;
+  // admission of the three firings in sequence: each inner channel receives
+  // its batch before it is read, so only the input and the free space count
+  Fifo &fin = g->fifos[p_in], &fcur = g->fifos[p_cur], &fthr = g->fifos[p_thr], &fout = g->fifos[p_out];
+  Fifo *fdel = p_del >= 0 ? &g->fifos[p_del] : nullptr;
+  int64_t av;
+  df_status st = available(g, fin, n * r, &av);
+  if (st) return st;
+  int64_t adm = std::min({n, av / r, space_of(fcur) / r, space_of(fthr) / r, space_of(fout) / r});
+  if (fdel) adm = std::min(adm, space_of(*fdel) / r);
+  if (adm < n && !(flags & DF_FIRE_PARTIAL))
+    return fail(g, DF_EAGAIN, "only %lld of %lld firings admissible", (long long)adm, (long long)n);
+  n = adm;
+  if (n_fired) *n_fired = n;
+  if (n == 0) return DF_OK;
+  const bool fused = !(flags & DF_PIPE_SEPARATE) && fdel && ta.ports[DF_THRES_PREV] == p_del &&
+                     mdp_fused_supported(gp.width, gp.height) && fcur.write_lo == fcur.write_hi &&
+                     fcur.write_lo == fcur.read_h && fthr.write_lo == fthr.write_hi && fthr.write_lo == fthr.read_h &&
+                     fdel->write_lo == fdel->write_hi && fdel->write_lo - fdel->read_h == 1;
+  if (!fused) {
+    for (Actor *a : {&ga, &ta, &ma}) {
+      int64_t k = 0;
+      st = fire_frames(g, *a, n, 0, &k);
+      if (st) return st;
+    }
+    return DF_OK;
+  }
+  const int64_t k = n * r;
+  MdpFusedArgs fa{};
+  fa.in = (const uint8_t *)fin.ring;
+  fa.in_idx = fin.idx;
+  fa.in_mask = fin.mask;
+  fa.delay = (uint8_t *)fdel->ring;
+  fa.delay_idx = fdel->idx;
+  fa.delay_mask = fdel->mask;
+  fa.out = (uint8_t *)fout.ring;
+  fa.out_idx = fout.idx;
+  fa.out_mask = fout.mask;
+  fa.W = gp.width;
+  fa.H = gp.height;
+  fa.thr = tp.threshold;
+  fa.n_frames = k;
+  KTiming kt;
+  HIPCHK(g, prof_pair(g, &kt, gauss));
+  HIPCHK(g, launch_mdp_fused(fa, g->stream, g->prof ? &kt : nullptr));
+  int64_t *ctr[8] = {fin.idx + 0, fcur.idx + 0, fcur.idx + 1, fdel->idx + 0, fdel->idx + 1,
+                     fthr.idx + 0, fthr.idx + 1, fout.idx + 1};
+  HIPCHK(g, launch_advance_n(ctr, 8, k, g->stream));
+  fin.read_h += k;
+  for (Fifo *f : {&fcur, fdel, &fthr}) {
+    f->read_h += k;
+    f->write_lo += k;
+    f->write_hi += k;
+  }
+  fout.write_lo += k;
+  fout.write_hi += k;
+  for (Actor *a : {&ga, &ta, &ma}) {
+    a->fired += n;
+    a->last_n = n;
+  }
+  return DF_OK;
+}
+
 extern "C" df_status df_fire(df_graph *g, int32_t actor, int64_t n, int flags, int64_t *n_fired) {
   ENTER(g);
   if (n_fired) *n_fired = 0;

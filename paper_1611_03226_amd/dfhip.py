@@ -27,6 +27,7 @@ DF_MED_IN, DF_MED_OUT = 0, 1
 DF_HIST_BRANCH, DF_HIST_SHARED = 0, 1
 DF_FIRE_PARTIAL = 1
 DF_FIRE_PERSISTENT, DF_FIRE_GRAPH = 1, 2
+DF_PIPE_SEPARATE = 2
 
 _NP_DTYPE = {DF_C64: np.complex64, DF_U8: np.uint8, DF_I32: np.int32, DF_I64: np.int64}
 
@@ -67,6 +68,7 @@ _SIGS = {
     "df_pop": ([_P, _I32, _P, _I64, C.c_int, C.POINTER(_I64)], _I32),
     "df_fire": ([_P, _I32, _I64, C.c_int, C.POINTER(_I64)], _I32),
     "df_fire_many": ([_P, _I32, _P, _P, C.c_int], _I32),
+    "df_fire_pipeline": ([_P, _I32, _I32, _I32, _I64, C.c_int, C.POINTER(_I64)], _I32),
     "df_set_tile": ([_P, _I32, _I32, _I32], _I32),
     "df_profile_enable": ([_P, _I32], _I32),
     "df_profile_read": ([_P, C.POINTER(C.c_double), C.POINTER(_I64)], _I32),
@@ -215,6 +217,12 @@ def df_fire_many(g, actors, n_firings, flags: int = 0) -> None:
     if a.shape != n.shape:
         raise ValueError("actors and n_firings differ in length")
     _check(_lib.df_fire_many(g, len(a), _host_ptr(a), _host_ptr(n), flags), g)
+
+
+def df_fire_pipeline(g, gauss: int, thres: int, med: int, n_firings: int, flags: int = 0) -> int:
+    out = C.c_int64()
+    _check(_lib.df_fire_pipeline(g, gauss, thres, med, n_firings, flags, C.byref(out)), g)
+    return out.value
 
 
 def df_set_tile(g, tile_outputs: int = 0, outputs_per_thread: int = 0, blocks_per_cu: int = 0) -> None:

@@ -57,9 +57,14 @@ class PaperMotionPipeline:
     rate: int
 
     def fire_all(self, G: "Graph", n_firings: int) -> None:
-        """Fire each actor n_firings times, in pipeline order."""
+        """Fire each actor n_firings times, in pipeline order (three launches)."""
         for a in (self.gauss, self.thres, self.med):
             G.fire(a, n_firings)
+
+    def fire_chain(self, G: "Graph", n_firings: int, fused: bool = True, partial: bool = False) -> int:
+        """The same firings through df_fire_pipeline (one fused launch when it applies)."""
+        flags = (0 if fused else D.DF_PIPE_SEPARATE) | (D.DF_FIRE_PARTIAL if partial else 0)
+        return D.df_fire_pipeline(G.g, self.gauss, self.thres, self.med, n_firings, flags)
 
 
 class Graph:

@@ -187,3 +187,110 @@ def test_full_size_sampled_frames():
         prev = omd.gauss5(w.frames[k - 1]) if k else np.zeros((240, 320), np.uint8)
         want = omd.med5(omd.thres(omd.gauss5(w.frames[k]), prev, 20))
         assert np.array_equal(out[k], want), k
+
+
+# ------------------------------------------------------------------ df_fire_pipeline
+
+def run_chain(frames, threshold=20, rate=4, batches=None, cap=0, fused=True):
+    """Like run_pipeline, but each batch is one df_fire_pipeline call."""
+    from paper_1611_03226_amd.graph import Graph
+    n, H, W = frames.shape
+    nf = n // rate
+    batches = batches or [nf]
+    cap = cap or _pow2(n + 1)
+    out = np.zeros((nf * rate, H, W), np.uint8)
+    with Graph(0) as G:
+        p = G.paper_motion_pipeline(W, H, threshold, rate, cap=cap)
+        pos = got = 0
+        for b in batches:
+            k = b * rate
+            G.push(p.inp, frames[pos:pos + k])
+            pos += k
+            assert p.fire_chain(G, b, fused=fused) == b
+            got += G.pop(p.out, out[got:got + k])
+        assert got == nf * rate
+        for f in (p.inp, p.g_cur, p.thr, p.out):
+            r, w, _ = G.status(f)
+            assert r == w == nf * rate
+        assert G.status(p.g_delayed)[:2] == (nf * rate, nf * rate + 1)
+        G.sync()
+    return out
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_chain_paper_size(fused):
+    say(f"md_paper chain 320x240 fused={fused}, batches 2,1,3")
+    w = paper_motion(seed=31, n_frames=24)
+    out = run_chain(w.frames, batches=[2, 1, 3], fused=fused)
+    assert np.array_equal(out, _expect(w.frames))
+
+
+@pytest.mark.parametrize("W,H", [(4, 9), (8, 5), (36, 23), (320, 50), (16, 3), (4, 1), (12, 2), (64, 17),
+                                 (37, 23), (13, 7)])
+def test_chain_ragged_sizes(W, H):
+    say(f"md_paper chain ragged {W}x{H}")
+    rng = np.random.default_rng(W * 1000 + H + 7)
+    frames = rng.integers(0, 256, (20, H, W)).astype(np.uint8)
+    frames[1::2] = np.clip(frames[0::2].astype(int) + rng.integers(-30, 31, (10, H, W)), 0, 255)
+    out = run_chain(frames, threshold=12, rate=4, batches=[1, 3, 1])
+    assert np.array_equal(out, _expect(frames, 12))
+
+
+def test_chain_many_frames_per_wave_range_and_ring_wrap():
+    # 27 firings of rate 1 in batches that cross the 8-frame ranges of the
+    # fused kernel and wrap a 16-frame ring
+    say("md_paper chain rate 1, 27 frames, capacity 16")
+    w = paper_motion(seed=32, n_frames=27, width=96, height=40)
+    out = run_chain(w.frames, rate=1, batches=[9, 1, 12, 5], cap=16)
+    assert np.array_equal(out, _expect(w.frames))
+
+
+def test_chain_falls_back_when_inner_channel_holds_tokens():
+    from paper_1611_03226_amd.graph import Graph
+    say("md_paper chain after a lone Gauss firing (separate fallback)")
+    w = paper_motion(seed=33, n_frames=16, width=64, height=32)
+    out = np.zeros((16, 32, 64), np.uint8)
+    with Graph(0) as G:
+        p = G.paper_motion_pipeline(64, 32, 20, 4, cap=32)
+        G.push(p.inp, w.frames)
+        assert G.fire(p.gauss, 1) == 1                 # Gauss->Thres now holds 4 frames
+        assert p.fire_chain(G, 3) == 3                 # cannot fuse: runs the three actors
+        assert G.fire(p.thres, 1) == 1 and G.fire(p.med, 1) == 1
+        assert G.pop(p.out, out) == 16
+        G.sync()
+    assert np.array_equal(out, _expect(w.frames))
+
+
+def test_chain_admission():
+    from paper_1611_03226_amd import dfhip as D
+    from paper_1611_03226_amd.graph import Graph
+    say("md_paper chain admission")
+    w = paper_motion(seed=34, n_frames=10, width=32, height=16)
+    with Graph(0) as G:
+        p = G.paper_motion_pipeline(32, 16, 20, 4, cap=16)
+        G.push(p.inp, w.frames)
+        with pytest.raises(D.DFError) as e:
+            p.fire_chain(G, 3)
+        assert e.value.code == D.DF_EAGAIN
+        assert G.status(p.inp)[:2] == (0, 10)
+        assert p.fire_chain(G, 3, partial=True) == 2
+        out = np.zeros((8, 16, 32), np.uint8)
+        assert G.pop(p.out, out) == 8
+        G.sync()
+    assert np.array_equal(out, _expect(w.frames[:8]))
+    with Graph(0) as G:
+        p = G.paper_motion_pipeline(32, 16, 20, 4, cap=16)
+        with pytest.raises(D.DFError) as e:
+            D.df_fire_pipeline(G.g, p.thres, p.gauss, p.med, 1)
+        assert e.value.code == D.DF_EINVAL
+
+
+def test_chain_full_size_sampled_frames():
+    """4096 frames of 320x240 in one fused batch (the bench's launch)."""
+    say("md_paper chain 4096 frames 320x240, one fused batch")
+    w = paper_motion(seed=28, n_frames=4096)
+    out = run_chain(w.frames)
+    for k in (0, 1, 7, 8, 9, 511, 1024, 2047, 3000, 4095):
+        prev = omd.gauss5(w.frames[k - 1]) if k else np.zeros((240, 320), np.uint8)
+        want = omd.med5(omd.thres(omd.gauss5(w.frames[k]), prev, 20))
+        assert np.array_equal(out[k], want), k
