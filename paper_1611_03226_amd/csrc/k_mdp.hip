@@ -333,9 +333,15 @@ __device__ inline void fused_frame(const FuseLane &q, const uint32_t *src, uint3
   int y0 = q.y0;
   uint32_t col = q.col;
   asm volatile("" : "+v"(y0), "+v"(col));
+  // every row of the band in flight at once (32-bit byte offsets from the
+  // wavefront-uniform frame base)
+  uint32_t rows[R + 6];
+#pragma unroll
+  for (int r = 0; r < R + 6; ++r)
+    rows[r] = *(const uint32_t *)((const char *)src + ((uint32_t)(min(max(y0 - 3 + r, 0), q.H - 1) * q.Wq) + col) * 4u);
 #pragma unroll
   for (int r = 0; r < R + 6; ++r) {
-    const uint32_t w = src[(uint32_t)(min(max(y0 - 3 + r, 0), q.H - 1) * q.Wq) + col];
+    const uint32_t w = rows[r];
     const uint32_t wl = lane_below(w), wr = lane_above(w);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
