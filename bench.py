@@ -517,7 +517,8 @@ def summarize_pmc(fetch_csv, write_csv, bench_json):
 
 
 MD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "md_paper_pipeline_traffic.md")
-MD_KERNELS = (("gauss", "k_gauss5_w<4, true, true>"), ("thres", "k_thres_v"), ("med", "k_med5_w<4, true>"))
+MD_KERNELS = (("gauss", "k_gauss5_w<4, true, true>"), ("thres", "k_thres_v"), ("med", "k_med5_w<4, true>"),
+              ("fused", "k_mdp_fused<16>"))
 
 
 def summarize_pmc_md(fetch_csv, write_csv, bench_json):
@@ -549,7 +550,7 @@ def summarize_pmc_md(fetch_csv, write_csv, bench_json):
     w = per_dispatch(write_csv, "WRITE_SIZE")
     fr = f["copy"][0] * 1024 / copy_bytes
     fw = w["copy"][0] * 1024 / copy_bytes
-    cmd = ("rocprofv3 --pmc {c} --kernel-include-regex 'k_gauss5|k_thres|k_med5|k_stream_copy' -d pmc_{l} -o {l} "
+    cmd = ("rocprofv3 --pmc {c} --kernel-include-regex 'k_gauss5|k_thres|k_med5|k_mdp_fused|k_stream_copy' -d pmc_{l} -o {l} "
            "--output-format csv -- python3 /root/repo/bench.py --no-cpu --only md_paper --no-per-firing --steps 5 "
            "--warmup 2 > {l}.json")
     lines = [
