@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kMdThreads) void k_med5_b(MdpArgs a, int64_t f0, in
 // inner channels stay in registers.  A wavefront owns 62 consecutive words
 // (lanes 1..62) of the flattened (row band, word column) sequence of a
 // frame, plus one halo lane on each side, for kFuseRun output rows, and
-// walks kFuseFrames consecutive frames: for each it computes the Gauss words
+// walks a range of consecutive frames: for each it computes the Gauss words
 // of its band (rows y0-1 .. y0+R, sliding 5-row window; the 2 neighbour bytes
 // on each side come from the adjacent lanes by DPP wave shifts), thresholds
 // them against the previous frame's Gauss words kept in registers, and takes
@@ -301,7 +301,6 @@ __global__ __launch_bounds__(kMdThreads) void k_med5_b(MdpArgs a, int64_t f0, in
 // not store; whole wavefronts past the range exit.
 constexpr int kFuseRun = 16;
 constexpr int kFuseOut = 62;
-constexpr int kFuseFrames = 8;
 
 __device__ __forceinline__ uint32_t lane_below(uint32_t v) {   // value of lane l-1 (0 in lane 0)
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, true);
@@ -325,7 +324,7 @@ struct FuseLane {
 
 template <int R, bool WARM>
 __device__ inline void fused_frame(const FuseLane &q, const uint32_t *src, uint32_t *dst, uint32_t *dg,
-                                   uint32_t (&gp)[R + 2]) {
+                                   uint32_t (&gpE)[R + 2], uint32_t (&gpO)[R + 2]) {
   uint32_t he[5] = {}, ho[5] = {}, mid[5] = {};
   uint32_t t_up = 0, t_c = 0;
   // recompute the row offsets per frame instead of holding them across the
@@ -354,22 +353,26 @@ __device__ inline void fused_frame(const FuseLane &q, const uint32_t *src, uint3
     if (r < 4) continue;
     const int j = r - 4;                          // Gauss / threshold row index
     const int t = y0 - 1 + j;                     // its frame row (clamped when used)
-    const uint32_t filt = swar::interleave(swar::vround5(he[0], he[1], he[2], he[3], he[4]),
-                                           swar::vround5(ho[0], ho[1], ho[2], ho[3], ho[4]));
-    const uint32_t g = (t >= 2 && t < q.H - 2) ? filt : mid[2];
+    // Gauss words kept split: even pixels in gE, odd pixels in gO
+    const bool filtered = t >= 2 && t < q.H - 2;
+    const uint32_t gE = filtered ? swar::vround5(he[0], he[1], he[2], he[3], he[4]) : mid[2] & swar::kLo;
+    const uint32_t gO = filtered ? swar::vround5(ho[0], ho[1], ho[2], ho[3], ho[4]) : (mid[2] >> 8) & swar::kLo;
     if (WARM) {
-      gp[j] = g;
+      gpE[j] = gE;
+      gpO[j] = gO;
       continue;
     }
-    const uint32_t t_dn = swar::absdiff_gt(g, gp[j], q.thr);
-    gp[j] = g;
-    if (dg && j >= 1 && j <= R && t < q.yend && q.store) dg[(uint32_t)(t * q.Wq) + col] = g;
+    const uint32_t t_dn = swar::thres_split(gE, gO, gpE[j], gpO[j], q.thr);
+    gpE[j] = gE;
+    gpO[j] = gO;
+    if (dg && j >= 1 && j <= R && t < q.yend && q.store) dg[(uint32_t)(t * q.Wq) + col] = swar::interleave(gE, gO);
     if (j >= 2) {
-      // median of threshold row j-1 (frame row y0 + j - 2)
+      // median of threshold row j-1 (frame row y0 + j - 2); its inputs are
+      // 0x00/0xFF masks, so the median is the bitwise majority
       const uint32_t L = swar::perm(t_c, lane_below(t_c), q.s1l), Rt = swar::perm(lane_above(t_c), t_c, q.s1r);
       const int y = y0 + j - 2;
       if (q.store && y < q.yend)
-        __builtin_nontemporal_store(swar::med5_bytes(t_c, t_up, t_dn, L, Rt), dst + (uint32_t)(y * q.Wq) + col);
+        __builtin_nontemporal_store(swar::med5_masks(t_c, t_up, t_dn, L, Rt), dst + (uint32_t)(y * q.Wq) + col);
     }
     t_up = t_c;
     t_c = t_dn;
@@ -377,7 +380,8 @@ __device__ inline void fused_frame(const FuseLane &q, const uint32_t *src, uint3
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void k_mdp_fused(MdpFusedArgs a, int32_t waves_per_chunk, int32_t bpc) {
+__global__ __launch_bounds__(256) void k_mdp_fused(MdpFusedArgs a, int32_t waves_per_chunk, int32_t bpc,
+                                                   int32_t frames_per_chunk) {
   const FramePart cp = frame_part(blockIdx.x, (uint32_t)bpc);   // (frame chunk, block of the chunk)
   const int32_t seg = (int32_t)cp.part * 4 + (int32_t)(threadIdx.x >> 6);
   if (seg >= waves_per_chunk) return;                            // whole wavefront
@@ -400,25 +404,31 @@ __global__ __launch_bounds__(256) void k_mdp_fused(MdpFusedArgs a, int32_t waves
   q.s1r = swar::win1_right(cx == q.Wq - 1);
   q.thr = (uint32_t)a.thr;
   const int64_t WH = (int64_t)a.W * a.H;
-  const int64_t f_begin = (int64_t)cp.frame * kFuseFrames;
-  const int64_t f_end = min(f_begin + kFuseFrames, a.n_frames);
+  const int64_t f_begin = (int64_t)cp.frame * frames_per_chunk;
+  const int64_t f_end = min(f_begin + frames_per_chunk, a.n_frames);
   const int64_t in0 = a.in_idx[0], out0 = a.out_idx[1], d_read = a.delay_idx[0], d_write = a.delay_idx[1];
 
-  uint32_t gp[R + 2];   // Gauss words of the previous frame, rows clamp(y0-1+j)
+  // Gauss words of the previous frame, rows clamp(y0-1+j), split into even
+  // and odd pixels
+  uint32_t gpE[R + 2], gpO[R + 2];
   if (f_begin == 0) {
     const uint32_t *pg = (const uint32_t *)(a.delay + (d_read & a.delay_mask) * WH);
 #pragma unroll
-    for (int j = 0; j < R + 2; ++j) gp[j] = pg[(uint32_t)(min(max(q.y0 - 1 + j, 0), a.H - 1) * q.Wq) + q.col];
+    for (int j = 0; j < R + 2; ++j) {
+      const uint32_t w = pg[(uint32_t)(min(max(q.y0 - 1 + j, 0), a.H - 1) * q.Wq) + q.col];
+      gpE[j] = w & swar::kLo;
+      gpO[j] = (w >> 8) & swar::kLo;
+    }
   } else {
     fused_frame<R, true>(q, (const uint32_t *)(a.in + ((in0 + f_begin - 1) & a.in_mask) * WH), nullptr, nullptr,
-                         gp);
+                         gpE, gpO);
   }
   for (int64_t f = f_begin; f < f_end; ++f) {
     // the delay channel keeps the last frame's Gauss output as its one token
     uint32_t *dg = f == a.n_frames - 1 ? (uint32_t *)(a.delay + ((d_write + a.n_frames - 1) & a.delay_mask) * WH)
                                        : nullptr;
     fused_frame<R, false>(q, (const uint32_t *)(a.in + ((in0 + f) & a.in_mask) * WH),
-                          (uint32_t *)(a.out + ((out0 + f) & a.out_mask) * WH), dg, gp);
+                          (uint32_t *)(a.out + ((out0 + f) & a.out_mask) * WH), dg, gpE, gpO);
   }
 }
 
@@ -520,13 +530,19 @@ hipError_t launch_mdp_fused(const MdpFusedArgs &a, hipStream_t s, const KTiming 
   const int64_t words = n_bands * (a.W / 4);
   const int32_t waves = (int32_t)((words + kFuseOut - 1) / kFuseOut);
   const int32_t bpc = (waves + 3) / 4;
-  const int64_t chunks = (a.n_frames + kFuseFrames - 1) / kFuseFrames;
+  // frame ranges as short as possible while the whole grid stays resident
+  // (one round of workgroups: no tail of a partly filled second round)
+  const int64_t resident = resident_blocks((const void *)k_mdp_fused<kFuseRun>, 256, 0);
+  const int64_t max_chunks = resident / bpc > 0 ? resident / bpc : 1;
+  const int64_t fpc = (a.n_frames + max_chunks - 1) / max_chunks;
+  const int64_t chunks = (a.n_frames + fpc - 1) / fpc;
   if (chunks * bpc > kMaxBlocks) return hipErrorInvalidValue;   // > 2^23 workgroups: not supported
   const dim3 grid((unsigned)(chunks * bpc));
   if (t)
-    hipExtLaunchKernelGGL(k_mdp_fused<kFuseRun>, grid, dim3(256), 0, s, t->start, t->stop, 0, a, waves, bpc);
+    hipExtLaunchKernelGGL(k_mdp_fused<kFuseRun>, grid, dim3(256), 0, s, t->start, t->stop, 0, a, waves, bpc,
+                          (int32_t)fpc);
   else
-    hipLaunchKernelGGL(k_mdp_fused<kFuseRun>, grid, dim3(256), 0, s, a, waves, bpc);
+    hipLaunchKernelGGL(k_mdp_fused<kFuseRun>, grid, dim3(256), 0, s, a, waves, bpc, (int32_t)fpc);
   return hipGetLastError();
 }
 

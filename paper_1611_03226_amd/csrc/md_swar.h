@@ -110,6 +110,27 @@ __host__ __device__ inline u16x2 med5(u16x2 a, u16x2 b, u16x2 c, u16x2 d, u16x2 
   return vmax(vmin(e, f), vmin(vmax(e, f), g));
 }
 
+// Threshold of pixels given in split form (even pixels 0, 2 in the 16-bit
+// lanes of *E, odd pixels 1, 3 in *O, values 0..255): 0xFF in every byte
+// where |cur - prev| > t (t in 0..255), else 0.  |d| + (255 - t) stays below
+// 512, so bit 8 of each lane is the comparison.
+__host__ __device__ inline uint32_t thres_split(uint32_t cE, uint32_t cO, uint32_t pE, uint32_t pO, uint32_t t) {
+  const uint32_t bias = (255u - t) * 0x00010001u;
+  const u16x2 ce = as_u16x2(cE), co = as_u16x2(cO), pe = as_u16x2(pE), po = as_u16x2(pO);
+  const uint32_t dE = from_u16x2(vmax(ce, pe) - vmin(ce, pe));
+  const uint32_t dO = from_u16x2(vmax(co, po) - vmin(co, po));
+  const uint32_t bE = ((dE + bias) >> 8) & 0x00010001u, bO = ((dO + bias) >> 8) & 0x00010001u;
+  return (bE | (bO << 8)) * 0xFFu;
+}
+
+// Median of five 0x00/0xFF byte masks, per byte: with only two values the
+// median is the majority, and the min/max network becomes AND/OR.
+__host__ __device__ inline uint32_t med5_masks(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e) {
+  const uint32_t f = (a & b) | (c & d);
+  const uint32_t g = (a | b) & (c | d);
+  return (e & f) | ((e | f) & g);
+}
+
 // Median of five words of four pixels each, per pixel.
 __host__ __device__ inline uint32_t med5_bytes(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e) {
   uint32_t r[2];

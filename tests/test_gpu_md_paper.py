@@ -290,7 +290,9 @@ def test_chain_full_size_sampled_frames():
     say("md_paper chain 4096 frames 320x240, one fused batch")
     w = paper_motion(seed=28, n_frames=4096)
     out = run_chain(w.frames)
-    for k in (0, 1, 7, 8, 9, 511, 1024, 2047, 3000, 4095):
+    # a contiguous stretch covers the starts of several per-wavefront frame
+    # ranges (their length depends on the device's occupancy)
+    for k in list(range(0, 40)) + [511, 1024, 2047, 3000, 4094, 4095]:
         prev = omd.gauss5(w.frames[k - 1]) if k else np.zeros((240, 320), np.uint8)
         want = omd.med5(omd.thres(omd.gauss5(w.frames[k]), prev, 20))
         assert np.array_equal(out[k], want), k
