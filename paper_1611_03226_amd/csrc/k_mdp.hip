@@ -332,12 +332,17 @@ __device__ inline void fused_frame(const FuseLane &q, const uint32_t *src, uint3
   int y0 = q.y0;
   uint32_t col = q.col;
   asm volatile("" : "+v"(y0), "+v"(col));
-  // every row of the band in flight at once (32-bit byte offsets from the
-  // wavefront-uniform frame base)
+  // every row of the band in flight at once: byte offsets from the
+  // wavefront-uniform frame base, stepped by one row and clamped into the
+  // frame in offset space (no multiply per row)
+  const int row_bytes = 4 * q.Wq, last_row = (q.H - 1) * row_bytes;
+  const int col_bytes = (int)col * 4;
+  int off = (y0 - 3) * row_bytes;
   uint32_t rows[R + 6];
 #pragma unroll
-  for (int r = 0; r < R + 6; ++r)
-    rows[r] = *(const uint32_t *)((const char *)src + ((uint32_t)(min(max(y0 - 3 + r, 0), q.H - 1) * q.Wq) + col) * 4u);
+  for (int r = 0; r < R + 6; ++r, off += row_bytes)
+    rows[r] = *(const uint32_t *)((const char *)src + (uint32_t)(min(max(off, 0), last_row) + col_bytes));
+  int out_off = y0 * row_bytes + col_bytes;         // byte offset of output row y0
 #pragma unroll
   for (int r = 0; r < R + 6; ++r) {
     const uint32_t w = rows[r];
@@ -365,14 +370,17 @@ __device__ inline void fused_frame(const FuseLane &q, const uint32_t *src, uint3
     const uint32_t t_dn = swar::thres_split(gE, gO, gpE[j], gpO[j], q.thr);
     gpE[j] = gE;
     gpO[j] = gO;
-    if (dg && j >= 1 && j <= R && t < q.yend && q.store) dg[(uint32_t)(t * q.Wq) + col] = swar::interleave(gE, gO);
+    // frame row t = y0 + j - 1 is output row j - 1 of the band
+    if (dg && j >= 1 && j <= R && t < q.yend && q.store)
+      *(uint32_t *)((char *)dg + (uint32_t)(out_off + (j - 1) * row_bytes)) = swar::interleave(gE, gO);
     if (j >= 2) {
       // median of threshold row j-1 (frame row y0 + j - 2); its inputs are
       // 0x00/0xFF masks, so the median is the bitwise majority
       const uint32_t L = swar::perm(t_c, lane_below(t_c), q.s1l), Rt = swar::perm(lane_above(t_c), t_c, q.s1r);
       const int y = y0 + j - 2;
       if (q.store && y < q.yend)
-        __builtin_nontemporal_store(swar::med5_masks(t_c, t_up, t_dn, L, Rt), dst + (uint32_t)(y * q.Wq) + col);
+        __builtin_nontemporal_store(swar::med5_masks(t_c, t_up, t_dn, L, Rt),
+                                    (uint32_t *)((char *)dst + (uint32_t)(out_off + (j - 2) * row_bytes)));
     }
     t_up = t_c;
     t_c = t_dn;

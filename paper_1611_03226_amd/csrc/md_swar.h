@@ -69,7 +69,8 @@ __host__ __device__ inline void hsum5(uint32_t lo, uint32_t hi, uint32_t *even, 
 // Vertical 5-tap binomial sum of horizontal sums, rounded (s + 128) >> 8,
 // back to one byte per 16-bit lane.  Lanes stay below 65536: 4080*16 + 128.
 __host__ __device__ inline uint32_t vround5(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e) {
-  const uint32_t s = a + e + 4u * (b + d) + 6u * c + 0x00800080u;
+  // 6c as 4c + 2c: c exceeds 24 bits, and a full 32-bit multiply is slow
+  const uint32_t s = a + e + ((b + d + c) << 2) + (c << 1) + 0x00800080u;
   return (s >> 8) & kLo;
 }
 
@@ -120,7 +121,8 @@ __host__ __device__ inline uint32_t thres_split(uint32_t cE, uint32_t cO, uint32
   const uint32_t dE = from_u16x2(vmax(ce, pe) - vmin(ce, pe));
   const uint32_t dO = from_u16x2(vmax(co, po) - vmin(co, po));
   const uint32_t bE = ((dE + bias) >> 8) & 0x00010001u, bO = ((dO + bias) >> 8) & 0x00010001u;
-  return (bE | (bO << 8)) * 0xFFu;
+  const uint32_t ones = bE | (bO << 8);     // 0x00 / 0x01 per byte
+  return (ones << 8) - ones;                // x 255, modulo 2^32
 }
 
 // Median of five 0x00/0xFF byte masks, per byte: with only two values the
