@@ -521,9 +521,11 @@ MD_KERNELS = (("gauss", "k_gauss5_w<4, true, true>"), ("thres", "k_thres_v"), ("
               ("fused", "k_mdp_fused<16>"))
 
 
-def summarize_pmc_md(fetch_csv, write_csv, bench_json):
-    """Traffic summary of the paper-pipeline kernels (Gauss, Thres, Med) from
-    two rocprofv3 --pmc runs, scaled by the stream copy like summarize_pmc."""
+def summarize_pmc_md(fetch_csv, write_csv, bench_json, sq_csv=None):
+    """Traffic summary of the paper-pipeline kernels (Gauss, Thres, Med, fused)
+    from two rocprofv3 --pmc runs, scaled by the stream copy like
+    summarize_pmc; with a third run's SQ counters, the VALU issue use of each
+    kernel (a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles)."""
     import csv
 
     def per_dispatch(path, counter):
@@ -550,9 +552,9 @@ def summarize_pmc_md(fetch_csv, write_csv, bench_json):
     w = per_dispatch(write_csv, "WRITE_SIZE")
     fr = f["copy"][0] * 1024 / copy_bytes
     fw = w["copy"][0] * 1024 / copy_bytes
-    cmd = ("rocprofv3 --pmc {c} --kernel-include-regex 'k_gauss5|k_thres|k_med5|k_mdp_fused|k_stream_copy' -d pmc_{l} -o {l} "
-           "--output-format csv -- python3 /root/repo/bench.py --no-cpu --only md_paper --no-per-firing --steps 5 "
-           "--warmup 2 > {l}.json")
+    cmd = ("rocprofv3 --pmc {c} --kernel-include-regex 'k_gauss5|k_thres|k_med5|k_mdp_fused|k_stream_copy' "
+           "-d pmc_{l} -o {l} --output-format csv -- python3 /root/repo/bench.py --no-cpu --only md_paper "
+           "--no-per-firing --steps 5 --warmup 2 > {l}.json")
     lines = [
         "# HBM traffic of the paper's motion-detection pipeline kernels, 4096 frames of 320x240 per launch",
         "",
@@ -560,8 +562,9 @@ def summarize_pmc_md(fetch_csv, write_csv, bench_json):
         "",
         "    " + cmd.format(c="FETCH_SIZE", l="fetch"),
         "    " + cmd.format(c="WRITE_SIZE", l="write"),
+        "    " + cmd.format(c="SQ_INSTS_VALU SQ_WAVES", l="sq"),
         "    python3 /root/repo/bench.py --summarize-pmc-md pmc_fetch/fetch_counter_collection.csv "
-        "pmc_write/write_counter_collection.csv fetch.json",
+        "pmc_write/write_counter_collection.csv fetch.json pmc_sq/sq_counter_collection.csv",
         "",
         f"Stream copy of {copy_bytes} bytes: FETCH_SIZE {f['copy'][0]:.1f} KiB, WRITE_SIZE {w['copy'][0]:.1f} KiB "
         f"per dispatch; scale factors {fr:.4f} (read) and {fw:.4f} (write) counter bytes per byte moved.",
@@ -575,6 +578,32 @@ def summarize_pmc_md(fetch_csv, write_csv, bench_json):
         alg = b["md_paper"]["kernels"][k]["algorithmic_bytes"]
         lines.append(f"| {pat} | {f[k][1]} / {w[k][1]} | {rd:.0f} | {wr:.0f} | {alg} | {(rd + wr) / alg:.4f} |")
     lines.append("")
+    if sq_csv:
+        sq = {}
+        durs = {}
+        with open(sq_csv) as fh:
+            for row in csv.DictReader(fh):
+                for k, pat in MD_KERNELS:
+                    if pat in row["Kernel_Name"]:
+                        d = sq.setdefault(k, {}).setdefault(row["Dispatch_Id"], {})
+                        d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+                        durs.setdefault(k, {})[row["Dispatch_Id"]] = (int(row["End_Timestamp"]) -
+                                                                     int(row["Start_Timestamp"])) * 1e-9
+        simds = 256 * 4
+        lines += ["VALU issue (third run, `--pmc SQ_INSTS_VALU SQ_WAVES`, same bench command): "
+                  "share of the 1024 SIMDs' cycles at 2.4 GHz spent issuing VALU instructions "
+                  "(4 cycles per wave64 instruction), over the dispatch's duration under the profiler.", "",
+                  "| kernel | waves | VALU instructions | duration us | VALU issue share |", "|---|---|---|---|---|"]
+        for k, pat in MD_KERNELS:
+            if k not in sq:
+                continue
+            ids = list(sq[k])
+            valu = sum(sq[k][i].get("SQ_INSTS_VALU", 0.0) for i in ids) / len(ids)
+            waves = sum(sq[k][i].get("SQ_WAVES", 0.0) for i in ids) / len(ids)
+            dur = sum(durs[k][i] for i in ids) / len(ids)
+            lines.append(f"| {pat} | {waves:.0f} | {valu:.3e} | {dur * 1e6:.1f} | "
+                         f"{valu * 4 / (simds * 2.4e9 * dur):.3f} |")
+        lines.append("")
     with open(MD_TRAFFIC_FILE, "w") as fh:
         fh.write("\n".join(lines))
     print("\n".join(lines))
@@ -593,13 +622,16 @@ def main():
                     help="stream-copy reference size in MiB (bandwidth and traffic-counter reference; 0: off)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
                     help="write the traffic summary from two rocprofv3 --pmc runs of this script (no GPU)")
-    ap.add_argument("--summarize-pmc-md", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
-                    help="same for the paper-pipeline kernels (runs with --only md_paper)")
+    ap.add_argument("--summarize-pmc-md", nargs="+", metavar="CSV_OR_JSON",
+                    help="FETCH_CSV WRITE_CSV BENCH_JSON [SQ_CSV]: same for the paper-pipeline kernels "
+                         "(runs with --only md_paper)")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return
     if args.summarize_pmc_md:
+        if len(args.summarize_pmc_md) not in (3, 4):
+            ap.error("--summarize-pmc-md takes FETCH_CSV WRITE_CSV BENCH_JSON [SQ_CSV]")
         summarize_pmc_md(*args.summarize_pmc_md)
         return
     if args.gpus != 1:
