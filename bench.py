@@ -290,6 +290,10 @@ def bench_md_paper(D, Graph, torch, steps=5, warmup=2, n_frames=4096):
     out = np.zeros((n, H, W), np.uint8)
     G.pop(p.out, out)
     nonempty = int((out.reshape(n, -1).max(axis=1) > 0).sum())
+    # channel memory: the paper's Eq. (1) sizing at this rate vs this run's rings
+    chans = [(p.inp, False), (p.g_cur, False), (p.g_delayed, True), (p.thr, False), (p.out, False)]
+    eq1 = sum(D.df_paper_channel_bytes(wh, rate, d) for _, d in chans)
+    rings = sum(G.status(f)[2] * wh for f, _ in chans)
     per_ms = float("nan")
     if PER_FIRING:
         # one more batch, fired one firing (4 frames) per actor call
@@ -306,6 +310,10 @@ def bench_md_paper(D, Graph, torch, steps=5, warmup=2, n_frames=4096):
                 fps_three_actors=round(n / (ms_sep * 1e-3), 1), ms_per_batch_three_actors=round(ms_sep, 4),
                 fps_fused=round(n / (ms_fused * 1e-3), 1), ms_per_batch_fused=round(ms_fused, 4),
                 kernels=kern, frames_with_motion=nonempty,
+                channel_bytes={"paper_eq1": eq1, "rings": rings,
+                               "note": "Eq. (1) double/triple buffers hold one firing per channel; the rings "
+                                       "hold whole batches (inner rings one batch, host-facing rings all "
+                                       "batches pushed ahead of the timed steps)"},
                 parity="tests/test_gpu_md_paper.py::test_full_size_sampled_frames and "
                        "::test_chain_full_size_sampled_frames (same workload and batch)",
                 per_firing_fps=num(n / (per_ms * 1e-3), 1), speedup_vs_per_firing=num(per_ms / ms_sep, 2),

@@ -149,6 +149,15 @@ typedef struct {
   int32_t threshold;       /* Thres: 0..255; ignored by Gauss and Med        */
 } df_frame_params;
 
+/* Bytes of a channel sized by the paper's rule, Eq. (1) of Sec. 3.2:
+ * token_bytes * (3*rate + 1) with a delay token (the buffer of Fig. 2),
+ * token_bytes * 2*rate without (a double buffer).  A host-side helper for
+ * comparing footprints: this library's rings are sized by the caller
+ * instead (a power of two of at least the batch), so that a batch of many
+ * firings can sit in one channel.  Returns -1 for token_bytes < 1 or
+ * rate < 1. */
+int64_t df_paper_channel_bytes(int64_t token_bytes, int64_t rate, int32_t has_delay);
+
 /* ------------------------------------------------------------------ graph */
 
 /* Create an empty network on HIP device `hip_device`.  `hip_stream` is a

@@ -71,6 +71,11 @@ static int64_t dtype_bytes(int dt) {
 
 extern "C" const char *df_version(void) { return "dfhip 0.1 gfx950"; }
 
+extern "C" int64_t df_paper_channel_bytes(int64_t token_bytes, int64_t rate, int32_t has_delay) {
+  if (token_bytes < 1 || rate < 1) return -1;
+  return token_bytes * (has_delay ? 3 * rate + 1 : 2 * rate);
+}
+
 extern "C" const char *df_last_error(const df_graph *g) {
   if (g) return g->last_error.c_str();
   return g_tls_error.c_str();
@@ -792,12 +797,21 @@ extern "C" df_status df_fire_pipeline(df_graph *g, int32_t gauss, int32_t thres,
   if (st) return st;
   int64_t adm = std::min({n, av / r, space_of(fcur) / r, space_of(fthr) / r, space_of(fout) / r});
   if (fdel) adm = std::min(adm, space_of(*fdel) / r);
+  const int p_prev = ta.ports[DF_THRES_PREV];
+  if (p_prev != p_del) {
+    // Thres's previous-frame channel is not fed by this Gauss: its tokens
+    // must already be there
+    int64_t ap;
+    st = available(g, g->fifos[p_prev], n * r, &ap);
+    if (st) return st;
+    adm = std::min(adm, ap / r);
+  }
   if (adm < n && !(flags & DF_FIRE_PARTIAL))
     return fail(g, DF_EAGAIN, "only %lld of %lld firings admissible", (long long)adm, (long long)n);
   n = adm;
   if (n_fired) *n_fired = n;
   if (n == 0) return DF_OK;
-  const bool fused = !(flags & DF_PIPE_SEPARATE) && fdel && ta.ports[DF_THRES_PREV] == p_del &&
+  const bool fused = !(flags & DF_PIPE_SEPARATE) && fdel && p_prev == p_del &&
                      mdp_fused_supported(gp.width, gp.height) && fcur.write_lo == fcur.write_hi &&
                      fcur.write_lo == fcur.read_h && fthr.write_lo == fthr.write_hi && fthr.write_lo == fthr.read_h &&
                      fdel->write_lo == fdel->write_hi && fdel->write_lo - fdel->read_h == 1;

@@ -79,6 +79,7 @@ _SIGS = {
     "df_dpd_coeff_adjoint_work_bytes": ([_I64, _I64, _I64, _I32, _I32], _I64),
     "df_mp_input_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I32, _I32], _I32),
     "df_stream_copy": ([_P, _P, _P, _I64], _I32),
+    "df_paper_channel_bytes": ([_I64, _I64, _I32], _I64),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -136,6 +137,11 @@ def _dev_ptr(t):
 
 def df_version() -> str:
     return _lib.df_version().decode()
+
+
+def df_paper_channel_bytes(token_bytes: int, rate: int, has_delay: bool) -> int:
+    """Channel bytes by the paper's sizing rule (host arithmetic, -1 if invalid)."""
+    return int(_lib.df_paper_channel_bytes(token_bytes, rate, 1 if has_delay else 0))
 
 
 def df_graph_create(device: int = 0, stream=None) -> int:

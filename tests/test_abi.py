@@ -90,3 +90,15 @@ def test_stream_copy_validation():
     assert lib.df_stream_copy(None, None, None, 24) == D.DF_EINVAL     # not a multiple of 16
     assert lib.df_stream_copy(None, None, None, -16) == D.DF_EINVAL
     assert lib.df_stream_copy(None, None, None, 32) == D.DF_EINVAL     # null pointers
+
+
+def test_paper_channel_bytes_matches_eq1():
+    """The library's Eq. (1) helper (host arithmetic) against the oracle's,
+    and the motion network's total against Table 1 (3.46 MB)."""
+    from oracle import fifo_layout as fl
+    from paper_1611_03226_amd import dfhip as D
+    for s, r, d in [(1, 1, False), (8, 4096, False), (76800, 4, True), (4, 32768, True), (3, 7, True)]:
+        assert D.df_paper_channel_bytes(s, r, d) == fl.capacity_bytes(s, r, d)
+    total = sum(D.df_paper_channel_bytes(s, r, d) for s, r, d in fl.paper_motion_channels(320, 240, 4))
+    assert round(total / 1e6, 2) == 3.46
+    assert D.df_paper_channel_bytes(0, 4, False) == -1 and D.df_paper_channel_bytes(8, 0, True) == -1

@@ -296,3 +296,31 @@ def test_chain_full_size_sampled_frames():
         prev = omd.gauss5(w.frames[k - 1]) if k else np.zeros((240, 320), np.uint8)
         want = omd.med5(omd.thres(omd.gauss5(w.frames[k]), prev, 20))
         assert np.array_equal(out[k], want), k
+
+
+def test_chain_with_host_fed_previous_frames():
+    """Gauss's second output unconnected, Thres's previous frames pushed by
+    the host: the chain runs as three actors, and its admission counts the
+    host-fed channel (no partial chain on DF_EAGAIN)."""
+    from paper_1611_03226_amd import dfhip as D
+    from paper_1611_03226_amd.graph import Graph
+    say("md_paper chain with host-fed previous frames")
+    rng = np.random.default_rng(35)
+    W, H = 32, 12
+    a = rng.integers(0, 256, (8, H, W)).astype(np.uint8)
+    b = rng.integers(0, 256, (8, H, W)).astype(np.uint8)
+    with Graph(0) as G:
+        p = G.paper_motion_pipeline(W, H, 30, 4, cap=16, second_output=False)
+        G.push(p.inp, a)
+        G.push(p.g_delayed, b[:3])                  # the channel's zero token + 3 frames: one firing
+        with pytest.raises(D.DFError) as e:
+            p.fire_chain(G, 2)
+        assert e.value.code == D.DF_EAGAIN
+        assert G.status(p.inp)[:2] == (0, 8) and G.status(p.g_cur)[:2] == (0, 0)
+        assert p.fire_chain(G, 2, partial=True) == 1
+        out = np.zeros((4, H, W), np.uint8)
+        assert G.pop(p.out, out) == 4
+        G.sync()
+    prev = np.concatenate([np.zeros((1, H, W), np.uint8), b[:3]])
+    for k in range(4):
+        assert np.array_equal(out[k], omd.med5(omd.thres(omd.gauss5(a[k]), prev[k], 30)))

@@ -142,3 +142,15 @@ def test_static_scene_gives_empty_mask_after_first_frame():
     f = np.random.default_rng(9).integers(0, 256, (8, 10)).astype(np.uint8)
     out = md.paper_motion_direct(np.stack([f] * 5), threshold=5)
     assert not out[1:].any()
+
+
+def test_eq1_capacity_reproduces_table1_motion_detection():
+    # Table 1: the proposed framework's heterogeneous motion detection
+    # (320x240 frames, token rate 4 on the GPU) allocates 3.46 MB of channel
+    # memory; Eq. (1) over its five channels gives 4*(2*4) + (3*4+1) = 45
+    # frames of 76,800 bytes
+    from oracle import fifo_layout as fl
+    assert fl.capacity_tokens(4, True) == 13 and fl.capacity_tokens(4, False) == 8
+    b = fl.network_bytes(fl.paper_motion_channels(320, 240, 4))
+    assert b == 45 * 76800
+    assert round(b / 1e6, 2) == 3.46
