@@ -321,6 +321,44 @@ def bench_md_paper(D, Graph, torch, steps=5, warmup=2, n_frames=4096):
                                    "i7-4770 + Radeon HD 7750 (OpenCL 1.2)": 6063})
 
 
+def bench_dpd_network(D, torch, steps=5, warmup=2):
+    """The scale workload (2^24 samples, 4096 firings of 4096, B 1..10, M 16)
+    through the network as the paper draws it (Poly -> per-branch channels ->
+    FIR_b -> Adder, three kernels over the batch) against the fused actor
+    body, both as stateless calls on the same device buffers."""
+    from workloads import dpd_scale
+    w = dpd_scale()
+    N, r = len(w.x), w.r
+    x = torch.from_numpy(w.x[None, :]).cuda()
+    c = torch.from_numpy(w.ctrl[None, :]).cuda()
+    h = torch.from_numpy(w.h).cuda()
+    y = torch.empty_like(x)
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_net = timed(lambda: D.df_dpd_forward_network(x, c, h, y, r, stream=st))
+    ms_fused = timed(lambda: D.df_dpd_forward(x, c, h, y, r, D.DF_HIST_BRANCH, stream=st))
+    eb = float(np.mean(w.ctrl))
+    net_bytes = (4 * eb + 2) * N * 8            # P: read x, write E[B] channels; FIR: read+write; A: read, write y
+    return dict(workload="dpd at scale as the P -> FIR_b -> A network with materialised branch channels",
+                ms_network=round(ms_net, 4), ms_fused=round(ms_fused, 4),
+                msps_network=round(N / (ms_net * 1e-3) / 1e6, 1), msps_fused=round(N / (ms_fused * 1e-3) / 1e6, 1),
+                fused_speedup=round(ms_net / ms_fused, 2), network_algorithmic_bytes=net_bytes,
+                network_GBps=round(net_bytes / (ms_net * 1e-3) / 1e9, 1),
+                network_hbm_frac=round(net_bytes / (ms_net * 1e-3) / HBM_PEAK, 4),
+                parity="tests/test_gpu_dpd_network.py::test_scale_workload_sampled_and_against_fused_body")
+
+
 def bench_instances(D, Graph, torch, steps=2):
     from paper_1611_03226_amd import tune
     from workloads import dpd_instances
@@ -624,7 +662,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,md_paper,instances,adaptation")
+    ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,md_paper,dpd_network,instances,adaptation")
     ap.add_argument("--no-per-firing", action="store_true", help="skip the per-firing launch comparisons")
     ap.add_argument("--calibrate-copy", type=int, default=1024, metavar="MIB",
                     help="stream-copy reference size in MiB (bandwidth and traffic-counter reference; 0: off)")
@@ -699,6 +737,7 @@ def main():
     extras = [("chain", lambda: bench_chain(D, Graph, torch)),
               ("motion", lambda: bench_motion(D, Graph, torch)),
               ("md_paper", lambda: bench_md_paper(D, Graph, torch)),
+              ("dpd_network", lambda: bench_dpd_network(D, torch)),
               ("instances", lambda: bench_instances(D, Graph, torch)),
               ("adaptation", lambda: bench_adaptation(D, torch))]
     if not args.no_extras:

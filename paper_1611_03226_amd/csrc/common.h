@@ -204,6 +204,22 @@ hipError_t launch_med5(const MdpArgs &a, hipStream_t s, const KTiming *t = nullp
 // Add delta to every counter ptr[0..n) (n <= 8) in one launch.
 hipError_t launch_advance_n(int64_t *const *ptr, int n, int64_t delta, hipStream_t s);
 
+// The predistortion network with materialised branch channels (rows of
+// nf firings of r samples; tables from the offset scan, off in samples).
+struct DpdNetArgs {
+  const float2 *x;       // [S][nf*r]
+  float2 *y;             // [S][nf*r]
+  const float2 *h;       // [B_max][M]
+  const int32_t *B;      // [S*nf] validated branch counts
+  const int64_t *off;    // [B_max][stride] channel offset of each firing's block
+  int64_t stride;        // S*nf
+  int64_t nf, r, S;
+  int32_t B_max, M;
+  float2 *chan;          // [B_max][S][nf*r] Poly -> FIR_b channels
+  float2 *firo;          // [B_max][S][nf*r] FIR_b -> Adder channels
+};
+hipError_t launch_dpd_network(const DpdNetArgs &a, hipStream_t s, const KTiming *t = nullptr);
+
 bool dpd_tiled_shape(int M);
 hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s);
 hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread,

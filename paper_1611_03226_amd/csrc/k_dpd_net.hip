@@ -1,0 +1,105 @@
+// The predistortion network of Sec. 4.2 run as the paper draws it: a Poly
+// actor P feeding one channel per branch, one FIR actor per branch, and an
+// Adder A, each a kernel over a whole batch, with the branch channels
+// materialised in device memory at the dynamic rates the control tokens set
+// (branch b receives a firing's r samples only when b < B of that firing).
+// Offsets into the branch channels come from the offset scan (k_scan
+// tables).  This is the unfused counterpart of the fused body in k_dpd.hip,
+// kept to show what the channels cost; it implements branch history only
+// (each FIR actor's delay line holds its own last inputs).
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace dfh {
+namespace {
+
+constexpr int kNetThreads = 256;
+
+__device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// P: for every sample of every firing, psi_b(x) = |x|^(2b) x into channel b
+// at the firing's offset, for b < B of the firing.
+__global__ __launch_bounds__(kNetThreads) void k_net_poly(DpdNetArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * kNetThreads + threadIdx.x;
+  const int64_t row_len = a.nf * a.r, total = a.S * row_len;
+  if (t >= total) return;
+  const int64_t s = t / row_len, rem = t - s * row_len, g = rem / a.r, i = rem - g * a.r;
+  const int64_t gg = s * a.nf + g;
+  const int Bg = a.B[gg];
+  const float2 x = a.x[t];
+  const float p = fmaf(x.x, x.x, x.y * x.y);
+  float2 v = x;
+  for (int b = 0; b < Bg; ++b) {
+    a.chan[(b * a.S + s) * row_len + a.off[b * a.stride + gg] + i] = v;
+    v = make_float2(v.x * p, v.y * p);
+  }
+}
+
+// FIR_b: one output per thread over the K_b samples channel b received in
+// row s (K_b = r times the number of firings with b < B), zero history
+// before the row's first sample.
+__global__ __launch_bounds__(kNetThreads) void k_net_fir(DpdNetArgs a) {
+  const int64_t row_len = a.nf * a.r;
+  const int64_t t = (int64_t)blockIdx.x * kNetThreads + threadIdx.x;
+  const int64_t bs = blockIdx.y;                      // b * S + s
+  if (t >= row_len) return;
+  const int b = (int)(bs / a.S);
+  const int64_t s = bs - (int64_t)b * a.S;
+  const int64_t g_last = s * a.nf + a.nf - 1;
+  const int64_t K = a.off[b * a.stride + g_last] + (a.B[g_last] > b ? a.r : 0);
+  if (t >= K) return;
+  const float2 *c = a.chan + bs * row_len;
+  const float2 *hb = a.h + (int64_t)b * a.M;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int m = 0; m < a.M && m <= t; ++m) {
+    const float2 u = cmul(hb[m], c[t - m]);
+    acc.x += u.x;
+    acc.y += u.y;
+  }
+  a.firo[bs * row_len + t] = acc;
+}
+
+// A: y = sum over b < B of FIR_b's output at the firing's offset.
+__global__ __launch_bounds__(kNetThreads) void k_net_add(DpdNetArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * kNetThreads + threadIdx.x;
+  const int64_t row_len = a.nf * a.r, total = a.S * row_len;
+  if (t >= total) return;
+  const int64_t s = t / row_len, rem = t - s * row_len, g = rem / a.r, i = rem - g * a.r;
+  const int64_t gg = s * a.nf + g;
+  const int Bg = a.B[gg];
+  float2 acc = make_float2(0.f, 0.f);
+  for (int b = 0; b < Bg; ++b) {
+    const float2 v = a.firo[(b * a.S + s) * row_len + a.off[b * a.stride + gg] + i];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  a.y[t] = acc;
+}
+
+}  // namespace
+
+hipError_t launch_dpd_network(const DpdNetArgs &a, hipStream_t s, const KTiming *t) {
+  const int64_t row_len = a.nf * a.r, total = a.S * row_len;
+  if (total <= 0) return hipSuccess;
+  const dim3 g1((unsigned)((total + kNetThreads - 1) / kNetThreads));
+  if (t)
+    hipExtLaunchKernelGGL(k_net_poly, g1, dim3(kNetThreads), 0, s, t->start, nullptr, 0, a);
+  else
+    hipLaunchKernelGGL(k_net_poly, g1, dim3(kNetThreads), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 g2((unsigned)((row_len + kNetThreads - 1) / kNetThreads), (unsigned)(a.B_max * a.S));
+  hipLaunchKernelGGL(k_net_fir, g2, dim3(kNetThreads), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (t)
+    hipExtLaunchKernelGGL(k_net_add, g1, dim3(kNetThreads), 0, s, nullptr, t->stop, 0, a);
+  else
+    hipLaunchKernelGGL(k_net_add, g1, dim3(kNetThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace dfh

@@ -28,17 +28,22 @@ df_status check_dpd_shape(int64_t S, int64_t len, int64_t r, int32_t B_max, int3
 struct Tables {
   int32_t *B = nullptr;
   int64_t *prev = nullptr;
+  int64_t *off = nullptr;
   int64_t *grp = nullptr;
   int64_t n = 0;
 };
 
 hipError_t make_tables(const int32_t *ctrl, int64_t S, int64_t nf, int64_t r, int32_t B_max, int32_t hist,
-                       hipStream_t s, Tables *t) {
+                       hipStream_t s, Tables *t, bool offsets = false) {
   t->n = S * nf;
   hipError_t e = hipMallocAsync((void **)&t->B, sizeof(int32_t) * std::max<int64_t>(t->n, 1), s);
   if (e != hipSuccess) return e;
   e = hipMallocAsync((void **)&t->prev, sizeof(int64_t) * std::max<int64_t>(t->n, 1) * B_max, s);
   if (e != hipSuccess) return e;
+  if (offsets) {
+    e = hipMallocAsync((void **)&t->off, sizeof(int64_t) * std::max<int64_t>(t->n, 1) * B_max, s);
+    if (e != hipSuccess) return e;
+  }
   e = hipMallocAsync((void **)&t->grp, 2 * sizeof(int64_t) * B_max * std::max<int64_t>(scan_groups(S, nf), 1), s);
   if (e != hipSuccess) return e;
   ScanArgs sa{};
@@ -51,6 +56,7 @@ hipError_t make_tables(const int32_t *ctrl, int64_t S, int64_t nf, int64_t r, in
   sa.hist_mode = hist;
   sa.B_out = t->B;
   sa.prev_out = t->prev;
+  sa.off_out = t->off;
   sa.grp = t->grp;
   sa.stride = t->n;
   sa.r = r;
@@ -60,6 +66,7 @@ hipError_t make_tables(const int32_t *ctrl, int64_t S, int64_t nf, int64_t r, in
 void free_tables(Tables *t, hipStream_t s) {
   if (t->B) (void)hipFreeAsync(t->B, s);
   if (t->prev) (void)hipFreeAsync(t->prev, s);
+  if (t->off) (void)hipFreeAsync(t->off, s);
   if (t->grp) (void)hipFreeAsync(t->grp, s);
 }
 
@@ -117,6 +124,44 @@ extern "C" df_status df_dpd_forward(void *stream, const void *x, const int32_t *
   }
   if (corr) (void)hipFreeAsync(corr, s);
   if (e != hipSuccess) return fail_hip(nullptr, e, "df_dpd_forward");
+  return DF_OK;
+}
+
+extern "C" df_status df_dpd_forward_network(void *stream, const void *x, const int32_t *ctrl, const void *h, void *y,
+                                            int64_t S, int64_t len, int64_t r, int32_t B_max, int32_t M) {
+  df_status st = check_dpd_shape(S, len, r, B_max, M, DF_HIST_BRANCH);
+  if (st) return st;
+  if (S == 0 || len == 0) return DF_OK;
+  if (!x || !ctrl || !h || !y) return fail(nullptr, DF_EINVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nf = len / r;
+  Tables t;
+  float2 *chan = nullptr, *firo = nullptr;
+  const size_t chan_bytes = sizeof(float2) * (size_t)B_max * (size_t)S * (size_t)len;
+  hipError_t e = make_tables(ctrl, S, nf, r, B_max, DF_HIST_BRANCH, s, &t, true);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&chan, chan_bytes, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&firo, chan_bytes, s);
+  if (e == hipSuccess) {
+    DpdNetArgs a{};
+    a.x = (const float2 *)x;
+    a.y = (float2 *)y;
+    a.h = (const float2 *)h;
+    a.B = t.B;
+    a.off = t.off;
+    a.stride = t.n;
+    a.nf = nf;
+    a.r = r;
+    a.S = S;
+    a.B_max = B_max;
+    a.M = M;
+    a.chan = chan;
+    a.firo = firo;
+    e = launch_dpd_network(a, s);
+  }
+  if (chan) (void)hipFreeAsync(chan, s);
+  if (firo) (void)hipFreeAsync(firo, s);
+  free_tables(&t, s);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "df_dpd_forward_network");
   return DF_OK;
 }
 

@@ -75,6 +75,7 @@ _SIGS = {
     "df_profile_read_actor": ([_P, _I32, C.POINTER(C.c_double), C.POINTER(_I64)], _I32),
     "df_debug_last_batch": ([_P, _I32, _P, _P, _P, _I64, C.POINTER(_I64)], _I32),
     "df_dpd_forward": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
+    "df_dpd_forward_network": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32], _I32),
     "df_dpd_coeff_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32, _P, _I64], _I32),
     "df_dpd_coeff_adjoint_work_bytes": ([_I64, _I64, _I64, _I32, _I32], _I64),
     "df_mp_input_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I32, _I32], _I32),
@@ -272,6 +273,14 @@ def df_dpd_forward(x, ctrl, h, y, r: int, hist: int = DF_HIST_BRANCH, stream=Non
     B, M = h.shape
     _check(_lib.df_dpd_forward(_stream_ptr(stream), _dev_ptr(x), None if ctrl is None else _dev_ptr(ctrl),
                                _dev_ptr(h), _dev_ptr(y), S, L, r, B, M, hist))
+
+
+def df_dpd_forward_network(x, ctrl, h, y, r: int, stream=None) -> None:
+    """Same as df_dpd_forward (branch history), through materialised branch channels."""
+    S, L = x.shape
+    B, M = h.shape
+    _check(_lib.df_dpd_forward_network(_stream_ptr(stream), _dev_ptr(x), _dev_ptr(ctrl), _dev_ptr(h), _dev_ptr(y),
+                                       S, L, r, B, M))
 
 
 def df_dpd_coeff_adjoint_work_bytes(S: int, L: int, r: int, B: int, M: int) -> int:
