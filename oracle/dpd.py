@@ -34,11 +34,24 @@ def basis(x: np.ndarray, b: int) -> np.ndarray:
     return p ** b * x
 
 
-def _check_ctrl(B, n_branches_max):
+def _check_ctrl(B, n_branches_max, control="count"):
     B = int(B)
+    if control == "mask":
+        if B < 0 or B >= (1 << n_branches_max):
+            raise ValueError(f"control mask {B} outside 0..2^{n_branches_max}-1")
+        return B
     if B < 0 or B > n_branches_max:
         raise ValueError(f"control token {B} outside 0..{n_branches_max}")
     return B
+
+
+def active(token, b, control="count") -> bool:
+    """Whether branch b is active in a firing: "count" tokens activate the
+    prefix b < B (the reading of Sec. 4.2 used throughout); "mask" tokens
+    activate the set bits, any subset of the branches (the paper's "which
+    set of the FIR filters")."""
+    token = int(token)
+    return bool((token >> b) & 1) if control == "mask" else b < token
 
 
 class Poly(Actor):
@@ -46,25 +59,25 @@ class Poly(Actor):
     for b < B and to 0 otherwise ("branch" history); with ``shared`` every
     output keeps rate r.  Input x always has rate r."""
 
-    def __init__(self, name, n_branches_max, shared=False):
+    def __init__(self, name, n_branches_max, shared=False, control="count"):
         super().__init__(name)
         self.B_max = n_branches_max
         self.shared = shared
+        self.mode = control
 
     def control(self, token):
-        B = _check_ctrl(token, self.B_max)
+        B = _check_ctrl(token, self.B_max, self.mode)
         rin = {"x": self.inputs["x"].rate}
         rout = {}
         for b in range(self.B_max):
             f = self.outputs[f"s{b}"]
-            rout[f"s{b}"] = f.rate if (self.shared or b < B) else 0
+            rout[f"s{b}"] = f.rate if (self.shared or active(B, b, self.mode)) else 0
         return rin, rout
 
     def fire(self, consumed, token):
-        B = int(token)
         x = consumed["x"]
-        n_out = self.B_max if self.shared else B
-        return {f"s{b}": basis(x, b) for b in range(n_out)}
+        return {f"s{b}": basis(x, b) for b in range(self.B_max)
+                if self.shared or active(token, b, self.mode)}
 
 
 class FIR(Actor):
@@ -96,25 +109,26 @@ class Adder(Actor):
     but only b < B is summed).  Output y always has rate r; y = sum_{b<B} u_b,
     zero when B = 0."""
 
-    def __init__(self, name, n_branches_max, shared=False):
+    def __init__(self, name, n_branches_max, shared=False, control="count"):
         super().__init__(name)
         self.B_max = n_branches_max
         self.shared = shared
+        self.mode = control
 
     def control(self, token):
-        B = _check_ctrl(token, self.B_max)
+        B = _check_ctrl(token, self.B_max, self.mode)
         rin = {}
         for b in range(self.B_max):
             f = self.inputs[f"u{b}"]
-            rin[f"u{b}"] = f.rate if (self.shared or b < B) else 0
+            rin[f"u{b}"] = f.rate if (self.shared or active(B, b, self.mode)) else 0
         return rin, {"y": self.outputs["y"].rate}
 
     def fire(self, consumed, token):
-        B = int(token)
         r = self.outputs["y"].rate
         y = np.zeros(r, np.complex128)
-        for b in range(B):
-            y = y + consumed[f"u{b}"]
+        for b in range(self.B_max):
+            if active(token, b, self.mode):
+                y = y + consumed[f"u{b}"]
         return {"y": y}
 
 
@@ -123,7 +137,7 @@ class DPDNetwork:
     with SrcC writing every control token to both cP and cA (control fan-out
     of the configuration actor C)."""
 
-    def __init__(self, x, ctrl, h, r, n_delay=0, initial=None, hist="branch"):
+    def __init__(self, x, ctrl, h, r, n_delay=0, initial=None, hist="branch", control="count"):
         h = np.asarray(h, np.complex128)
         B_max, M = h.shape
         if hist not in ("branch", "shared"):
@@ -144,7 +158,7 @@ class DPDNetwork:
         self.srcc = Source("SrcC", {"cP": ctrl, "cA": ctrl})
         self.srcc.connect_out("cP", self.fcP)
         self.srcc.connect_out("cA", self.fcA)
-        self.P = Poly("P", B_max, shared)
+        self.P = Poly("P", B_max, shared, control)
         self.P.connect_ctrl(self.fcP)
         self.P.connect_in("x", self.fx)
         self.firs = []
@@ -154,7 +168,7 @@ class DPDNetwork:
             f.connect_in("in", self.fs[b])
             f.connect_out("out", self.fu[b])
             self.firs.append(f)
-        self.A = Adder("A", B_max, shared)
+        self.A = Adder("A", B_max, shared, control)
         self.A.connect_ctrl(self.fcA)
         for b in range(B_max):
             self.A.connect_in(f"u{b}", self.fu[b])
@@ -169,12 +183,12 @@ class DPDNetwork:
 
 
 def run_dpd(x, ctrl, h, r, n_delay=0, initial=None, hist="branch",
-            policy="round_robin", seed=0) -> np.ndarray:
+            policy="round_robin", seed=0, control="count") -> np.ndarray:
     """Output stream y (complex128) of the DPD network fired to quiescence."""
-    return DPDNetwork(x, ctrl, h, r, n_delay, initial, hist).run(policy, seed)
+    return DPDNetwork(x, ctrl, h, r, n_delay, initial, hist, control).run(policy, seed)
 
 
-def run_dpd_streams(x, ctrl, h, r, hist="branch") -> np.ndarray:
+def run_dpd_streams(x, ctrl, h, r, hist="branch", control="count") -> np.ndarray:
     """Independent networks, one per row of x [S, L] (zero initial state, no
     delay tokens); ctrl [S, L/r] or None for all branches active."""
     x = np.asarray(x)
@@ -183,7 +197,7 @@ def run_dpd_streams(x, ctrl, h, r, hist="branch") -> np.ndarray:
     out = np.zeros((S, L), np.complex128)
     for s in range(S):
         c = np.full(L // r, h.shape[0]) if ctrl is None else np.asarray(ctrl)[s]
-        out[s] = run_dpd(x[s], c, h, r, hist=hist)
+        out[s] = run_dpd(x[s], c, h, r, hist=hist, control=control)
     return out
 
 

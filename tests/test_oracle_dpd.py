@@ -185,3 +185,52 @@ def test_delay_tokens_leave_d_samples_unconsumed():
     net.run()
     assert net.fx.count() == w.n_delay
     assert net.P.n_fired == w.n_firings
+
+
+# ------------------------------------------------------------------ mask control
+
+def test_prefix_masks_equal_branch_counts():
+    w = dpd_random(41, 12, 16, 5, 4)
+    masks = (1 << w.ctrl.astype(np.int64)) - 1          # B -> bits 0..B-1
+    y_count = dpd.run_dpd(w.x, w.ctrl, w.h, w.r)
+    y_mask = dpd.run_dpd(w.x, masks, w.h, w.r, control="mask")
+    assert np.array_equal(y_count, y_mask)
+
+
+def test_single_bit_masks_are_one_fir_over_its_compacted_channel():
+    # only branch b ever active: the output of a firing with the bit set is
+    # lfilter(h_b) of the concatenated basis samples of the active firings
+    w = dpd_random(42, 10, 8, 4, 5)
+    b = 2
+    on = np.random.default_rng(42).random(10) < 0.6
+    masks = np.where(on, 1 << b, 0)
+    y = dpd.run_dpd(w.x, masks, w.h, w.r, control="mask").reshape(10, 8)
+    xs = w.x.astype(np.complex128).reshape(10, 8)
+    chan = np.concatenate([dpd.basis(xs[j], b) for j in range(10) if on[j]])
+    u = scipy.signal.lfilter(w.h[b].astype(np.complex128), [1.0], chan).reshape(-1, 8)
+    k = 0
+    for j in range(10):
+        if on[j]:
+            assert np.allclose(y[j], u[k], rtol=0, atol=1e-12)
+            k += 1
+        else:
+            assert not y[j].any()
+
+
+def test_masks_on_disjoint_branch_sets_add():
+    # branches used by m1 are never used by m2 and vice versa, so every
+    # branch channel is the same in the combined network
+    w = dpd_random(43, 14, 8, 6, 4)
+    rng = np.random.default_rng(43)
+    m1 = rng.integers(0, 64, 14) & 0b010101                  # even branches only
+    m2 = rng.integers(0, 64, 14) & 0b101010                  # odd branches only
+    y1 = dpd.run_dpd(w.x, m1, w.h, w.r, control="mask")
+    y2 = dpd.run_dpd(w.x, m2, w.h, w.r, control="mask")
+    y12 = dpd.run_dpd(w.x, m1 | m2, w.h, w.r, control="mask")
+    assert np.allclose(y12, y1 + y2, rtol=0, atol=1e-12)
+
+
+def test_out_of_range_mask_is_rejected():
+    w = dpd_random(44, 2, 4, 3, 2)
+    with pytest.raises(ValueError):
+        dpd.run_dpd(w.x, np.array([1, 8]), w.h, w.r, control="mask")
