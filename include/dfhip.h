@@ -331,17 +331,22 @@ df_status df_dpd_forward(void *stream, const void *x, const int32_t *ctrl,
                          int64_t r, int32_t B_max, int32_t M, int32_t hist);
 
 /* The same y computed by the network of Sec. 4.2 as drawn: a Poly kernel
- * writing psi_b(x) of every firing to branch channel b (only for b < B of
- * the firing: the dynamic rates of Sec. 2.2), one FIR kernel per branch over
- * the samples its channel received, and an Adder kernel summing the active
- * branches' outputs at each firing's channel offsets (from the offset scan).
- * The 2*B_max*n_streams*len complex64 branch channels are allocated on
- * `stream` for the call.  Branch history only (the FIR actors' own delay
- * lines, DF_HIST_BRANCH); ctrl must not be NULL.  Results equal
- * df_dpd_forward's up to FP32 rounding order.  Errors as df_dpd_forward. */
+ * writing psi_b(x) of every firing to branch channel b (only for the
+ * firing's active branches: the dynamic rates of Sec. 2.2), one FIR kernel
+ * per branch over the samples its channel received, and an Adder kernel
+ * summing the active branches' outputs at each firing's channel offsets.
+ * ctrl_mode DF_CTRL_COUNT: a token B activates b < B (as everywhere else);
+ * DF_CTRL_MASK: a token is a bit mask of active branches, any subset (Sec.
+ * 4.2 lets the configuration actor select which set of FIR filters runs);
+ * out-of-range tokens count as 0.  The 2*B_max*n_streams*len complex64
+ * branch channels are allocated on `stream` for the call.  Branch history
+ * only (the FIR actors' own delay lines, DF_HIST_BRANCH); ctrl must not be
+ * NULL.  With count tokens the results equal df_dpd_forward's up to FP32
+ * rounding order.  Errors as df_dpd_forward. */
+enum { DF_CTRL_COUNT = 0, DF_CTRL_MASK = 1 };
 df_status df_dpd_forward_network(void *stream, const void *x, const int32_t *ctrl,
                                  const void *h, void *y, int64_t n_streams, int64_t len,
-                                 int64_t r, int32_t B_max, int32_t M);
+                                 int64_t r, int32_t B_max, int32_t M, int32_t ctrl_mode);
 
 /* Coefficient adjoint: grad_h[b][m] = sum over rows and samples n of
  * G[n] * conj(d y[n] / d h[b][m]), i.e. dL/dRe h + i dL/dIm h given

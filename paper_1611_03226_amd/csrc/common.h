@@ -217,8 +217,12 @@ struct DpdNetArgs {
   int32_t B_max, M;
   float2 *chan;          // [B_max][S][nf*r] Poly -> FIR_b channels
   float2 *firo;          // [B_max][S][nf*r] FIR_b -> Adder channels
+  int32_t mask_mode;     // 0: B[g] counts (branches b < B active), 1: B[g] is a bit mask
 };
 hipError_t launch_dpd_network(const DpdNetArgs &a, hipStream_t s, const KTiming *t = nullptr);
+// Tables for bit-mask control tokens: validated masks (out of range -> 0)
+// into B [S*nf] and channel offsets into off [B_max][S*nf], from ctrl [S][nf].
+hipError_t launch_mask_tables(const int32_t *ctrl, int32_t *B, int64_t *off, const DpdNetArgs &a, hipStream_t s);
 
 bool dpd_tiled_shape(int M);
 hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s);

@@ -4,9 +4,10 @@
 // materialised in device memory at the dynamic rates the control tokens set
 // (branch b receives a firing's r samples only when b < B of that firing).
 // Offsets into the branch channels come from the offset scan (k_scan
-// tables).  This is the unfused counterpart of the fused body in k_dpd.hip,
-// kept to show what the channels cost; it implements branch history only
-// (each FIR actor's delay line holds its own last inputs).
+// tables, or k_mask_tables for bit-mask control tokens, which activate any
+// set of branches).  This is the unfused counterpart of the fused body in
+// k_dpd.hip, kept to show what the channels cost; it implements branch
+// history only (each FIR actor's delay line holds its own last inputs).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -16,6 +17,10 @@ namespace dfh {
 namespace {
 
 constexpr int kNetThreads = 256;
+
+__device__ inline bool active(int token, int b, int mask_mode) {
+  return mask_mode ? ((token >> b) & 1) != 0 : b < token;
+}
 
 __device__ inline float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
@@ -33,8 +38,9 @@ __global__ __launch_bounds__(kNetThreads) void k_net_poly(DpdNetArgs a) {
   const float2 x = a.x[t];
   const float p = fmaf(x.x, x.x, x.y * x.y);
   float2 v = x;
-  for (int b = 0; b < Bg; ++b) {
-    a.chan[(b * a.S + s) * row_len + a.off[b * a.stride + gg] + i] = v;
+  const int n_b = a.mask_mode ? a.B_max : Bg;
+  for (int b = 0; b < n_b; ++b) {
+    if (active(Bg, b, a.mask_mode)) a.chan[(b * a.S + s) * row_len + a.off[b * a.stride + gg] + i] = v;
     v = make_float2(v.x * p, v.y * p);
   }
 }
@@ -50,7 +56,7 @@ __global__ __launch_bounds__(kNetThreads) void k_net_fir(DpdNetArgs a) {
   const int b = (int)(bs / a.S);
   const int64_t s = bs - (int64_t)b * a.S;
   const int64_t g_last = s * a.nf + a.nf - 1;
-  const int64_t K = a.off[b * a.stride + g_last] + (a.B[g_last] > b ? a.r : 0);
+  const int64_t K = a.off[b * a.stride + g_last] + (active(a.B[g_last], b, a.mask_mode) ? a.r : 0);
   if (t >= K) return;
   const float2 *c = a.chan + bs * row_len;
   const float2 *hb = a.h + (int64_t)b * a.M;
@@ -72,7 +78,9 @@ __global__ __launch_bounds__(kNetThreads) void k_net_add(DpdNetArgs a) {
   const int64_t gg = s * a.nf + g;
   const int Bg = a.B[gg];
   float2 acc = make_float2(0.f, 0.f);
-  for (int b = 0; b < Bg; ++b) {
+  const int n_b = a.mask_mode ? a.B_max : Bg;
+  for (int b = 0; b < n_b; ++b) {
+    if (!active(Bg, b, a.mask_mode)) continue;
     const float2 v = a.firo[(b * a.S + s) * row_len + a.off[b * a.stride + gg] + i];
     acc.x += v.x;
     acc.y += v.y;
@@ -80,7 +88,33 @@ __global__ __launch_bounds__(kNetThreads) void k_net_add(DpdNetArgs a) {
   a.y[t] = acc;
 }
 
+// Mask tables: one thread per (row, branch) walks the row's firings in
+// order (an exclusive count of the firings whose mask has bit b).
+__global__ __launch_bounds__(64) void k_mask_tables(const int32_t *ctrl, int32_t *B, int64_t *off, DpdNetArgs a) {
+  const int64_t q = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (q >= a.S * a.B_max) return;
+  const int64_t s = q / a.B_max;
+  const int b = (int)(q - s * a.B_max);
+  const int32_t lim = 1 << a.B_max;
+  int64_t cnt = 0;
+  for (int64_t g = 0; g < a.nf; ++g) {
+    const int64_t gg = s * a.nf + g;
+    int32_t m = ctrl[gg];
+    if (m < 0 || m >= lim) m = 0;
+    if (b == 0) B[gg] = m;
+    off[b * a.stride + gg] = cnt * a.r;
+    cnt += (m >> b) & 1;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_mask_tables(const int32_t *ctrl, int32_t *B, int64_t *off, const DpdNetArgs &a, hipStream_t s) {
+  const int64_t n = a.S * a.B_max;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mask_tables, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, ctrl, B, off, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_dpd_network(const DpdNetArgs &a, hipStream_t s, const KTiming *t) {
   const int64_t row_len = a.nf * a.r, total = a.S * row_len;

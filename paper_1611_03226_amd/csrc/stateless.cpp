@@ -128,9 +128,11 @@ extern "C" df_status df_dpd_forward(void *stream, const void *x, const int32_t *
 }
 
 extern "C" df_status df_dpd_forward_network(void *stream, const void *x, const int32_t *ctrl, const void *h, void *y,
-                                            int64_t S, int64_t len, int64_t r, int32_t B_max, int32_t M) {
+                                            int64_t S, int64_t len, int64_t r, int32_t B_max, int32_t M,
+                                            int32_t ctrl_mode) {
   df_status st = check_dpd_shape(S, len, r, B_max, M, DF_HIST_BRANCH);
   if (st) return st;
+  if (ctrl_mode != DF_CTRL_COUNT && ctrl_mode != DF_CTRL_MASK) return fail(nullptr, DF_EINVAL, "bad ctrl_mode");
   if (S == 0 || len == 0) return DF_OK;
   if (!x || !ctrl || !h || !y) return fail(nullptr, DF_EINVAL, "null pointer");
   hipStream_t s = (hipStream_t)stream;
@@ -138,7 +140,14 @@ extern "C" df_status df_dpd_forward_network(void *stream, const void *x, const i
   Tables t;
   float2 *chan = nullptr, *firo = nullptr;
   const size_t chan_bytes = sizeof(float2) * (size_t)B_max * (size_t)S * (size_t)len;
-  hipError_t e = make_tables(ctrl, S, nf, r, B_max, DF_HIST_BRANCH, s, &t, true);
+  hipError_t e = hipSuccess;
+  if (ctrl_mode == DF_CTRL_COUNT) {
+    e = make_tables(ctrl, S, nf, r, B_max, DF_HIST_BRANCH, s, &t, true);
+  } else {
+    t.n = S * nf;
+    e = hipMallocAsync((void **)&t.B, sizeof(int32_t) * t.n, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&t.off, sizeof(int64_t) * t.n * B_max, s);
+  }
   if (e == hipSuccess) e = hipMallocAsync((void **)&chan, chan_bytes, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&firo, chan_bytes, s);
   if (e == hipSuccess) {
@@ -156,7 +165,9 @@ extern "C" df_status df_dpd_forward_network(void *stream, const void *x, const i
     a.M = M;
     a.chan = chan;
     a.firo = firo;
-    e = launch_dpd_network(a, s);
+    a.mask_mode = ctrl_mode == DF_CTRL_MASK;
+    if (a.mask_mode) e = launch_mask_tables(ctrl, t.B, t.off, a, s);
+    if (e == hipSuccess) e = launch_dpd_network(a, s);
   }
   if (chan) (void)hipFreeAsync(chan, s);
   if (firo) (void)hipFreeAsync(firo, s);

@@ -28,6 +28,7 @@ DF_HIST_BRANCH, DF_HIST_SHARED = 0, 1
 DF_FIRE_PARTIAL = 1
 DF_FIRE_PERSISTENT, DF_FIRE_GRAPH = 1, 2
 DF_PIPE_SEPARATE = 2
+DF_CTRL_COUNT, DF_CTRL_MASK = 0, 1
 
 _NP_DTYPE = {DF_C64: np.complex64, DF_U8: np.uint8, DF_I32: np.int32, DF_I64: np.int64}
 
@@ -75,7 +76,7 @@ _SIGS = {
     "df_profile_read_actor": ([_P, _I32, C.POINTER(C.c_double), C.POINTER(_I64)], _I32),
     "df_debug_last_batch": ([_P, _I32, _P, _P, _P, _I64, C.POINTER(_I64)], _I32),
     "df_dpd_forward": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
-    "df_dpd_forward_network": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32], _I32),
+    "df_dpd_forward_network": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
     "df_dpd_coeff_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32, _P, _I64], _I32),
     "df_dpd_coeff_adjoint_work_bytes": ([_I64, _I64, _I64, _I32, _I32], _I64),
     "df_mp_input_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I32, _I32], _I32),
@@ -275,12 +276,13 @@ def df_dpd_forward(x, ctrl, h, y, r: int, hist: int = DF_HIST_BRANCH, stream=Non
                                _dev_ptr(h), _dev_ptr(y), S, L, r, B, M, hist))
 
 
-def df_dpd_forward_network(x, ctrl, h, y, r: int, stream=None) -> None:
-    """Same as df_dpd_forward (branch history), through materialised branch channels."""
+def df_dpd_forward_network(x, ctrl, h, y, r: int, mask: bool = False, stream=None) -> None:
+    """Same as df_dpd_forward (branch history), through materialised branch
+    channels; mask=True reads the control tokens as bit masks of active branches."""
     S, L = x.shape
     B, M = h.shape
     _check(_lib.df_dpd_forward_network(_stream_ptr(stream), _dev_ptr(x), _dev_ptr(ctrl), _dev_ptr(h), _dev_ptr(y),
-                                       S, L, r, B, M))
+                                       S, L, r, B, M, DF_CTRL_MASK if mask else DF_CTRL_COUNT))
 
 
 def df_dpd_coeff_adjoint_work_bytes(S: int, L: int, r: int, B: int, M: int) -> int:

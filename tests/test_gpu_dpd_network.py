@@ -1,7 +1,8 @@
 """GPU parity of the predistortion network run with materialised branch
 channels (Poly -> FIR_b -> Adder, Sec. 4.2, dynamic rates of Sec. 2.2)
 through the C ABI: against the FP64 oracle network per firing (relative-to-RMS
-tolerance of the FP32 path), and against the fused actor body."""
+tolerance of the FP32 path), against the fused actor body, and with bit-mask
+control tokens (any set of active branches)."""
 import numpy as np
 import pytest
 
@@ -18,11 +19,11 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def _network(x, ctrl, h, r):
+def _network(x, ctrl, h, r, mask=False):
     import torch
     from paper_1611_03226_amd import dfhip as D
     y = torch.empty(x.shape, dtype=torch.complex64, device="cuda")
-    D.df_dpd_forward_network(_t(x), _t(ctrl), _t(h), y, r)
+    D.df_dpd_forward_network(_t(x), _t(ctrl), _t(h), y, r, mask=mask)
     torch.cuda.synchronize()
     return y.cpu().numpy()
 
@@ -81,3 +82,40 @@ def test_scale_workload_sampled_and_against_fused_body():
     idx = np.random.default_rng(3).integers(0, len(w.x), 200)
     ref = odpd.output_at(w.x, w.ctrl, w.h, w.r, idx)
     assert np.max(np.abs(y[idx] - ref)) <= DPD_TOL * rms
+
+
+@pytest.mark.parametrize("S,nf,r,B,M", [(2, 21, 64, 10, 16), (3, 9, 5, 6, 6), (1, 33, 16, 16, 3)])
+def test_mask_control_matches_oracle(S, nf, r, B, M):
+    say(f"dpd network masks: S={S} nf={nf} r={r} B={B} M={M}")
+    rng = np.random.default_rng(S * 77 + nf + B)
+    x = complex_gaussian(rng, (S, nf * r))
+    h = dpd_coeffs(rng, B, M)
+    masks = rng.integers(0, 1 << B, (S, nf)).astype(np.int32)
+    masks[:, 1] = 0
+    masks[0, 2] = (1 << B) - 1
+    y = _network(x, masks, h, r, mask=True)
+    ref = odpd.run_dpd_streams(x, masks, h, r, "branch", control="mask")
+    for s in range(S):
+        worst, _, bad_zero = rel_rms_per_firing(y[s], ref[s], r)
+        assert worst <= DPD_TOL and bad_zero == 0, (s, worst, bad_zero)
+
+
+def test_prefix_masks_equal_counts_and_out_of_range_masks_are_zero():
+    say("dpd network: prefix masks vs counts, out-of-range masks")
+    rng = np.random.default_rng(78)
+    S, nf, r, B, M = 2, 12, 32, 8, 8
+    x = complex_gaussian(rng, (S, nf * r))
+    h = dpd_coeffs(rng, B, M)
+    counts = rng.integers(0, B + 1, (S, nf)).astype(np.int32)
+    y_count = _network(x, counts, h, r)
+    y_mask = _network(x, ((1 << counts.astype(np.int64)) - 1).astype(np.int32), h, r, mask=True)
+    assert np.array_equal(y_count, y_mask)            # same channel offsets, same kernels
+    bad = counts.copy()
+    bad[0, 3] = 1 << B                                 # out of range: no branch active
+    bad[1, 5] = -1
+    y_bad = _network(x, bad, h, r, mask=True)
+    fixed = bad.copy()
+    fixed[0, 3] = 0
+    fixed[1, 5] = 0
+    assert np.array_equal(y_bad, _network(x, fixed, h, r, mask=True))
+    assert not y_bad[0, 3 * r:4 * r].any()
