@@ -359,6 +359,60 @@ def bench_dpd_network(D, torch, steps=5, warmup=2):
                 parity="tests/test_gpu_dpd_network.py::test_scale_workload_sampled_and_against_fused_body")
 
 
+def bench_host_io(D, Graph, torch, steps=3, warmup=1):
+    """PCIe-inclusive rates: each step pushes its batch from host memory,
+    fires it, and pops the outputs back to host memory (the boundary's host
+    pointer forms, which copy and synchronise).  DPD at scale (2^24 samples)
+    and the paper's motion pipeline (4096 frames of 320x240, fused chain)."""
+    from workloads import dpd_scale, paper_motion
+    res = {}
+    w = dpd_scale()
+    N, nf = len(w.x), w.n_firings
+    G = Graph(0)
+    ch = G.dpd_chain(w.h, w.r, cap_x=pow2(2 * N), cap_ctrl=pow2(2 * nf), cap_y=pow2(2 * N))
+    # page-locked host buffers (torch pin_memory) viewed as numpy arrays
+    x = torch.from_numpy(np.ascontiguousarray(w.x)).pin_memory().numpy()
+    c = torch.from_numpy(np.ascontiguousarray(w.ctrl)).pin_memory().numpy()
+    y = torch.empty(N, dtype=torch.complex64).pin_memory().numpy()
+
+    def dpd_step():
+        G.push(ch.ctrl, c)
+        G.push(ch.x, x)
+        G.fire(ch.actor, nf)
+        G.pop(ch.y, y)
+    for _ in range(warmup):
+        dpd_step()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dpd_step()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    G.close()
+    res["dpd_scale"] = {"ms_per_step": round(ms, 3), "msps": round(N / (ms * 1e-3) / 1e6, 1),
+                        "host_bytes_per_step": 16 * N + 4 * nf}
+    m = paper_motion(n_frames=4096)
+    n, H, W = m.frames.shape
+    G = Graph(0)
+    p = G.paper_motion_pipeline(W, H, 20, 4, cap=pow2(n + 1))
+    f = torch.from_numpy(np.ascontiguousarray(m.frames)).pin_memory().numpy()
+    out = torch.empty(f.shape, dtype=torch.uint8).pin_memory().numpy()
+
+    def md_step():
+        G.push(p.inp, f)
+        p.fire_chain(G, n // 4)
+        G.pop(p.out, out)
+    for _ in range(warmup):
+        md_step()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        md_step()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    G.close()
+    res["md_paper_fused"] = {"ms_per_step": round(ms, 3), "fps": round(n / (ms * 1e-3), 1),
+                             "host_bytes_per_step": 2 * n * W * H}
+    res["note"] = "host buffers page-locked; the HBM-resident rates are the main line and extras"
+    return res
+
+
 def bench_instances(D, Graph, torch, steps=2):
     from paper_1611_03226_amd import tune
     from workloads import dpd_instances
@@ -662,7 +716,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,md_paper,dpd_network,instances,adaptation")
+    ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,md_paper,dpd_network,host_io,instances,adaptation")
     ap.add_argument("--no-per-firing", action="store_true", help="skip the per-firing launch comparisons")
     ap.add_argument("--calibrate-copy", type=int, default=1024, metavar="MIB",
                     help="stream-copy reference size in MiB (bandwidth and traffic-counter reference; 0: off)")
@@ -738,6 +792,7 @@ def main():
               ("motion", lambda: bench_motion(D, Graph, torch)),
               ("md_paper", lambda: bench_md_paper(D, Graph, torch)),
               ("dpd_network", lambda: bench_dpd_network(D, torch)),
+              ("host_io", lambda: bench_host_io(D, Graph, torch)),
               ("instances", lambda: bench_instances(D, Graph, torch)),
               ("adaptation", lambda: bench_adaptation(D, torch))]
     if not args.no_extras:
