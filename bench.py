@@ -389,6 +389,19 @@ def bench_host_io(D, Graph, torch, steps=3, warmup=1):
     G.close()
     res["dpd_scale"] = {"ms_per_step": round(ms, 3), "msps": round(N / (ms * 1e-3) / 1e6, 1),
                         "host_bytes_per_step": 16 * N + 4 * nf}
+    # the same stream with input copies, firings and output copies overlapped
+    # (df_stream_dpd, 8 batches of 512 firings, rings of two batches)
+    nbat, fpb = 8, nf // 8
+    G = Graph(0)
+    ch = G.dpd_chain(w.h, w.r, cap_x=pow2(2 * fpb * w.r), cap_ctrl=pow2(2 * fpb), cap_y=pow2(2 * fpb * w.r))
+    D.df_stream_dpd(G.g, ch.actor, x, c, y, nbat, fpb)          # warm-up
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        D.df_stream_dpd(G.g, ch.actor, x, c, y, nbat, fpb)
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    G.close()
+    res["dpd_scale_overlapped"] = {"ms_per_step": round(ms, 3), "msps": round(N / (ms * 1e-3) / 1e6, 1),
+                                   "batches": nbat, "firings_per_batch": fpb}
     m = paper_motion(n_frames=4096)
     n, H, W = m.frames.shape
     G = Graph(0)

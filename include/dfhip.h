@@ -283,6 +283,23 @@ enum { DF_PIPE_SEPARATE = 2 };
 df_status df_fire_pipeline(df_graph *g, int32_t gauss, int32_t thres, int32_t med,
                            int64_t n_firings, int flags, int64_t *n_fired);
 
+/* Stream host data through one predistortion actor: n_batches batches of
+ * firings_per_batch firings, control tokens from ctrl_host (int32
+ * [n_batches*firings_per_batch]), samples from x_host (complex64
+ * [n_batches*firings_per_batch*firing_size]), outputs to y_host (same
+ * size).  The same tokens as pushing, firing and popping each batch in turn,
+ * but batch k's input copy, batch k-1's firing and batch k-2's output copy
+ * run concurrently (two copy streams beside the graph's stream, ordered by
+ * events; the analogue of GPP-mapped source/sink actors running beside the
+ * GPU actors, Sec. 3.3).  Host buffers should be page-locked for the copies
+ * to overlap.  The control and output channels must be empty and written /
+ * read by the host; every channel must hold two batches (the input channel
+ * two batches plus its pending tokens).  Returns when all outputs are in
+ * y_host.  Errors: DF_EINVAL, DF_ESTATE, DF_EDEVICE. */
+df_status df_stream_dpd(df_graph *g, int32_t actor, const void *x_host,
+                        const int32_t *ctrl_host, void *y_host, int64_t n_batches,
+                        int64_t firings_per_batch);
+
 /* Tile configuration of the DPD body kernels: tile_outputs samples per
  * workgroup work item (a multiple of 64*outputs_per_thread, at most
  * 512*outputs_per_thread), outputs_per_thread (4 or 8), and the persistent

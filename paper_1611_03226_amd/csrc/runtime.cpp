@@ -149,6 +149,8 @@ extern "C" df_status df_graph_destroy(df_graph *g) {
   for (auto &a : g->actors) free_actor(a);
   (void)hipFree(g->idx_pool);
   (void)hipFree(g->err_dev);
+  if (g->copy_in) (void)hipStreamDestroy(g->copy_in);
+  if (g->copy_out) (void)hipStreamDestroy(g->copy_out);
   if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
   delete g;
   return DF_OK;
@@ -379,9 +381,11 @@ extern "C" df_status df_connect(df_graph *g, int32_t actor, int32_t port, int32_
 
 // ------------------------------------------------------------------ push / pop
 
-// Copy n tokens between a ring (starting at token position pos) and a flat buffer.
+// Copy n tokens between a ring (starting at token position pos) and a flat
+// buffer, on stream `st` (the graph's stream when null).
 static hipError_t ring_copy(df_graph *g, Fifo &f, int64_t pos, void *flat, int64_t n, bool to_ring,
-                            bool flat_on_device) {
+                            bool flat_on_device, hipStream_t st = nullptr) {
+  if (!st) st = g->stream;
   const int64_t slot = pos & f.mask;
   const int64_t first = std::min(n, f.cap - slot);
   const size_t tb = (size_t)f.token_bytes;
@@ -391,11 +395,11 @@ static hipError_t ring_copy(df_graph *g, Fifo &f, int64_t pos, void *flat, int64
                                : (flat_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
   hipError_t e;
   if (to_ring) {
-    e = hipMemcpyAsync(ring + slot * tb, p, first * tb, kind, g->stream);
-    if (e == hipSuccess && n > first) e = hipMemcpyAsync(ring, p + first * tb, (n - first) * tb, kind, g->stream);
+    e = hipMemcpyAsync(ring + slot * tb, p, first * tb, kind, st);
+    if (e == hipSuccess && n > first) e = hipMemcpyAsync(ring, p + first * tb, (n - first) * tb, kind, st);
   } else {
-    e = hipMemcpyAsync(p, ring + slot * tb, first * tb, kind, g->stream);
-    if (e == hipSuccess && n > first) e = hipMemcpyAsync(p + first * tb, ring, (n - first) * tb, kind, g->stream);
+    e = hipMemcpyAsync(p, ring + slot * tb, first * tb, kind, st);
+    if (e == hipSuccess && n > first) e = hipMemcpyAsync(p + first * tb, ring, (n - first) * tb, kind, st);
   }
   return e;
 }
@@ -869,6 +873,101 @@ extern "C" df_status df_fire(df_graph *g, int32_t actor, int64_t n, int flags, i
   if (a.kind == DF_ACTOR_DPD) return fire_dpd(g, a, n, flags, n_fired);
   if (a.kind == DF_ACTOR_MOTION) return fire_motion(g, a, n, flags, n_fired);
   return fire_frames(g, a, n, flags, n_fired);
+}
+
+// Host-to-host streaming through one predistortion actor with the three
+// transfers overlapped: batch k's input copy (stream copy_in), batch k-1's
+// firing (graph stream) and batch k-2's output copy (stream copy_out) run
+// at once.  Events order every ring region between its writer and readers:
+// an input copy waits for the firing that last read the slots it fills, a
+// firing waits for its input copy and for the output copy that last drained
+// the slots it writes, an output copy waits for its firing.
+extern "C" df_status df_stream_dpd(df_graph *g, int32_t actor, const void *x_host, const int32_t *ctrl_host,
+                                   void *y_host, int64_t n_batches, int64_t firings_per_batch) {
+  ENTER(g);
+  if (actor < 0 || actor >= (int)g->actors.size()) return fail(g, DF_EINVAL, "bad actor id %d", actor);
+  Actor &a = g->actors[actor];
+  if (a.kind != DF_ACTOR_DPD) return fail(g, DF_EINVAL, "not a predistortion actor");
+  if (n_batches < 0 || firings_per_batch < 1) return fail(g, DF_EINVAL, "bad batch counts");
+  if (a.ports[DF_DPD_CTRL] < 0 || a.ports[DF_DPD_IN] < 0 || a.ports[DF_DPD_OUT] < 0)
+    return fail(g, DF_ESTATE, "predistortion actor has unconnected ports");
+  if (n_batches == 0) return DF_OK;
+  if (!x_host || !ctrl_host || !y_host) return fail(g, DF_EINVAL, "null pointer");
+  Fifo &fc = g->fifos[a.ports[DF_DPD_CTRL]];
+  Fifo &fx = g->fifos[a.ports[DF_DPD_IN]];
+  Fifo &fy = g->fifos[a.ports[DF_DPD_OUT]];
+  if (fc.writer >= 0 || fx.writer >= 0 || fy.reader >= 0)
+    return fail(g, DF_ESTATE, "the actor's channels must be fed and drained by the host");
+  if (fy.write_lo != fy.write_hi || fy.write_lo != fy.read_h || fc.write_hi != fc.read_h)
+    return fail(g, DF_ESTATE, "output and control channels must be empty");
+  const int64_t nb = firings_per_batch, ns = nb * a.dp.firing_size;
+  if (fx.cap < 2 * ns + (fx.write_hi - fx.read_h) || fc.cap < 2 * nb || fy.cap < 2 * ns)
+    return fail(g, DF_EINVAL, "channels must hold two batches (plus pending input tokens)");
+  df_status st = ensure_dpd_scratch(g, a, nb);
+  if (st) return st;
+  if (!g->copy_in) HIPCHK(g, hipStreamCreateWithFlags(&g->copy_in, hipStreamNonBlocking));
+  if (!g->copy_out) HIPCHK(g, hipStreamCreateWithFlags(&g->copy_out, hipStreamNonBlocking));
+  std::vector<hipEvent_t> ev_in(n_batches), ev_fired(n_batches), ev_out(n_batches);
+  for (int64_t k = 0; k < n_batches; ++k) {
+    HIPCHK(g, hipEventCreateWithFlags(&ev_in[k], hipEventDisableTiming));
+    HIPCHK(g, hipEventCreateWithFlags(&ev_fired[k], hipEventDisableTiming));
+    HIPCHK(g, hipEventCreateWithFlags(&ev_out[k], hipEventDisableTiming));
+  }
+  hipEvent_t start;
+  HIPCHK(g, hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  HIPCHK(g, hipEventRecord(start, g->stream));       // earlier work on the graph
+  HIPCHK(g, hipStreamWaitEvent(g->copy_in, start, 0));
+  HIPCHK(g, hipStreamWaitEvent(g->copy_out, start, 0));
+  const int64_t x_read0 = fx.read_h, x_write0 = fx.write_hi, y0 = fy.write_hi;
+  const char *xh = (const char *)x_host;
+  const char *ch = (const char *)ctrl_host;
+  char *yh = (char *)y_host;
+  // the batch whose slots a write of positions up to `last` reuses: the one
+  // holding position last - cap, if any (batches start at `base`, n apart)
+  auto reused = [](int64_t last, int64_t cap, int64_t base, int64_t n) -> int64_t {
+    const int64_t p = last - cap;
+    return p < base ? -1 : (p - base) / n;
+  };
+  for (int64_t k = 0; k < n_batches; ++k) {
+    // input: control tokens and samples of batch k
+    int64_t j = std::max(reused(x_write0 + (k + 1) * ns - 1, fx.cap, x_read0, ns),
+                         reused(fc.write_hi + nb - 1, fc.cap, fc.read_h - k * nb, nb));
+    if (j >= k) return fail(g, DF_EINVAL, "channel too small for two batches");
+    if (j >= 0) HIPCHK(g, hipStreamWaitEvent(g->copy_in, ev_fired[j], 0));
+    HIPCHK(g, ring_copy(g, fc, fc.write_hi, (void *)(ch + k * nb * sizeof(int32_t)), nb, true, false, g->copy_in));
+    HIPCHK(g, launch_advance(fc.idx + 1, nb, g->copy_in));
+    HIPCHK(g, ring_copy(g, fx, fx.write_hi, (void *)(xh + k * ns * fx.token_bytes), ns, true, false, g->copy_in));
+    HIPCHK(g, launch_advance(fx.idx + 1, ns, g->copy_in));
+    HIPCHK(g, hipEventRecord(ev_in[k], g->copy_in));
+    fc.write_lo += nb;
+    fc.write_hi += nb;
+    fx.write_lo += ns;
+    fx.write_hi += ns;
+    // firing of batch k
+    HIPCHK(g, hipStreamWaitEvent(g->stream, ev_in[k], 0));
+    j = reused(y0 + (k + 1) * ns - 1, fy.cap, y0, ns);
+    if (j >= k) return fail(g, DF_EINVAL, "channel too small for two batches");
+    if (j >= 0) HIPCHK(g, hipStreamWaitEvent(g->stream, ev_out[j], 0));
+    st = dpd_enqueue(g, a, nb);
+    if (st) return st;
+    HIPCHK(g, hipEventRecord(ev_fired[k], g->stream));
+    // output of batch k
+    HIPCHK(g, hipStreamWaitEvent(g->copy_out, ev_fired[k], 0));
+    HIPCHK(g, ring_copy(g, fy, fy.read_h, (void *)(yh + k * ns * fy.token_bytes), ns, false, false, g->copy_out));
+    HIPCHK(g, launch_advance(fy.idx + 0, ns, g->copy_out));
+    HIPCHK(g, hipEventRecord(ev_out[k], g->copy_out));
+    fy.read_h += ns;
+  }
+  HIPCHK(g, hipStreamWaitEvent(g->stream, ev_in[n_batches - 1], 0));
+  HIPCHK(g, hipStreamWaitEvent(g->stream, ev_out[n_batches - 1], 0));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  for (int64_t k = 0; k < n_batches; ++k) {
+    (void)hipEventDestroy(ev_in[k]);
+    (void)hipEventDestroy(ev_fired[k]);
+    (void)hipEventDestroy(ev_out[k]);
+  }
+  (void)hipEventDestroy(start);
+  return DF_OK;
 }
 
 extern "C" df_status df_set_tile(df_graph *g, int32_t tile_outputs, int32_t outputs_per_thread,

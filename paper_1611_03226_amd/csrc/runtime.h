@@ -66,6 +66,7 @@ struct Persistent;  // multi-instance batching state
 struct df_graph {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t copy_in = nullptr, copy_out = nullptr;  // host transfers of df_stream_dpd (created on first use)
   bool own_stream = false;
   bool poisoned = false;
   std::string last_error;

@@ -70,6 +70,7 @@ _SIGS = {
     "df_fire": ([_P, _I32, _I64, C.c_int, C.POINTER(_I64)], _I32),
     "df_fire_many": ([_P, _I32, _P, _P, C.c_int], _I32),
     "df_fire_pipeline": ([_P, _I32, _I32, _I32, _I64, C.c_int, C.POINTER(_I64)], _I32),
+    "df_stream_dpd": ([_P, _I32, _P, _P, _P, _I64, _I64], _I32),
     "df_set_tile": ([_P, _I32, _I32, _I32], _I32),
     "df_profile_enable": ([_P, _I32], _I32),
     "df_profile_read": ([_P, C.POINTER(C.c_double), C.POINTER(_I64)], _I32),
@@ -231,6 +232,16 @@ def df_fire_pipeline(g, gauss: int, thres: int, med: int, n_firings: int, flags:
     out = C.c_int64()
     _check(_lib.df_fire_pipeline(g, gauss, thres, med, n_firings, flags, C.byref(out)), g)
     return out.value
+
+
+def df_stream_dpd(g, actor: int, x: np.ndarray, ctrl: np.ndarray, y: np.ndarray, n_batches: int,
+                  firings_per_batch: int) -> None:
+    """Host arrays in, host array out, with transfers and firings overlapped."""
+    for a in (x, ctrl, y):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("host buffers must be C-contiguous")
+    _check(_lib.df_stream_dpd(g, actor, _host_ptr(x), _host_ptr(ctrl), _host_ptr(y), n_batches,
+                              firings_per_batch), g)
 
 
 def df_set_tile(g, tile_outputs: int = 0, outputs_per_thread: int = 0, blocks_per_cu: int = 0) -> None:
