@@ -25,14 +25,18 @@ __host__ __device__ inline uint32_t funnel(uint32_t hi, uint32_t lo, int s) {
 }
 
 // Byte permute: byte i of the result is byte sel[i] (0..7) of the 8-byte
-// pool lo (bytes 0..3) : hi (bytes 4..7).
+// pool lo (bytes 0..3) : hi (bytes 4..7); a selector byte of 0x0C gives 0.
 __host__ __device__ inline uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_perm(hi, lo, sel);
 #else
   const uint64_t pool = ((uint64_t)hi << 32) | lo;
   uint32_t r = 0;
-  for (int i = 0; i < 4; ++i) r |= (uint32_t)((pool >> (8 * ((sel >> (8 * i)) & 7))) & 0xFF) << (8 * i);
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t s = (sel >> (8 * i)) & 0xFF;
+    const uint32_t v = s < 8 ? (uint32_t)((pool >> (8 * s)) & 0xFF) : s == 0x0C ? 0u : 0xFFu;
+    r |= v << (8 * i);
+  }
   return r;
 #endif
 }
@@ -55,13 +59,14 @@ __host__ __device__ inline uint32_t win1_right(bool edge) { return edge ? 0x0303
 // 0..3) and hi (bytes 4..7).  Returns the sums of (p0, p2) in *even and of
 // (p1, p3) in *odd, one per 16-bit lane (each at most 255*16 = 4080).
 __host__ __device__ inline void hsum5(uint32_t lo, uint32_t hi, uint32_t *even, uint32_t *odd) {
-  // u[k]: bytes k and k+2 of X in the two 16-bit lanes
+  // u[k]: bytes k and k+2 of X in the two 16-bit lanes, one byte permute
+  // each (selector 0x0C writes a zero byte)
   const uint32_t u0 = lo & kLo;
-  const uint32_t u1 = funnel(hi, lo, 8) & kLo;
-  const uint32_t u2 = funnel(hi, lo, 16) & kLo;
-  const uint32_t u3 = funnel(hi, lo, 24) & kLo;
+  const uint32_t u1 = perm(hi, lo, 0x0C030C01u);
+  const uint32_t u2 = perm(hi, lo, 0x0C040C02u);
+  const uint32_t u3 = perm(hi, lo, 0x0C050C03u);
   const uint32_t u4 = hi & kLo;
-  const uint32_t u5 = (hi >> 8) & kLo;
+  const uint32_t u5 = perm(hi, lo, 0x0C070C05u);
   *even = u0 + u4 + 4u * (u1 + u3) + 6u * u2;
   *odd = u1 + u5 + 4u * (u2 + u4) + 6u * u3;
 }
