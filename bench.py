@@ -566,9 +566,10 @@ def cpu_baseline(budget_s=12.0):
                 sample=f"{what}, FP64 sequential dataflow scheduler, {dt:.1f} s")
 
 
-def summarize_pmc(fetch_csv, write_csv, bench_json):
+def summarize_pmc(fetch_csv, write_csv, bench_json, sq_csv=None):
     """Traffic summary: per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the
-    actor body and of the stream copy, scaled by the copy's bytes."""
+    actor body and of the stream copy, scaled by the copy's bytes; with a
+    third run's SQ counters, the body's VALU issue share."""
     import csv
 
     def per_dispatch(path, counter):
@@ -624,6 +625,25 @@ def summarize_pmc(fetch_csv, write_csv, bench_json):
         f"- source_sha256: {b['roofline']['kernel_sources_sha256']}",
         "",
     ]
+    if sq_csv:
+        sq, durs = {}, {}
+        with open(sq_csv) as fh:
+            for row in csv.DictReader(fh):
+                if "k_dpd_tiled<16, 4, 10>" not in row["Kernel_Name"]:
+                    continue
+                d = sq.setdefault(row["Dispatch_Id"], {})
+                d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+                durs[row["Dispatch_Id"]] = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-9
+        ids = list(sq)
+        valu = sum(sq[i].get("SQ_INSTS_VALU", 0.0) for i in ids) / len(ids)
+        dur = sum(durs[i] for i in ids) / len(ids)
+        lines += [
+            "Third run (`--pmc SQ_INSTS_VALU SQ_WAVES`, same command, `-d pmc_sq -o sq`): "
+            f"{valu:.4e} VALU instructions per dispatch over {dur * 1e6:.1f} us; at 4 cycles per wave64 "
+            f"instruction on 1024 SIMDs at 2.4 GHz that is a VALU issue share of "
+            f"{valu * 4 / (1024 * 2.4e9 * dur):.3f}.",
+            "",
+        ]
     with open(TRAFFIC_FILE, "w") as fh:
         fh.write("\n".join(lines))
     print("\n".join(lines))
@@ -733,13 +753,16 @@ def main():
     ap.add_argument("--no-per-firing", action="store_true", help="skip the per-firing launch comparisons")
     ap.add_argument("--calibrate-copy", type=int, default=1024, metavar="MIB",
                     help="stream-copy reference size in MiB (bandwidth and traffic-counter reference; 0: off)")
-    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
-                    help="write the traffic summary from two rocprofv3 --pmc runs of this script (no GPU)")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV_OR_JSON",
+                    help="FETCH_CSV WRITE_CSV BENCH_JSON [SQ_CSV]: write the traffic summary from the "
+                         "rocprofv3 --pmc runs of this script (no GPU)")
     ap.add_argument("--summarize-pmc-md", nargs="+", metavar="CSV_OR_JSON",
                     help="FETCH_CSV WRITE_CSV BENCH_JSON [SQ_CSV]: same for the paper-pipeline kernels "
                          "(runs with --only md_paper)")
     args = ap.parse_args()
     if args.summarize_pmc:
+        if len(args.summarize_pmc) not in (3, 4):
+            ap.error("--summarize-pmc takes FETCH_CSV WRITE_CSV BENCH_JSON [SQ_CSV]")
         summarize_pmc(*args.summarize_pmc)
         return
     if args.summarize_pmc_md:
