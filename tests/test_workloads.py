@@ -55,3 +55,14 @@ def test_adaptation_workload():
     assert w.x.shape == (2, 1024)
     assert abs(np.sqrt(np.mean(np.abs(w.x) ** 2)) - 0.25) < 0.02
     assert w.a.shape == (4, 4) and w.a[0, 0] == 1 and w.h0[0, 0] == 1
+
+
+def test_paper_motion_frames():
+    from workloads import paper_motion
+    a, b = paper_motion(seed=4, n_frames=5), paper_motion(seed=4, n_frames=5)
+    assert a.frames.shape == (5, 240, 320) and a.frames.dtype == np.uint8
+    assert np.array_equal(a.frames, b.frames)
+    assert a.width * a.height == 76800                  # the paper's 76,800-byte tokens
+    # consecutive frames differ (noise and moving rectangles), but mostly by little
+    d = np.abs(a.frames[1].astype(int) - a.frames[0].astype(int))
+    assert 0 < np.median(d) <= 8
