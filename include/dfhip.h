@@ -46,8 +46,12 @@ enum {
   DF_ENOMEM = -3,    /* device or host allocation failed                         */
   DF_ESTATE = -4,    /* call not valid in the current wiring / state             */
   DF_EDEVICE = -5,   /* HIP runtime error; the graph is poisoned                 */
-  DF_ECONTROL = -6   /* a control token read on the device was out of range
-                        (sticky; reported by df_sync / df_fifo_status)           */
+  DF_ECONTROL = -6,  /* a control token read on the device was out of range
+                        (sticky; reported by df_sync)                            */
+  DF_EINDEX = -7     /* a channel counter update on the device broke the ring
+                        invariant read <= write <= read + capacity (the
+                        order-preserving channel of Sec. 3.2 would have lost
+                        or re-read tokens; sticky; reported by df_sync)          */
 };
 
 typedef enum { DF_C64 = 1, DF_U8 = 2, DF_I32 = 3, DF_I64 = 4 } df_dtype;
@@ -168,7 +172,12 @@ df_status df_graph_create(df_graph **g, int hip_device, void *hip_stream);
 /* Synchronise, free all FIFO storage, actor state and the owned stream. */
 df_status df_graph_destroy(df_graph *g);
 
-/* Wait for all enqueued work; report sticky device errors (DF_ECONTROL). */
+/* Wait for all enqueued work; report sticky device errors (DF_EINDEX, then
+ * DF_ECONTROL).  Every kernel that advances a channel counter (push, pop,
+ * batch commits) checks the channel's ring invariant afterwards.  With the
+ * environment variable DFHIP_CHECK_INDICES=1 at df_graph_create, every
+ * push, pop and firing call also synchronises and reports these errors
+ * itself, so the failing call is the one that returns them. */
 df_status df_sync(df_graph *g);
 
 /* Reason for the last failing call on g (static storage, never NULL). */
@@ -198,6 +207,14 @@ df_status df_fifo_create(df_graph *g, df_dtype dt, int64_t elems_per_token,
 df_status df_fifo_status(df_graph *g, int32_t fifo, int64_t *read_idx,
                          int64_t *write_idx, int64_t *capacity);
 
+/* Element type and token shape of a channel: *dtype receives its df_dtype,
+ * *elems_per_token the elements of one token and *token_bytes their bytes.
+ * Lets a binding check that a buffer handed to df_push / df_pop holds the
+ * tokens it claims.  Any output pointer may be NULL.  Host only; no device
+ * work.  Errors: DF_EINVAL (bad fifo id). */
+df_status df_fifo_info(df_graph *g, int32_t fifo, int32_t *dtype,
+                       int64_t *elems_per_token, int64_t *token_bytes);
+
 /* ------------------------------------------------------------------ actors */
 
 /* Create an actor of `kind` with a parameter struct (df_dpd_params or
@@ -215,6 +232,13 @@ df_status df_actor_create(df_graph *g, df_actor_kind kind, const void *params,
  * Errors: DF_EINVAL (bad ids, port, dtype or token size), DF_ESTATE (port or
  * channel end already connected, initial tokens on a control channel). */
 df_status df_connect(df_graph *g, int32_t actor, int32_t port, int32_t fifo);
+
+/* Fixed token rate of one port of an actor (Sec. 2.2: tokens a firing moves
+ * on that port; for the predistortion actor's branch-dependent rates the
+ * data ports move firing_size samples every firing, the control port 1).
+ * The motion actor's outputs are data-dependent: *rate receives the upper
+ * bound 1.  Host only.  Errors: DF_EINVAL (bad actor id or port). */
+df_status df_port_rate(df_graph *g, int32_t actor, int32_t port, int64_t *rate);
 
 /* ------------------------------------------------------------------ tokens */
 
@@ -322,6 +346,12 @@ df_status df_profile_read(df_graph *g, double *total_ms, int64_t *n_launches);
 df_status df_profile_read_actor(df_graph *g, int32_t actor, double *total_ms,
                                 int64_t *n_launches);
 
+/* Test hook: overwrite the device read and write counters of a channel
+ * (the host's own bookkeeping is left alone), so that a test can drive the
+ * ring invariant check of the next counter update.  Stream-ordered.
+ * Errors: DF_EINVAL (bad fifo id), DF_EDEVICE. */
+df_status df_debug_set_counters(df_graph *g, int32_t fifo, int64_t read_idx, int64_t write_idx);
+
 /* Test hook: per-firing tables of the last batch of a DPD actor (device
  * results copied to host arrays of at least cap entries per row):
  * rates [n_branches_max][n], offsets [n_branches_max][n] (token offset of
@@ -393,6 +423,17 @@ df_status df_mp_input_adjoint(void *stream, const void *u, const void *a,
  * scaled.  bytes must be a multiple of 16 and both pointers 16-byte
  * aligned (else DF_EINVAL); the buffers must not overlap and stay owned by
  * the caller, who keeps them alive until the stream has passed the copy. */
+/* Measurement helper (no operation of the method): one HBM access mix over
+ * `bytes` bytes on `stream`, for the achievable-bandwidth references.
+ * mode 0: copy src -> dst (reads and writes `bytes`, same as df_stream_copy);
+ * 1: read src only (dst receives at most 16 bytes);
+ * 2: write dst only (src unused, may be NULL);
+ * 3: dst[i] = src[i] ^ src[bytes + i] (reads 2*bytes from src, writes bytes).
+ * bytes a multiple of 16, pointers 16-byte aligned, buffers owned by the
+ * caller and alive until the stream has passed the call.
+ * Errors: DF_EINVAL. */
+df_status df_hbm_ref(void *stream, int32_t mode, const void *src, void *dst, int64_t bytes);
+
 df_status df_stream_copy(void *stream, const void *src, void *dst,
                          int64_t bytes);
 

@@ -12,6 +12,24 @@ constexpr int kMaxTaps = 32;
 // Sticky device error bits (an int32 in device memory per graph).
 enum : int32_t { kErrControl = 1, kErrIndex = 2 };
 
+// Channel counters: every channel owns one 32-byte-aligned slot of four
+// int64 words in device memory, [0] read count, [1] write count,
+// [2] capacity in tokens, [3] unused.  Kernels address the counters through
+// a pointer to word 0 or word 1 of a slot.
+constexpr int kCtrWords = 4;
+
+__device__ __forceinline__ int64_t *chan_slot(int64_t *ctr) {
+  return (int64_t *)((uintptr_t)ctr & ~(uintptr_t)(kCtrWords * sizeof(int64_t) - 1));
+}
+
+// The ring invariant of a channel after a counter update: the reader never
+// passes the writer, and the writer never runs more than a capacity ahead
+// (read <= write <= read + capacity).  A violation sets the sticky kErrIndex.
+__device__ __forceinline__ void check_chan(const int64_t *slot, int32_t *err) {
+  const int64_t occ = slot[1] - slot[0];
+  if ((occ < 0 || occ > slot[2]) && err) atomicOr(err, (int32_t)kErrIndex);
+}
+
 // ---------------------------------------------------------------- DPD
 //
 // One batch of predistortion firings.  Firing g (0 <= g < n_firings) reads
@@ -40,6 +58,7 @@ struct DpdCommitArgs {
   int64_t r;
   int32_t B_max;
   int32_t M;
+  int32_t *err;           // sticky error word (ring invariant), may be nullptr
 };
 
 struct DpdArgs {
@@ -202,7 +221,9 @@ hipError_t launch_gauss5(const MdpArgs &a, hipStream_t s, const KTiming *t = nul
 hipError_t launch_thres(const MdpArgs &a, hipStream_t s, const KTiming *t = nullptr);
 hipError_t launch_med5(const MdpArgs &a, hipStream_t s, const KTiming *t = nullptr);
 // Add delta to every counter ptr[0..n) (n <= 8) in one launch.
-hipError_t launch_advance_n(int64_t *const *ptr, int n, int64_t delta, hipStream_t s);
+hipError_t launch_advance_n(int64_t *const *ptr, int n, int64_t delta, int32_t *err, hipStream_t s);
+// Add delta[i] to counter ptr[i] (n <= 8) in one launch.
+hipError_t launch_advance_by(int64_t *const *ptr, const int64_t *delta, int n, int32_t *err, hipStream_t s);
 
 // The predistortion network with materialised branch channels (rows of
 // nf firings of r samples; tables from the offset scan, off in samples).
@@ -229,7 +250,9 @@ hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s);
 hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread,
                            const KTiming *timing = nullptr);
 hipError_t launch_dpd_commit(const DpdCommitArgs &a, hipStream_t s);
-hipError_t launch_advance(int64_t *idx, int64_t delta, hipStream_t s);
+// Add delta to one counter (word 0 or 1 of a channel slot) and check the
+// channel's ring invariant.
+hipError_t launch_advance(int64_t *idx, int64_t delta, int32_t *err, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_motion_count(const MotionArgs &a, hipStream_t s);
 hipError_t launch_motion_emit_scan(const int32_t *count, int64_t n, int64_t emit_threshold,
@@ -237,9 +260,12 @@ hipError_t launch_motion_emit_scan(const int32_t *count, int64_t n, int64_t emit
 hipError_t launch_motion_emit(const MotionArgs &a, hipStream_t s);
 hipError_t launch_adj(const AdjArgs &a, hipStream_t s);
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
+// Bandwidth reference of one access mix: 0 copy, 1 read only, 2 write only,
+// 3 two reads one write (src holds 2*bytes).
+hipError_t launch_hbm_ref(int mode, const void *src, void *dst, int64_t bytes, hipStream_t s);
 hipError_t launch_mp_adj(const float2 *u, const float2 *a, const float2 *g, float2 *Gu, int64_t n_streams,
                          int64_t len, int K, int Q, hipStream_t s);
 hipError_t launch_motion_commit(const int64_t *emit_off, int64_t n, int64_t *cur_idx, int64_t *prev_idx,
-                                int64_t *out_idx, int64_t *index_idx, hipStream_t s);
+                                int64_t *out_idx, int64_t *index_idx, int32_t *err, hipStream_t s);
 
 }  // namespace dfh

@@ -1,38 +1,97 @@
-// Plain device-to-device stream copy: the bandwidth and traffic-counter
-// reference against which the actor kernels are measured.  16-byte
-// streaming (non-temporal) loads and stores, four independent accesses per
-// thread per iteration (the streaming form measured 6% faster than cached
-// accesses).
+// HBM bandwidth references (no operation of the method): the achievable
+// bandwidth against which the actor kernels are measured, and the scale for
+// the FETCH_SIZE / WRITE_SIZE traffic counters.  Four access mixes, all with
+// 16-byte streaming (non-temporal) accesses and a persistent grid-stride
+// loop that keeps eight independent 16-byte loads per thread in flight:
+//   copy   dst[i] = src[i]                 (1 read : 1 write)
+//   read   XOR-fold of src                 (read only)
+//   write  dst[i] = pattern                (write only)
+//   2r1w   dst[i] = src[i] ^ src[i + n]    (2 reads : 1 write, the shape of
+//                                           a two-input frame actor)
+#include <algorithm>
+
 #include "common.h"
 
 namespace dfh {
 
-__global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
-                                                     int64_t n) {
-  // each workgroup copies one span of 1024 vectors (four per thread)
-  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-  if (base + 768 < n) {
-    typedef uint32_t v4 __attribute__((ext_vector_type(4)));
-    const v4 *s4 = (const v4 *)src;
-    v4 *d4 = (v4 *)dst;
-    const v4 a = __builtin_nontemporal_load(s4 + base), b = __builtin_nontemporal_load(s4 + base + 256);
-    const v4 c = __builtin_nontemporal_load(s4 + base + 512), d = __builtin_nontemporal_load(s4 + base + 768);
-    __builtin_nontemporal_store(a, d4 + base);
-    __builtin_nontemporal_store(b, d4 + base + 256);
-    __builtin_nontemporal_store(c, d4 + base + 512);
-    __builtin_nontemporal_store(d, d4 + base + 768);
-  } else {
-    for (int64_t i = base; i < n; i += 256) dst[i] = src[i];
+namespace {
+
+typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+constexpr int kRefThreads = 256;
+constexpr int kRefUnroll = 8;                        // 16-byte vectors per thread per step
+constexpr int64_t kRefStep = (int64_t)kRefThreads * kRefUnroll;
+
+__device__ __forceinline__ v4 ld(const v4 *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st(v4 *p, v4 v) { __builtin_nontemporal_store(v, p); }
+
+// mode 0 copy, 1 read, 2 write, 3 two reads one write; n = 16-byte vectors
+template <int MODE>
+__global__ __launch_bounds__(kRefThreads) void k_hbm_ref(const v4 *__restrict__ src, v4 *__restrict__ dst,
+                                                         int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kRefStep;
+  const int64_t full = n - n % kRefStep;               // whole steps: no bounds checks inside
+  v4 acc = {0u, 0u, 0u, 0u};
+  for (int64_t base = (int64_t)blockIdx.x * kRefStep + threadIdx.x; base < full; base += stride) {
+    v4 a[kRefUnroll];
+    if (MODE != 2) {
+#pragma unroll
+      for (int u = 0; u < kRefUnroll; ++u) a[u] = ld(src + base + u * kRefThreads);
+    }
+    if (MODE == 3) {
+#pragma unroll
+      for (int u = 0; u < kRefUnroll; ++u) a[u] ^= ld(src + n + base + u * kRefThreads);
+    }
+#pragma unroll
+    for (int u = 0; u < kRefUnroll; ++u) {
+      if (MODE == 1) {
+        acc ^= a[u];
+      } else if (MODE == 2) {
+        const uint32_t v = (uint32_t)(base + u * kRefThreads);
+        st(dst + base + u * kRefThreads, v4{v, v, v, v});
+      } else {
+        st(dst + base + u * kRefThreads, a[u]);
+      }
+    }
+  }
+  // the tail (fewer than one step of vectors), by the first workgroup
+  if (blockIdx.x == 0) {
+    for (int64_t i = full + threadIdx.x; i < n; i += kRefThreads) {
+      if (MODE == 1) acc ^= src[i];
+      else if (MODE == 2) dst[i] = v4{(uint32_t)i, (uint32_t)i, (uint32_t)i, (uint32_t)i};
+      else if (MODE == 3) dst[i] = src[i] ^ src[n + i];
+      else dst[i] = src[i];
+    }
+  }
+  // read mode: the fold is stored only if it equals an improbable value, so
+  // no load can be dropped and almost nothing is written
+  if (MODE == 1 && acc.x == 0x9e3779b9u && acc.y == 0x7f4a7c15u) dst[0] = acc;
+}
+
+template <int MODE>
+hipError_t launch_ref(const void *src, void *dst, int64_t n, hipStream_t s) {
+  const int64_t want = (n + kRefStep - 1) / kRefStep;
+  const int64_t resident = resident_blocks((const void *)k_hbm_ref<MODE>, kRefThreads, 0);
+  const int64_t blocks = std::max<int64_t>(1, std::min(want, 4 * resident));
+  hipLaunchKernelGGL(k_hbm_ref<MODE>, dim3((unsigned)blocks), dim3(kRefThreads), 0, s, (const v4 *)src, (v4 *)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_hbm_ref(int mode, const void *src, void *dst, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / 16;
+  if (n <= 0) return hipSuccess;
+  switch (mode) {
+    case 0: return launch_ref<0>(src, dst, n, s);
+    case 1: return launch_ref<1>(src, dst, n, s);
+    case 2: return launch_ref<2>(src, dst, n, s);
+    case 3: return launch_ref<3>(src, dst, n, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s) {
-  const int64_t n = bytes / 16;
-  if (n <= 0) return hipSuccess;
-  const int64_t blocks = (n + 1023) / 1024;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n);
-  return hipGetLastError();
+  return launch_hbm_ref(0, src, dst, bytes, s);
 }
 
 }  // namespace dfh

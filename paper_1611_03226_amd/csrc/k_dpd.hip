@@ -78,6 +78,9 @@ __device__ __forceinline__ void dpd_commit_block(const DpdCommitArgs &a) {
     a.x_idx[0] = Rx + a.n_firings * a.r;
     a.ctrl_idx[0] += a.n_firings;
     a.y_idx[1] += a.n_firings * a.r;
+    check_chan(a.x_idx, a.err);
+    check_chan(a.ctrl_idx, a.err);
+    check_chan(a.y_idx, a.err);
   }
 }
 
@@ -269,12 +272,15 @@ hipError_t launch_dpd_commit(const DpdCommitArgs &a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ small helpers
-__global__ void k_advance(int64_t *idx, int64_t delta) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) idx[0] += delta;
+__global__ void k_advance(int64_t *idx, int64_t delta, int32_t *err) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    idx[0] += delta;
+    check_chan(chan_slot(idx), err);
+  }
 }
 
-hipError_t launch_advance(int64_t *idx, int64_t delta, hipStream_t s) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, idx, delta);
+hipError_t launch_advance(int64_t *idx, int64_t delta, int32_t *err, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, idx, delta, err);
   return hipGetLastError();
 }
 

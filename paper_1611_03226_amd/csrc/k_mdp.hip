@@ -467,11 +467,14 @@ int32_t div_up32(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 
 struct Counters {
   int64_t *p[8];
+  int64_t d[8];
 };
 
-__global__ void k_advance_n(Counters c, int n, int64_t delta) {
-  if (threadIdx.x == 0 && blockIdx.x == 0)
-    for (int i = 0; i < n; ++i) *c.p[i] += delta;
+__global__ void k_advance_n(Counters c, int n, int32_t *err) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int i = 0; i < n; ++i) *c.p[i] += c.d[i];
+    for (int i = 0; i < n; ++i) check_chan(chan_slot(c.p[i]), err);
+  }
 }
 
 }  // namespace
@@ -521,12 +524,21 @@ hipError_t launch_med5(const MdpArgs &a, hipStream_t s, const KTiming *t) {
   return launch_frames(k_med5_b, kMdThreads, a, div_up32((int64_t)a.W * a.H, kMdThreads), s, t);
 }
 
-hipError_t launch_advance_n(int64_t *const *ptr, int n, int64_t delta, hipStream_t s) {
+hipError_t launch_advance_by(int64_t *const *ptr, const int64_t *delta, int n, int32_t *err, hipStream_t s) {
   if (n < 1 || n > 8) return hipErrorInvalidValue;
   Counters c{};
-  for (int i = 0; i < n; ++i) c.p[i] = ptr[i];
-  hipLaunchKernelGGL(k_advance_n, dim3(1), dim3(64), 0, s, c, n, delta);
+  for (int i = 0; i < n; ++i) {
+    c.p[i] = ptr[i];
+    c.d[i] = delta[i];
+  }
+  hipLaunchKernelGGL(k_advance_n, dim3(1), dim3(64), 0, s, c, n, err);
   return hipGetLastError();
+}
+
+hipError_t launch_advance_n(int64_t *const *ptr, int n, int64_t delta, int32_t *err, hipStream_t s) {
+  if (n < 1 || n > 8) return hipErrorInvalidValue;
+  const int64_t d[8] = {delta, delta, delta, delta, delta, delta, delta, delta};
+  return launch_advance_by(ptr, d, n, err, s);
 }
 
 bool mdp_fused_supported(int32_t W, int32_t H) { return W % 4 == 0 && W >= 4 && H >= 1; }

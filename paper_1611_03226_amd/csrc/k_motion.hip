@@ -255,13 +255,17 @@ __global__ __launch_bounds__(64) void k_emit_scan(const int32_t *count, int64_t 
 }
 
 __global__ void k_motion_commit(const int64_t *emit_off, int64_t n, int64_t *cur_idx, int64_t *prev_idx,
-                                int64_t *out_idx, int64_t *index_idx) {
+                                int64_t *out_idx, int64_t *index_idx, int32_t *err) {
   if (threadIdx.x != 0) return;
   const int64_t total = emit_off[n];
   cur_idx[0] += n;
   if (prev_idx) prev_idx[0] += n;
   out_idx[1] += total;
   index_idx[1] += total;
+  check_chan(cur_idx, err);
+  if (prev_idx) check_chan(prev_idx, err);
+  check_chan(out_idx, err);
+  check_chan(index_idx, err);
 }
 
 constexpr int MOTION_F = 4;      // frames per wavefront (self-delay form)
@@ -306,9 +310,9 @@ hipError_t launch_motion_emit(const MotionArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_motion_commit(const int64_t *emit_off, int64_t n, int64_t *cur_idx, int64_t *prev_idx,
-                                int64_t *out_idx, int64_t *index_idx, hipStream_t s) {
+                                int64_t *out_idx, int64_t *index_idx, int32_t *err, hipStream_t s) {
   hipLaunchKernelGGL(k_motion_commit, dim3(1), dim3(64), 0, s, emit_off, n, cur_idx, prev_idx, out_idx,
-                     index_idx);
+                     index_idx, err);
   return hipGetLastError();
 }
 

@@ -307,6 +307,9 @@ __global__ __launch_bounds__(256) void k_pers_commit(PersArgs a, int M) {
     d.x_idx[0] = Rx + n * d.r;
     d.ctrl_idx[0] += n;
     d.y_idx[1] += n * d.r;
+    check_chan(d.x_idx, a.err);
+    check_chan(d.ctrl_idx, a.err);
+    check_chan(d.y_idx, a.err);
   }
 }
 
@@ -415,8 +418,8 @@ using namespace dfh;
     if (e_ != hipSuccess) return fail_hip((g), e_, #expr); \
   } while (0)
 
-extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *actors, const int64_t *n_firings,
-                                  int flags) {
+static df_status fire_many(df_graph *g, int32_t n_actors, const int32_t *actors, const int64_t *n_firings,
+                           int flags) {
   if (!g) return fail(nullptr, DF_EINVAL, "null graph");
   if (g->poisoned) return fail(g, DF_EDEVICE, "graph poisoned by an earlier HIP error");
   HIPCHK(g, hipSetDevice(g->device));
@@ -620,4 +623,11 @@ extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *
     a.last_n = 0;
   }
   return DF_OK;
+}
+
+extern "C" df_status df_fire_many(df_graph *g, int32_t n_actors, const int32_t *actors, const int64_t *n_firings,
+                                  int flags) {
+  df_status st = fire_many(g, n_actors, actors, n_firings, flags);
+  if (st == DF_OK) dlog(g, 1, "df_fire_many %d actors flags 0x%x", n_actors, flags);
+  return g && !g->poisoned ? after_call(g, st) : st;
 }

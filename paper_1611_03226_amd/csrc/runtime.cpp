@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -105,13 +106,23 @@ extern "C" df_status df_graph_create(df_graph **out, int device, void *stream) {
     }
     g->own_stream = true;
   }
-  const size_t idx_bytes = sizeof(int64_t) * 2 * kMaxFifos;
+  const size_t idx_bytes = sizeof(int64_t) * kCtrWords * kMaxFifos;
   if ((e = hipMalloc(&g->idx_pool, idx_bytes)) != hipSuccess ||
       (e = hipMalloc(&g->err_dev, sizeof(int32_t) * 4)) != hipSuccess ||
       (e = hipMemset(g->idx_pool, 0, idx_bytes)) != hipSuccess ||
       (e = hipMemset(g->err_dev, 0, sizeof(int32_t) * 4)) != hipSuccess) {
     df_graph_destroy(g);
     return fail(nullptr, DF_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  if (const char *v = getenv("DFHIP_CHECK_INDICES")) g->check_indices = atoi(v) != 0;
+  if (const char *v = getenv("DFHIP_LOG")) g->log_level = atoi(v);
+  if (const char *v = getenv("DFHIP_TILE")) {
+    // "tile_outputs,outputs_per_thread,blocks_per_cu" (0 keeps a default)
+    int t = 0, k = 0, b = 0;
+    if (sscanf(v, "%d,%d,%d", &t, &k, &b) < 1 || df_set_tile(g, t, k, b) != DF_OK) {
+      df_graph_destroy(g);
+      return fail(nullptr, DF_EINVAL, "DFHIP_TILE=\"%s\" is not tile,outputs_per_thread,blocks_per_cu", v);
+    }
   }
   *out = g;
   return DF_OK;
@@ -156,11 +167,32 @@ extern "C" df_status df_graph_destroy(df_graph *g) {
   return DF_OK;
 }
 
+df_status dfh::after_call(df_graph *g, df_status st) {
+  if (st != DF_OK || !g->check_indices) return st;
+  return sync_errors(g);
+}
+
+void dfh::dlog(const df_graph *g, int level, const char *fmt, ...) {
+  if (!g || g->log_level < level) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  fprintf(stderr, "[dfhip] %s\n", buf);
+}
+
 extern "C" df_status df_sync(df_graph *g) {
   ENTER(g);
+  return sync_errors(g);
+}
+
+df_status dfh::sync_errors(df_graph *g) {
   HIPCHK(g, hipStreamSynchronize(g->stream));
   int32_t err = 0;
   HIPCHK(g, hipMemcpy(&err, g->err_dev, sizeof err, hipMemcpyDeviceToHost));
+  if (err & kErrIndex)
+    return fail(g, DF_EINDEX, "a channel counter update broke read <= write <= read + capacity on the device");
   if (err & kErrControl) return fail(g, DF_ECONTROL, "a control token outside 0..n_branches_max was read on the device");
   return DF_OK;
 }
@@ -189,7 +221,7 @@ extern "C" df_status df_fifo_create(df_graph *g, df_dtype dt, int64_t elems_per_
   f.mask = cap - 1;
   f.n_initial = n_initial;
   const int id = (int)g->fifos.size();
-  f.idx = g->idx_pool + 2 * id;
+  f.idx = g->idx_pool + kCtrWords * id;
   hipError_t e = hipMalloc(&f.ring, (size_t)(cap * f.token_bytes));
   if (e != hipSuccess) return fail(g, DF_ENOMEM, "ring allocation of %lld bytes failed",
                                    (long long)(cap * f.token_bytes));
@@ -203,7 +235,7 @@ extern "C" df_status df_fifo_create(df_graph *g, df_dtype dt, int64_t elems_per_
       return fail_hip(g, e, "initial tokens");
     }
   }
-  const int64_t init_idx[2] = {0, n_initial};
+  const int64_t init_idx[kCtrWords] = {0, n_initial, cap, 0};
   e = hipMemcpy(f.idx, init_idx, sizeof init_idx, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(f.ring);
@@ -237,6 +269,17 @@ extern "C" df_status df_fifo_status(df_graph *g, int32_t fifo, int64_t *read_idx
   if (read_idx) *read_idx = f.read_h;
   if (write_idx) *write_idx = f.write_lo;
   if (capacity) *capacity = f.cap;
+  return DF_OK;
+}
+
+extern "C" df_status df_fifo_info(df_graph *g, int32_t fifo, int32_t *dtype, int64_t *elems_per_token,
+                                  int64_t *token_bytes) {
+  if (!g) return fail(nullptr, DF_EINVAL, "null graph");
+  if (fifo < 0 || fifo >= (int)g->fifos.size()) return fail(g, DF_EINVAL, "bad fifo id %d", fifo);
+  const Fifo &f = g->fifos[fifo];
+  if (dtype) *dtype = (int32_t)f.dt;
+  if (elems_per_token) *elems_per_token = f.elems_per_token;
+  if (token_bytes) *token_bytes = f.token_bytes;
   return DF_OK;
 }
 
@@ -379,6 +422,22 @@ extern "C" df_status df_connect(df_graph *g, int32_t actor, int32_t port, int32_
   return DF_OK;
 }
 
+extern "C" df_status df_port_rate(df_graph *g, int32_t actor, int32_t port, int64_t *rate) {
+  if (!g) return fail(nullptr, DF_EINVAL, "null graph");
+  if (actor < 0 || actor >= (int)g->actors.size()) return fail(g, DF_EINVAL, "bad actor id %d", actor);
+  if (!rate) return fail(g, DF_EINVAL, "null output pointer");
+  const Actor &a = g->actors[actor];
+  PortSpec ps;
+  if (!port_spec(a, port, &ps)) return fail(g, DF_EINVAL, "actor %d has no port %d", actor, port);
+  if (a.kind == DF_ACTOR_DPD)
+    *rate = port == DF_DPD_CTRL ? 1 : a.dp.firing_size;
+  else if (a.kind == DF_ACTOR_MOTION)
+    *rate = 1;
+  else
+    *rate = a.fp.rate;
+  return DF_OK;
+}
+
 // ------------------------------------------------------------------ push / pop
 
 // Copy n tokens between a ring (starting at token position pos) and a flat
@@ -424,11 +483,11 @@ extern "C" df_status df_push(df_graph *g, int32_t fifo, const void *src, int64_t
         return fail(g, DF_EINVAL, "control token %d at %lld outside 0..%d", v[i], (long long)i, bm);
   }
   HIPCHK(g, ring_copy(g, f, f.write_hi, (void *)src, n, true, src_on_device != 0));
-  HIPCHK(g, launch_advance(f.idx + 1, n, g->stream));
+  HIPCHK(g, launch_advance(f.idx + 1, n, g->err_dev, g->stream));
   f.write_lo += n;
   f.write_hi += n;
   if (!src_on_device) HIPCHK(g, hipStreamSynchronize(g->stream));
-  return DF_OK;
+  return after_call(g, DF_OK);
 }
 
 extern "C" df_status df_pop(df_graph *g, int32_t fifo, void *dst, int64_t max_tokens, int dst_on_device,
@@ -447,12 +506,12 @@ extern "C" df_status df_pop(df_graph *g, int32_t fifo, void *dst, int64_t max_to
   if (k > 0) {
     if (!dst) return fail(g, DF_EINVAL, "null destination");
     HIPCHK(g, ring_copy(g, f, f.read_h, dst, k, false, dst_on_device != 0));
-    HIPCHK(g, launch_advance(f.idx + 0, k, g->stream));
+    HIPCHK(g, launch_advance(f.idx + 0, k, g->err_dev, g->stream));
     f.read_h += k;
     if (!dst_on_device) HIPCHK(g, hipStreamSynchronize(g->stream));
   }
   if (n_popped) *n_popped = k;
-  return DF_OK;
+  return after_call(g, DF_OK);
 }
 
 // ------------------------------------------------------------------ firing
@@ -576,6 +635,7 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   ca.r = r;
   ca.B_max = bm;
   ca.M = M;
+  ca.err = g->err_dev;
   // the tiled body's last workgroup commits the batch; the generic body
   // leaves it to a kernel of its own
   const bool fused = dpd_tiled_shape(M);
@@ -681,7 +741,7 @@ static df_status fire_motion(df_graph *g, Actor &a, int64_t n, int flags, int64_
       const int64_t last = (fc.read_h + k - 1) & fc.mask;
       HIPCHK(g, hipMemcpyAsync(a.state, fc.ring + last * wh, (size_t)wh, hipMemcpyDeviceToDevice, g->stream));
     }
-    HIPCHK(g, launch_motion_commit(a.emit_off, k, fc.idx, fp ? fp->idx : nullptr, fm.idx, fi.idx, g->stream));
+    HIPCHK(g, launch_motion_commit(a.emit_off, k, fc.idx, fp ? fp->idx : nullptr, fm.idx, fi.idx, g->err_dev, g->stream));
     fc.read_h += k;
     if (fp) fp->read_h += k;
     fm.write_hi += k;
@@ -756,7 +816,7 @@ static df_status fire_frames(df_graph *g, Actor &a, int64_t n, int flags, int64_
   for (int i = 0; i < n_in; ++i) ctr[nc++] = in[i]->idx + 0;
   for (int i = 0; i < n_out; ++i)
     if (out[i]) ctr[nc++] = out[i]->idx + 1;
-  HIPCHK(g, launch_advance_n(ctr, nc, k, g->stream));
+  HIPCHK(g, launch_advance_n(ctr, nc, k, g->err_dev, g->stream));
   for (int i = 0; i < n_in; ++i) in[i]->read_h += k;
   for (int i = 0; i < n_out; ++i)
     if (out[i]) {
@@ -768,8 +828,8 @@ static df_status fire_frames(df_graph *g, Actor &a, int64_t n, int flags, int64_
   return DF_OK;
 }
 
-extern "C" df_status df_fire_pipeline(df_graph *g, int32_t gauss, int32_t thres, int32_t med, int64_t n, int flags,
-                                      int64_t *n_fired) {
+static df_status fire_pipeline(df_graph *g, int32_t gauss, int32_t thres, int32_t med, int64_t n, int flags,
+                               int64_t *n_fired) {
   ENTER(g);
   if (n_fired) *n_fired = 0;
   const int na = (int)g->actors.size();
@@ -847,7 +907,7 @@ extern "C" df_status df_fire_pipeline(df_graph *g, int32_t gauss, int32_t thres,
   HIPCHK(g, launch_mdp_fused(fa, g->stream, g->prof ? &kt : nullptr));
   int64_t *ctr[8] = {fin.idx + 0, fcur.idx + 0, fcur.idx + 1, fdel->idx + 0, fdel->idx + 1,
                      fthr.idx + 0, fthr.idx + 1, fout.idx + 1};
-  HIPCHK(g, launch_advance_n(ctr, 8, k, g->stream));
+  HIPCHK(g, launch_advance_n(ctr, 8, k, g->err_dev, g->stream));
   fin.read_h += k;
   for (Fifo *f : {&fcur, fdel, &fthr}) {
     f->read_h += k;
@@ -863,6 +923,13 @@ extern "C" df_status df_fire_pipeline(df_graph *g, int32_t gauss, int32_t thres,
   return DF_OK;
 }
 
+extern "C" df_status df_fire_pipeline(df_graph *g, int32_t gauss, int32_t thres, int32_t med, int64_t n, int flags,
+                                      int64_t *n_fired) {
+  df_status st = fire_pipeline(g, gauss, thres, med, n, flags, n_fired);
+  if (st == DF_OK) dlog(g, 1, "df_fire_pipeline %d -> %d -> %d n %lld", gauss, thres, med, (long long)n);
+  return g && !g->poisoned ? after_call(g, st) : st;
+}
+
 extern "C" df_status df_fire(df_graph *g, int32_t actor, int64_t n, int flags, int64_t *n_fired) {
   ENTER(g);
   if (n_fired) *n_fired = 0;
@@ -870,9 +937,10 @@ extern "C" df_status df_fire(df_graph *g, int32_t actor, int64_t n, int flags, i
   if (n < 0) return fail(g, DF_EINVAL, "negative firing count");
   if (flags & ~DF_FIRE_PARTIAL) return fail(g, DF_EINVAL, "bad flags 0x%x", flags);
   Actor &a = g->actors[actor];
-  if (a.kind == DF_ACTOR_DPD) return fire_dpd(g, a, n, flags, n_fired);
-  if (a.kind == DF_ACTOR_MOTION) return fire_motion(g, a, n, flags, n_fired);
-  return fire_frames(g, a, n, flags, n_fired);
+  dlog(g, 1, "df_fire actor %d kind %d n %lld flags 0x%x", actor, (int)a.kind, (long long)n, flags);
+  if (a.kind == DF_ACTOR_DPD) return after_call(g, fire_dpd(g, a, n, flags, n_fired));
+  if (a.kind == DF_ACTOR_MOTION) return after_call(g, fire_motion(g, a, n, flags, n_fired));
+  return after_call(g, fire_frames(g, a, n, flags, n_fired));
 }
 
 // Host-to-host streaming through one predistortion actor with the three
@@ -928,6 +996,10 @@ extern "C" df_status df_stream_dpd(df_graph *g, int32_t actor, const void *x_hos
     const int64_t p = last - cap;
     return p < base ? -1 : (p - base) / n;
   };
+  // The copy streams carry copies only; every counter update runs on the
+  // graph stream, after the copy it accounts for (a kernel on a copy stream
+  // would share a hardware queue with the firings and serialise them).
+  int64_t y_drained = 0;          // batches whose output-copy has been accounted on the graph stream
   for (int64_t k = 0; k < n_batches; ++k) {
     // input: control tokens and samples of batch k
     int64_t j = std::max(reused(x_write0 + (k + 1) * ns - 1, fx.cap, x_read0, ns),
@@ -935,31 +1007,51 @@ extern "C" df_status df_stream_dpd(df_graph *g, int32_t actor, const void *x_hos
     if (j >= k) return fail(g, DF_EINVAL, "channel too small for two batches");
     if (j >= 0) HIPCHK(g, hipStreamWaitEvent(g->copy_in, ev_fired[j], 0));
     HIPCHK(g, ring_copy(g, fc, fc.write_hi, (void *)(ch + k * nb * sizeof(int32_t)), nb, true, false, g->copy_in));
-    HIPCHK(g, launch_advance(fc.idx + 1, nb, g->copy_in));
     HIPCHK(g, ring_copy(g, fx, fx.write_hi, (void *)(xh + k * ns * fx.token_bytes), ns, true, false, g->copy_in));
-    HIPCHK(g, launch_advance(fx.idx + 1, ns, g->copy_in));
     HIPCHK(g, hipEventRecord(ev_in[k], g->copy_in));
     fc.write_lo += nb;
     fc.write_hi += nb;
     fx.write_lo += ns;
     fx.write_hi += ns;
-    // firing of batch k
+    // firing of batch k, after its input copy (then the write counters move)
+    // and after the output copy that last drained the slots it writes
     HIPCHK(g, hipStreamWaitEvent(g->stream, ev_in[k], 0));
     j = reused(y0 + (k + 1) * ns - 1, fy.cap, y0, ns);
     if (j >= k) return fail(g, DF_EINVAL, "channel too small for two batches");
-    if (j >= 0) HIPCHK(g, hipStreamWaitEvent(g->stream, ev_out[j], 0));
+    int64_t *ctr[3] = {fc.idx + 1, fx.idx + 1, fy.idx + 0};
+    const int64_t delta[3] = {nb, ns, ns};
+    int nc = 2;
+    if (j >= 0) {
+      HIPCHK(g, hipStreamWaitEvent(g->stream, ev_out[j], 0));
+      if (j >= y_drained) {       // batches up to j are drained: move y's read counter
+        nc = 3;
+        ctr[2] = fy.idx + 0;
+        const int64_t d = (j + 1 - y_drained) * ns;
+        const int64_t deltas[3] = {nb, ns, d};
+        HIPCHK(g, launch_advance_by(ctr, deltas, nc, g->err_dev, g->stream));
+        y_drained = j + 1;
+      } else {
+        HIPCHK(g, launch_advance_by(ctr, delta, nc, g->err_dev, g->stream));
+      }
+    } else {
+      HIPCHK(g, launch_advance_by(ctr, delta, nc, g->err_dev, g->stream));
+    }
     st = dpd_enqueue(g, a, nb);
     if (st) return st;
     HIPCHK(g, hipEventRecord(ev_fired[k], g->stream));
     // output of batch k
     HIPCHK(g, hipStreamWaitEvent(g->copy_out, ev_fired[k], 0));
     HIPCHK(g, ring_copy(g, fy, fy.read_h, (void *)(yh + k * ns * fy.token_bytes), ns, false, false, g->copy_out));
-    HIPCHK(g, launch_advance(fy.idx + 0, ns, g->copy_out));
     HIPCHK(g, hipEventRecord(ev_out[k], g->copy_out));
     fy.read_h += ns;
   }
   HIPCHK(g, hipStreamWaitEvent(g->stream, ev_in[n_batches - 1], 0));
   HIPCHK(g, hipStreamWaitEvent(g->stream, ev_out[n_batches - 1], 0));
+  if (y_drained < n_batches) {
+    int64_t *ctr[1] = {fy.idx + 0};
+    const int64_t d[1] = {(n_batches - y_drained) * ns};
+    HIPCHK(g, launch_advance_by(ctr, d, 1, g->err_dev, g->stream));
+  }
   HIPCHK(g, hipStreamSynchronize(g->stream));
   for (int64_t k = 0; k < n_batches; ++k) {
     (void)hipEventDestroy(ev_in[k]);
@@ -967,7 +1059,7 @@ extern "C" df_status df_stream_dpd(df_graph *g, int32_t actor, const void *x_hos
     (void)hipEventDestroy(ev_out[k]);
   }
   (void)hipEventDestroy(start);
-  return DF_OK;
+  return after_call(g, DF_OK);
 }
 
 extern "C" df_status df_set_tile(df_graph *g, int32_t tile_outputs, int32_t outputs_per_thread,
@@ -982,6 +1074,16 @@ extern "C" df_status df_set_tile(df_graph *g, int32_t tile_outputs, int32_t outp
   if (outputs_per_thread) g->outputs_per_thread = outputs_per_thread;
   if (tile_outputs) g->tile = tile_outputs;
   if (blocks_per_cu) g->blocks_per_cu = blocks_per_cu;
+  return DF_OK;
+}
+
+extern "C" df_status df_debug_set_counters(df_graph *g, int32_t fifo, int64_t read_idx, int64_t write_idx) {
+  ENTER(g);
+  if (fifo < 0 || fifo >= (int)g->fifos.size()) return fail(g, DF_EINVAL, "bad fifo id %d", fifo);
+  Fifo &f = g->fifos[fifo];
+  const int64_t v[2] = {read_idx, write_idx};
+  HIPCHK(g, hipMemcpyAsync(f.idx, v, sizeof v, hipMemcpyHostToDevice, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
   return DF_OK;
 }
 

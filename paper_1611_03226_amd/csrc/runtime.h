@@ -72,12 +72,14 @@ struct df_graph {
   std::string last_error;
   std::vector<dfh::Fifo> fifos;
   std::vector<dfh::Actor> actors;
-  int64_t *idx_pool = nullptr;   // device [kMaxFifos][2]
+  int64_t *idx_pool = nullptr;   // device [kMaxFifos][kCtrWords] channel counter slots
   int32_t *err_dev = nullptr;    // sticky device error word
   int tile = 0;                  // 0 = default
   int outputs_per_thread = 4;
   int blocks_per_cu = 0;          // persistent grid; 0 = default
   dfh::Persistent *pers = nullptr;
+  bool check_indices = false;    // DFHIP_CHECK_INDICES: every token-moving call syncs and reports device errors
+  int log_level = 0;             // DFHIP_LOG: 1 = one line per firing call on stderr
   bool prof = false;                                   // record body-kernel events
   struct ProfEntry {
     hipEvent_t start, stop;
@@ -91,6 +93,13 @@ namespace dfh {
 df_status fail(df_graph *g, df_status st, const char *fmt, ...);
 df_status fail_hip(df_graph *g, hipError_t e, const char *what);
 df_status refresh_fifo(df_graph *g, Fifo &f);
+// Synchronise and turn the sticky device error word into a status.
+df_status sync_errors(df_graph *g);
+// Result of a token-moving call: with DFHIP_CHECK_INDICES set, a successful
+// call also synchronises and reports device errors.
+df_status after_call(df_graph *g, df_status st);
+// One diagnostic line on stderr when DFHIP_LOG >= level.
+void dlog(const df_graph *g, int level, const char *fmt, ...);
 df_status ensure_dpd_scratch(df_graph *g, Actor &a, int64_t n);
 df_status dpd_admit(df_graph *g, Actor &a, int64_t n, int64_t *n_adm);
 df_status dpd_enqueue(df_graph *g, Actor &a, int64_t n);

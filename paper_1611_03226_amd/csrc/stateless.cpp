@@ -251,6 +251,17 @@ extern "C" df_status df_mp_input_adjoint(void *stream, const void *u, const void
   return DF_OK;
 }
 
+extern "C" df_status df_hbm_ref(void *stream, int32_t mode, const void *src, void *dst, int64_t bytes) {
+  if (mode < 0 || mode > 3) return fail(nullptr, DF_EINVAL, "mode must be 0..3");
+  if (bytes < 0 || bytes % 16) return fail(nullptr, DF_EINVAL, "bytes must be a non-negative multiple of 16");
+  if (bytes == 0) return DF_OK;
+  if (!dst || (mode != 2 && !src)) return fail(nullptr, DF_EINVAL, "null pointer");
+  if (((uintptr_t)src | (uintptr_t)dst) % 16) return fail(nullptr, DF_EINVAL, "pointers must be 16-byte aligned");
+  hipError_t e = launch_hbm_ref(mode, src, dst, bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "df_hbm_ref");
+  return DF_OK;
+}
+
 extern "C" df_status df_stream_copy(void *stream, const void *src, void *dst, int64_t bytes) {
   if (bytes < 0 || bytes % 16) return fail(nullptr, DF_EINVAL, "bytes must be a non-negative multiple of 16");
   if (bytes == 0) return DF_OK;

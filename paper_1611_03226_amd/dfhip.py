@@ -14,9 +14,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdfhip.so")
 
-DF_OK, DF_EINVAL, DF_EAGAIN, DF_ENOMEM, DF_ESTATE, DF_EDEVICE, DF_ECONTROL = 0, -1, -2, -3, -4, -5, -6
+DF_OK, DF_EINVAL, DF_EAGAIN, DF_ENOMEM, DF_ESTATE, DF_EDEVICE, DF_ECONTROL, DF_EINDEX = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "DF_OK", -1: "DF_EINVAL", -2: "DF_EAGAIN", -3: "DF_ENOMEM", -4: "DF_ESTATE",
-                -5: "DF_EDEVICE", -6: "DF_ECONTROL"}
+                -5: "DF_EDEVICE", -6: "DF_ECONTROL", -7: "DF_EINDEX"}
 DF_C64, DF_U8, DF_I32, DF_I64 = 1, 2, 3, 4
 DF_ACTOR_DPD, DF_ACTOR_MOTION, DF_ACTOR_GAUSS5, DF_ACTOR_THRES, DF_ACTOR_MED5 = 1, 2, 3, 4, 5
 DF_DPD_CTRL, DF_DPD_IN, DF_DPD_OUT = 0, 1, 2
@@ -63,6 +63,8 @@ _SIGS = {
     "df_version": ([], C.c_char_p),
     "df_fifo_create": ([_P, C.c_int, _I64, _I64, _I64, _P, C.POINTER(_I32)], _I32),
     "df_fifo_status": ([_P, _I32, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)], _I32),
+    "df_fifo_info": ([_P, _I32, C.POINTER(_I32), C.POINTER(_I64), C.POINTER(_I64)], _I32),
+    "df_port_rate": ([_P, _I32, _I32, C.POINTER(_I64)], _I32),
     "df_actor_create": ([_P, C.c_int, _P, C.c_size_t, C.POINTER(_I32)], _I32),
     "df_connect": ([_P, _I32, _I32, _I32], _I32),
     "df_push": ([_P, _I32, _P, _I64, C.c_int], _I32),
@@ -76,12 +78,14 @@ _SIGS = {
     "df_profile_read": ([_P, C.POINTER(C.c_double), C.POINTER(_I64)], _I32),
     "df_profile_read_actor": ([_P, _I32, C.POINTER(C.c_double), C.POINTER(_I64)], _I32),
     "df_debug_last_batch": ([_P, _I32, _P, _P, _P, _I64, C.POINTER(_I64)], _I32),
+    "df_debug_set_counters": ([_P, _I32, _I64, _I64], _I32),
     "df_dpd_forward": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
     "df_dpd_forward_network": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
     "df_dpd_coeff_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32, _P, _I64], _I32),
     "df_dpd_coeff_adjoint_work_bytes": ([_I64, _I64, _I64, _I32, _I32], _I64),
     "df_mp_input_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I32, _I32], _I32),
     "df_stream_copy": ([_P, _P, _P, _I64], _I32),
+    "df_hbm_ref": ([_P, _I32, _P, _P, _I64], _I32),
     "df_paper_channel_bytes": ([_I64, _I64, _I32], _I64),
 }
 EXPORTED = tuple(_SIGS)
@@ -134,6 +138,82 @@ def _dev_ptr(t):
     if not t.is_contiguous():
         raise ValueError("device tensors must be contiguous")
     return t.data_ptr()
+
+
+_TORCH_DTYPE_NAME = {DF_C64: "complex64", DF_U8: "uint8", DF_I32: "int32", DF_I64: "int64"}
+
+
+def _tensor_dtype_ok(t, dt: int) -> bool:
+    return str(t.dtype) == "torch." + _TORCH_DTYPE_NAME[dt]
+
+
+def host_tokens(data, dt: int, elems_per_token: int, n_tokens: int | None = None):
+    """Host source buffer for n_tokens tokens of dtype dt: returns (array,
+    n).  Integer data is converted only when every value is representable,
+    complex data only to complex64; anything else raises ValueError.  n
+    defaults to the whole tokens the buffer holds, which must then be a
+    whole number."""
+    want = np.dtype(_NP_DTYPE[dt])
+    a = np.asarray(data)
+    if a.dtype != want:
+        if a.dtype.kind in "iub" and want.kind in "iu":
+            b = a.astype(want)
+            if not np.array_equal(b.astype(a.dtype), a):
+                raise ValueError(f"values do not fit the channel's {want} tokens")
+            a = b
+        elif a.dtype.kind == "c" and want.kind == "c":
+            a = a.astype(want)
+        else:
+            raise ValueError(f"buffer dtype {a.dtype} does not match the channel's {want} tokens")
+    a = np.ascontiguousarray(a)
+    if n_tokens is None:
+        if a.size % elems_per_token:
+            raise ValueError(f"buffer of {a.size} elements is not a whole number of "
+                             f"{elems_per_token}-element tokens")
+        n_tokens = a.size // elems_per_token
+    if n_tokens < 0:
+        raise ValueError("negative token count")
+    if a.size < n_tokens * elems_per_token:
+        raise ValueError(f"buffer of {a.size} elements holds fewer than {n_tokens} tokens "
+                         f"of {elems_per_token} elements")
+    return a, n_tokens
+
+
+def host_dest(dst, dt: int, elems_per_token: int, max_tokens: int | None = None) -> int:
+    """Check a host destination for up to max_tokens tokens; returns the
+    token count (default: as many whole tokens as dst holds)."""
+    want = np.dtype(_NP_DTYPE[dt])
+    if not isinstance(dst, np.ndarray):
+        raise ValueError("host destinations must be numpy arrays")
+    if dst.dtype != want:
+        raise ValueError(f"destination dtype {dst.dtype} does not match the channel's {want} tokens")
+    if not dst.flags["C_CONTIGUOUS"] or not dst.flags["WRITEABLE"]:
+        raise ValueError("host destinations must be C-contiguous and writeable")
+    room = dst.size // elems_per_token
+    if max_tokens is None:
+        return room
+    if max_tokens < 0:
+        raise ValueError("negative token count")
+    if max_tokens > room:
+        raise ValueError(f"destination of {dst.size} elements has room for {room} tokens, "
+                         f"not {max_tokens}")
+    return max_tokens
+
+
+def device_tokens(t, dt: int, elems_per_token: int, n_tokens: int | None = None) -> int:
+    """Check a device tensor for n_tokens tokens (source or destination);
+    returns the token count (default: the whole tokens it holds)."""
+    if not _tensor_dtype_ok(t, dt):
+        raise ValueError(f"tensor dtype {t.dtype} does not match the channel's "
+                         f"{_TORCH_DTYPE_NAME[dt]} tokens")
+    room = t.numel() // elems_per_token
+    if n_tokens is None:
+        return room
+    if n_tokens < 0:
+        raise ValueError("negative token count")
+    if n_tokens > room:
+        raise ValueError(f"tensor of {t.numel()} elements holds {room} tokens, not {n_tokens}")
+    return n_tokens
 
 
 # ------------------------------------------------------------------ graph
@@ -194,22 +274,41 @@ def df_connect(g, actor: int, port: int, fifo: int) -> None:
     _check(_lib.df_connect(g, actor, port, fifo), g)
 
 
+def df_fifo_info(g, fifo: int):
+    """(dtype, elems_per_token, token_bytes) of a channel."""
+    dt, e, b = C.c_int32(), C.c_int64(), C.c_int64()
+    _check(_lib.df_fifo_info(g, fifo, C.byref(dt), C.byref(e), C.byref(b)), g)
+    return dt.value, e.value, b.value
+
+
+def df_port_rate(g, actor: int, port: int) -> int:
+    out = C.c_int64()
+    _check(_lib.df_port_rate(g, actor, port, C.byref(out)), g)
+    return out.value
+
+
 def df_push(g, fifo: int, data, n_tokens: int | None = None) -> None:
-    """Push host (numpy) or device (torch) data; n_tokens defaults to len(data)."""
-    n = len(data) if n_tokens is None else n_tokens
+    """Push host (numpy) or device (torch) data; n_tokens defaults to the
+    whole tokens data holds.  dtype and size are checked against the channel."""
+    dt, ept, _ = df_fifo_info(g, fifo)
     if _is_tensor(data):
+        n = device_tokens(data, dt, ept, n_tokens)
         _check(_lib.df_push(g, fifo, _dev_ptr(data), n, 1), g)
     else:
-        _check(_lib.df_push(g, fifo, _host_ptr(np.ascontiguousarray(data)), n, 0), g)
+        a, n = host_tokens(data, dt, ept, n_tokens)
+        _check(_lib.df_push(g, fifo, _host_ptr(a), n, 0), g)
 
 
 def df_pop(g, fifo: int, dst, max_tokens: int | None = None) -> int:
-    """Pop into host (numpy) or device (torch) dst; returns tokens moved."""
-    n = len(dst) if max_tokens is None else max_tokens
+    """Pop into host (numpy) or device (torch) dst; returns tokens moved.
+    max_tokens defaults to the whole tokens dst has room for."""
+    dt, ept, _ = df_fifo_info(g, fifo)
     out = C.c_int64()
     if _is_tensor(dst):
+        n = device_tokens(dst, dt, ept, max_tokens)
         _check(_lib.df_pop(g, fifo, _dev_ptr(dst), n, 1, C.byref(out)), g)
     else:
+        n = host_dest(dst, dt, ept, max_tokens)
         _check(_lib.df_pop(g, fifo, _host_ptr(dst), n, 0, C.byref(out)), g)
     return out.value
 
@@ -237,9 +336,20 @@ def df_fire_pipeline(g, gauss: int, thres: int, med: int, n_firings: int, flags:
 def df_stream_dpd(g, actor: int, x: np.ndarray, ctrl: np.ndarray, y: np.ndarray, n_batches: int,
                   firings_per_batch: int) -> None:
     """Host arrays in, host array out, with transfers and firings overlapped."""
-    for a in (x, ctrl, y):
+    r = df_port_rate(g, actor, DF_DPD_IN)
+    nf = n_batches * firings_per_batch
+    if n_batches < 0 or firings_per_batch < 1:
+        raise ValueError("bad batch counts")
+    for name, a, want, n in (("x", x, np.complex64, nf * r), ("ctrl", ctrl, np.int32, nf),
+                             ("y", y, np.complex64, nf * r)):
+        if not isinstance(a, np.ndarray) or a.dtype != want:
+            raise ValueError(f"{name} must be a {np.dtype(want)} numpy array")
         if not a.flags["C_CONTIGUOUS"]:
             raise ValueError("host buffers must be C-contiguous")
+        if a.size < n:
+            raise ValueError(f"{name} holds {a.size} elements, {n} needed")
+    if not y.flags["WRITEABLE"]:
+        raise ValueError("y must be writeable")
     _check(_lib.df_stream_dpd(g, actor, _host_ptr(x), _host_ptr(ctrl), _host_ptr(y), n_batches,
                               firings_per_batch), g)
 
@@ -266,6 +376,11 @@ def df_profile_read_actor(g, actor: int):
     return t.value, n.value
 
 
+def df_debug_set_counters(g, fifo: int, read_idx: int, write_idx: int) -> None:
+    """Test hook: overwrite a channel's device counters (host bookkeeping unchanged)."""
+    _check(_lib.df_debug_set_counters(g, fifo, read_idx, write_idx), g)
+
+
 def df_debug_last_batch(g, actor: int, n_branches_max: int, cap: int):
     rates = np.zeros((n_branches_max, cap), np.int32)
     offs = np.zeros((n_branches_max, cap), np.int64)
@@ -279,8 +394,28 @@ def df_debug_last_batch(g, actor: int, n_branches_max: int, cap: int):
 
 # ------------------------------------------------------------------ stateless
 
+def check_dpd_tensors(x, ctrl, h, y, r: int, coeff_name: str = "h") -> None:
+    """Shapes and dtypes of the stateless predistortion calls: x, y complex64
+    [S, L] of equal shape, L a multiple of r, h complex64 [B, M], ctrl None
+    or int32 [S, L/r]."""
+    if x.dim() != 2 or tuple(y.shape) != tuple(x.shape):
+        raise ValueError(f"x and {'y' if y is not None else 'G'} must be [S, L] of equal shape")
+    for name, t in (("x", x), ("y", y)):
+        if not _tensor_dtype_ok(t, DF_C64):
+            raise ValueError(f"{name} must be complex64, got {t.dtype}")
+    if h.dim() != 2 or not _tensor_dtype_ok(h, DF_C64):
+        raise ValueError(f"{coeff_name} must be a complex64 [B, M] tensor")
+    S, L = x.shape
+    if r < 1 or L % r:
+        raise ValueError(f"L = {L} is not a multiple of r = {r}")
+    if ctrl is not None:
+        if not _tensor_dtype_ok(ctrl, DF_I32) or tuple(ctrl.shape) != (S, L // r):
+            raise ValueError(f"ctrl must be int32 of shape ({S}, {L // r})")
+
+
 def df_dpd_forward(x, ctrl, h, y, r: int, hist: int = DF_HIST_BRANCH, stream=None) -> None:
     """x, y: complex64 device tensors [S, L]; ctrl int32 [S, L/r] or None; h complex64 [B, M]."""
+    check_dpd_tensors(x, ctrl, h, y, r)
     S, L = x.shape
     B, M = h.shape
     _check(_lib.df_dpd_forward(_stream_ptr(stream), _dev_ptr(x), None if ctrl is None else _dev_ptr(ctrl),
@@ -290,6 +425,9 @@ def df_dpd_forward(x, ctrl, h, y, r: int, hist: int = DF_HIST_BRANCH, stream=Non
 def df_dpd_forward_network(x, ctrl, h, y, r: int, mask: bool = False, stream=None) -> None:
     """Same as df_dpd_forward (branch history), through materialised branch
     channels; mask=True reads the control tokens as bit masks of active branches."""
+    if ctrl is None:
+        raise ValueError("the network form needs control tokens")
+    check_dpd_tensors(x, ctrl, h, y, r)
     S, L = x.shape
     B, M = h.shape
     _check(_lib.df_dpd_forward_network(_stream_ptr(stream), _dev_ptr(x), _dev_ptr(ctrl), _dev_ptr(h), _dev_ptr(y),
@@ -301,14 +439,25 @@ def df_dpd_coeff_adjoint_work_bytes(S: int, L: int, r: int, B: int, M: int) -> i
 
 
 def df_dpd_coeff_adjoint(x, ctrl, G, grad_h, r: int, work, hist: int = DF_HIST_BRANCH, stream=None) -> None:
+    check_dpd_tensors(x, ctrl, grad_h, G, r, coeff_name="grad_h")
     S, L = x.shape
     B, M = grad_h.shape
+    need = df_dpd_coeff_adjoint_work_bytes(S, L, r, B, M)
+    if work.numel() * work.element_size() < need:
+        raise ValueError(f"work buffer holds {work.numel() * work.element_size()} bytes, {need} needed")
     _check(_lib.df_dpd_coeff_adjoint(_stream_ptr(stream), _dev_ptr(x), None if ctrl is None else _dev_ptr(ctrl),
                                      _dev_ptr(G), _dev_ptr(grad_h), S, L, r, B, M, hist, _dev_ptr(work),
                                      work.numel() * work.element_size()))
 
 
 def df_mp_input_adjoint(u, a, g, Gu, stream=None) -> None:
+    if u.dim() != 2 or tuple(g.shape) != tuple(u.shape) or tuple(Gu.shape) != tuple(u.shape):
+        raise ValueError("u, g and Gu must be [S, L] of equal shape")
+    for name, t in (("u", u), ("a", a), ("g", g), ("Gu", Gu)):
+        if not _tensor_dtype_ok(t, DF_C64):
+            raise ValueError(f"{name} must be complex64, got {t.dtype}")
+    if a.dim() != 2:
+        raise ValueError("a must be a [K, Q] tensor")
     S, L = u.shape
     K, Q = a.shape
     _check(_lib.df_mp_input_adjoint(_stream_ptr(stream), _dev_ptr(u), _dev_ptr(a), _dev_ptr(g), _dev_ptr(Gu),
@@ -318,3 +467,17 @@ def df_mp_input_adjoint(u, a, g, Gu, stream=None) -> None:
 def df_stream_copy(src, dst, nbytes: int, stream=None) -> None:
     """Plain device copy of nbytes (bandwidth / traffic-counter reference)."""
     _check(_lib.df_stream_copy(_stream_ptr(stream), _dev_ptr(src), _dev_ptr(dst), nbytes))
+
+
+HBM_REF_COPY, HBM_REF_READ, HBM_REF_WRITE, HBM_REF_2R1W = 0, 1, 2, 3
+
+
+def df_hbm_ref(mode: int, src, dst, nbytes: int, stream=None) -> None:
+    """One bandwidth-reference access mix over nbytes (see the header)."""
+    need_src = 2 * nbytes if mode == HBM_REF_2R1W else (0 if mode == HBM_REF_WRITE else nbytes)
+    need_dst = 16 if mode == HBM_REF_READ else nbytes
+    if src is not None and src.numel() * src.element_size() < need_src:
+        raise ValueError(f"src holds fewer than {need_src} bytes")
+    if dst.numel() * dst.element_size() < need_dst:
+        raise ValueError(f"dst holds fewer than {need_dst} bytes")
+    _check(_lib.df_hbm_ref(_stream_ptr(stream), mode, None if src is None else _dev_ptr(src), _dev_ptr(dst), nbytes))

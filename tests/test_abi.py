@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -102,3 +103,74 @@ def test_paper_channel_bytes_matches_eq1():
     total = sum(D.df_paper_channel_bytes(s, r, d) for s, r, d in fl.paper_motion_channels(320, 240, 4))
     assert round(total / 1e6, 2) == 3.46
     assert D.df_paper_channel_bytes(0, 4, False) == -1 and D.df_paper_channel_bytes(8, 0, True) == -1
+
+
+# ---------------------------------------------------------------- binding checks
+# The binding checks every buffer against the channel's token type before it
+# hands a pointer to the library (no device needed for these).
+
+def test_host_source_dtype_and_size_checks():
+    from paper_1611_03226_amd import dfhip as D
+    # int64 control tokens that fit are converted, not reinterpreted
+    a, n = D.host_tokens(np.array([1, 2, 3], np.int64), D.DF_I32, 1)
+    assert a.dtype == np.int32 and list(a) == [1, 2, 3] and n == 3
+    a, n = D.host_tokens([4, 5], D.DF_I32, 1)
+    assert a.dtype == np.int32 and n == 2
+    with pytest.raises(ValueError):
+        D.host_tokens(np.array([1 << 40], np.int64), D.DF_I32, 1)      # does not fit int32
+    with pytest.raises(ValueError):
+        D.host_tokens(np.zeros(8, np.float32), D.DF_C64, 1)             # float pairs are not complex64
+    with pytest.raises(ValueError):
+        D.host_tokens(np.zeros(4, np.complex64), D.DF_C64, 1, 5)        # fewer tokens than claimed
+    with pytest.raises(ValueError):
+        D.host_tokens(np.zeros(10, np.uint8), D.DF_U8, 4)               # not whole 4-byte tokens
+    a, n = D.host_tokens(np.zeros((3, 2, 2), np.uint8), D.DF_U8, 4)    # frames: tokens = frames
+    assert n == 3
+    a, n = D.host_tokens(np.zeros(4, np.complex128), D.DF_C64, 1)
+    assert a.dtype == np.complex64 and n == 4
+
+
+def test_host_destination_checks():
+    from paper_1611_03226_amd import dfhip as D
+    assert D.host_dest(np.zeros((5, 4, 4), np.uint8), D.DF_U8, 16) == 5
+    assert D.host_dest(np.zeros(80, np.uint8), D.DF_U8, 16) == 5       # flat buffer: whole frames only
+    with pytest.raises(ValueError):
+        D.host_dest(np.zeros(80, np.uint8), D.DF_U8, 16, 6)            # no room for 6 frames
+    with pytest.raises(ValueError):
+        D.host_dest(np.zeros(8, np.float32), D.DF_C64, 1)
+    with pytest.raises(ValueError):
+        D.host_dest(np.zeros(8, np.complex64)[::2], D.DF_C64, 1)       # not contiguous
+    ro = np.zeros(4, np.complex64)
+    ro.setflags(write=False)
+    with pytest.raises(ValueError):
+        D.host_dest(ro, D.DF_C64, 1)
+
+
+def test_tensor_buffer_checks():
+    import torch
+    from paper_1611_03226_amd import dfhip as D
+    assert D.device_tokens(torch.zeros(6, dtype=torch.complex64), D.DF_C64, 1) == 6
+    assert D.device_tokens(torch.zeros(6, dtype=torch.complex64), D.DF_C64, 1, 4) == 4
+    with pytest.raises(ValueError):
+        D.device_tokens(torch.zeros(12, dtype=torch.float32), D.DF_C64, 1)
+    with pytest.raises(ValueError):
+        D.device_tokens(torch.zeros(6, dtype=torch.complex64), D.DF_C64, 1, 7)
+    x = torch.zeros(2, 64, dtype=torch.complex64)
+    h = torch.zeros(3, 4, dtype=torch.complex64)
+    D.check_dpd_tensors(x, torch.zeros(2, 8, dtype=torch.int32), h, x.clone(), 8)
+    for bad in (dict(ctrl=torch.zeros(2, 8, dtype=torch.int64)),          # ctrl dtype
+                dict(ctrl=torch.zeros(2, 7, dtype=torch.int32)),          # ctrl shape
+                dict(y=torch.zeros(2, 32, dtype=torch.complex64)),        # y shape
+                dict(h=torch.zeros(3, 4, dtype=torch.float32)),           # h dtype
+                dict(r=7)):                                               # L % r
+        kw = dict(x=x, ctrl=torch.zeros(2, 8, dtype=torch.int32), h=h, y=x.clone(), r=8)
+        kw.update(bad)
+        with pytest.raises(ValueError):
+            D.check_dpd_tensors(**kw)
+
+
+def test_status_codes_match_header():
+    from paper_1611_03226_amd import dfhip as D
+    text = open(HEADER).read()
+    for name, code in (("DF_ECONTROL", D.DF_ECONTROL), ("DF_EINDEX", D.DF_EINDEX)):
+        assert re.search(rf"{name}\s*=\s*{code}\b", text), name

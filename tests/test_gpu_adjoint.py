@@ -45,6 +45,32 @@ def test_stateless_forward_matches_oracle(with_ctrl, hist):
         assert (num[den == 0] == 0).all()
 
 
+@pytest.mark.parametrize("B,M,r,with_ctrl", [(11, 16, 300, True), (13, 8, 96, True), (16, 16, 257, True),
+                                              (16, 4, 64, True), (12, 8, 512, False), (16, 16, 1024, False)])
+def test_stateless_forward_wide_branch_counts(B, M, r, with_ctrl):
+    """n_branches_max 11..16 (the 16-branch instantiations of the tiled body
+    and head pass) through the stateless call, against the oracle."""
+    import torch
+    from paper_1611_03226_amd import dfhip as D
+    say(f"stateless forward B={B} M={M} r={r} ctrl={with_ctrl}")
+    rng = np.random.default_rng(80 + B + M)
+    S, nf = 2, 7
+    L = nf * r
+    x = complex_gaussian(rng, (S, L))
+    h = dpd_coeffs(rng, B, M)
+    ctrl = rng.integers(0, B + 1, (S, nf)).astype(np.int32) if with_ctrl else None
+    y = torch.empty((S, L), dtype=torch.complex64, device="cuda")
+    D.df_dpd_forward(_t(x), None if ctrl is None else _t(ctrl), _t(h), y, r)
+    torch.cuda.synchronize()
+    ref = odpd.run_dpd_streams(x, ctrl, h, r if with_ctrl else L, "branch")
+    y = y.cpu().numpy()
+    for s in range(S):
+        num = np.linalg.norm((y[s] - ref[s]).reshape(-1, r), axis=1)
+        den = np.linalg.norm(ref[s].reshape(-1, r), axis=1)
+        assert (num[den > 0] / den[den > 0]).max() <= DPD_TOL
+        assert (num[den == 0] == 0).all()
+
+
 def test_mp_input_adjoint_matches_oracle():
     import torch
     from paper_1611_03226_amd import dfhip as D
@@ -58,9 +84,15 @@ def test_mp_input_adjoint_matches_oracle():
     D.df_mp_input_adjoint(_t(u), _t(a), _t(g), Gu)
     torch.cuda.synchronize()
     ref = opa.pa_input_vjp(u, a, g)
-    err = np.linalg.norm(Gu.cpu().numpy() - ref) / np.linalg.norm(ref)
-    print(f"mp input adjoint rel error {err:.3e}")
+    got = Gu.cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    # element by element: FP32 rounding of each output relative to its own
+    # magnitude, with an absolute floor at the RMS scale for near-zero outputs
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    elem = np.abs(got - ref) / (np.abs(ref) + 1e-3 * rms)
+    print(f"mp input adjoint rel error {err:.3e}, worst element {elem.max():.3e}")
     assert err <= 1e-5
+    assert elem.max() <= 1e-4
 
 
 @pytest.mark.parametrize("with_ctrl,hist", [(False, "branch"), (True, "branch"), (True, "shared")])
@@ -84,6 +116,32 @@ def test_coefficient_adjoint_matches_fp64_adjoint(with_ctrl, hist):
     ref = opa.dpd_coeff_vjp_streams(x, ctrl, G, B, M, r if with_ctrl else L, hist)
     rel = _rel_per_branch(g1, ref)
     print("per-branch rel error", ", ".join(f"{v:.1e}" for v in rel))
+    assert max(rel) <= 1e-4
+
+
+@pytest.mark.parametrize("B,M,r,with_ctrl", [(1, 4, 256, True), (5, 8, 512, True), (16, 16, 1024, True),
+                                              (3, 5, 300, True), (7, 13, 2100, False), (16, 32, 640, True)])
+def test_coefficient_adjoint_shapes(B, M, r, with_ctrl):
+    """Branch and tap counts away from (10, 16): one branch, B_max 16, taps
+    not a multiple of 4 (a partly used wavefront), ragged chunks; per branch
+    against the FP64 adjoint."""
+    import torch
+    from paper_1611_03226_amd import dfhip as D
+    say(f"coeff adjoint B={B} M={M} r={r} ctrl={with_ctrl}")
+    rng = np.random.default_rng(90 + B * M)
+    S, nf = 2, 5
+    L = nf * r
+    x = complex_gaussian(rng, (S, L))
+    G = complex_gaussian(rng, (S, L))
+    ctrl = rng.integers(0, B + 1, (S, nf)).astype(np.int32) if with_ctrl else None
+    if with_ctrl:
+        ctrl[0, 0] = B                            # every branch receives samples
+    grad = torch.empty((B, M), dtype=torch.complex64, device="cuda")
+    work = torch.empty(D.df_dpd_coeff_adjoint_work_bytes(S, L, r, B, M), dtype=torch.uint8, device="cuda")
+    D.df_dpd_coeff_adjoint(_t(x), None if ctrl is None else _t(ctrl), _t(G), grad, r, work)
+    ref = opa.dpd_coeff_vjp_streams(x, ctrl, G, B, M, r if with_ctrl else L, "branch")
+    rel = _rel_per_branch(grad.cpu().numpy(), ref)
+    print(f"B={B} M={M}: per-branch rel error max {max(rel):.1e}")
     assert max(rel) <= 1e-4
 
 

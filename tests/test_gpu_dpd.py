@@ -74,6 +74,14 @@ CASES = [
     (46, 40, 31, 16, 32, 0, 0, "branch", [11, 29], 0),       # B_max 16, M 32 (generic)
     (47, 33, 2048, 10, 16, 4, 0, "branch", [33], 0),         # tiles of 1024 in a firing
     (48, 9, 15, 2, 16, 0, 0, "branch", [4, 5], 128),         # r = M - 1 exactly, wrap
+    # n_branches_max 11..16: the tiled kernels' 16-branch instantiations
+    (70, 24, 300, 11, 16, 2, 0, "branch", [10, 14], 4096),   # B_max 11, M 16, ragged tile, wrap
+    (71, 20, 1100, 13, 16, 0, 1, "shared", [20], 0),         # B_max 13, M 16, ragged tail tile
+    (72, 32, 257, 16, 16, 3, 0, "branch", [5, 27], 8192),    # B_max 16, M 16, delay, wrap
+    (73, 28, 96, 16, 8, 1, 0, "branch", [28], 2048),         # B_max 16, M 8, wrap
+    (74, 36, 70, 13, 8, 0, 0, "shared", [9, 9, 18], 0),      # B_max 13, M 8
+    (75, 40, 50, 16, 4, 2, 0, "branch", [40], 1024),         # B_max 16, M 4, wrap
+    (76, 30, 33, 11, 4, 0, 1, "branch", [1] * 30, 64),       # B_max 11, M 4, per-firing
 ]
 
 
@@ -196,22 +204,16 @@ def test_scale_workload_reduced_length(G):
     assert worst <= DPD_TOL
 
 
-def test_scale_workload_full_size_sampled(G):
-    """2^24 samples in one 4096-firing batch; the oracle computes 3000 random
-    outputs and every head-of-firing output of 8 firings one by one."""
-    say("dpd scale 2^24 sampled")
+def test_scale_workload_full_size(G):
+    """2^24 samples in one 4096-firing batch, in the launch configuration the
+    benchmark times; every firing against the FP64 oracle network."""
+    say("dpd scale 2^24 full")
     w = dpd_scale()
     y, ch = run_dpd_chain(G, w, cap_x=1 << 24, cap_ctrl=4096, cap_y=1 << 24)
-    rng = np.random.default_rng(0)
-    idx = rng.integers(0, len(y), 3000)
-    heads = np.concatenate([j * w.r + np.arange(20) for j in rng.integers(0, w.n_firings, 8)])
-    idx = np.concatenate([idx, heads])
-    xs = odpd.read_stream(w.x)
-    ref = odpd.output_at(xs, w.ctrl, w.h, w.r, idx)
-    rms = np.sqrt(np.mean(np.abs(y.astype(np.complex128)) ** 2))
-    err = np.abs(y[idx] - ref) / rms
-    print(f"dpd scale 2^24: max |err|/RMS over {len(idx)} samples {err.max():.3e}")
-    assert err.max() <= DPD_TOL
+    ref = odpd.run_dpd(w.x, w.ctrl, w.h, w.r)
+    worst, glob, bad0 = rel_rms_per_firing(y, ref, w.r)
+    print(f"dpd scale 2^24: rel-RMS worst firing {worst:.3e} global {glob:.3e}")
+    assert worst <= DPD_TOL and bad0 == 0
 
 
 @pytest.mark.parametrize("hist", ["branch", "shared"])

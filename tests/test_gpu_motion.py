@@ -138,3 +138,22 @@ def test_wide_frames_span_several_column_chunks(self_delay):
         w = gen_motion(seed=13, n_frames=9, width=W, height=45, rect_min=10, rect_max=40, segment=3)
         masks, idx = run_motion_gpu(w.frames, self_delay, permille=0)
         _check(w.frames, masks, idx, permille=0)
+
+
+@pytest.mark.parametrize("threshold", [0, 100, 255])
+@pytest.mark.parametrize("self_delay", [True, False])
+def test_thresholds_match_oracle(threshold, self_delay):
+    """Other difference thresholds than 25: 0 (any change counts), 100, and
+    255 (nothing can exceed it: no frame emits)."""
+    say(f"motion threshold={threshold} self_delay={self_delay}")
+    w = gen_motion(seed=14, n_frames=12, width=320, height=97, rect_min=12, rect_max=60, segment=3)
+    frames = w.frames.copy()
+    # large steps so that a threshold of 100 still finds changed blocks
+    frames[5, 20:60, 30:90] = 255
+    frames[6, 20:60, 30:90] = 0
+    masks, idx = run_motion_gpu(frames, self_delay, threshold=threshold, permille=1)
+    _check(frames, masks, idx, threshold=threshold, permille=1)
+    if threshold == 255:
+        assert len(idx) == 0
+    else:
+        assert len(idx) > 0

@@ -6,9 +6,10 @@ tokens on the input channel."""
 import numpy as np
 import pytest
 
+from oracle import dpd as odpd
 from workloads import dpd_random
 
-from helpers import say
+from helpers import DPD_TOL, rel_rms_per_firing, say
 
 pytestmark = pytest.mark.gpu
 
@@ -64,6 +65,12 @@ def test_streamed_equals_sequential(nb, n_batches, r, B, M, d):
     a = _sequential(w, nb, n_batches, d, initial)
     b = _streamed(w, nb, n_batches, d, initial)
     assert np.array_equal(a, b)
+    # and both against the oracle network fed the same host streams
+    n = nb * n_batches
+    ref = odpd.run_dpd(w.x[:n * r], w.ctrl[:n], w.h, r, n_delay=d, initial=initial)
+    worst, glob, bad0 = rel_rms_per_firing(b, ref, r)
+    print(f"stream_dpd: rel-RMS worst firing {worst:.3e} global {glob:.3e}")
+    assert worst <= DPD_TOL and bad0 == 0
 
 
 def test_stream_rejects_small_channels():

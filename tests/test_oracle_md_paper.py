@@ -154,3 +154,17 @@ def test_eq1_capacity_reproduces_table1_motion_detection():
     b = fl.network_bytes(fl.paper_motion_channels(320, 240, 4))
     assert b == 45 * 76800
     assert round(b / 1e6, 2) == 3.46
+
+
+def test_golden_digest_file_is_consistent():
+    """The stored full-size digests start where the oracle's first block
+    ends up (the first 64 frames recomputed here from the oracle)."""
+    import hashlib
+    import os
+    from workloads import paper_motion
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "md_paper_4096_digests.txt")
+    rows = [l.split() for l in open(path) if not l.startswith("#")]
+    assert len(rows) == 64 and [int(k) for k, _ in rows] == list(range(0, 4096, 64))
+    w = paper_motion(seed=28, n_frames=4096)
+    out = md.paper_motion_direct(w.frames[:64], 20)
+    assert hashlib.sha256(out.tobytes()).hexdigest() == rows[0][1]
