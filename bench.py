@@ -31,13 +31,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PER_FIRING = True
-COPY = {"Bps": None}               # measured stream-copy bandwidth
+COPY = {"Bps": None}               # best measured HBM reference bandwidth (any access mix)
 METRIC = "DPD Msamples/s + motion frames/s at 1 GPU; % HBM roofline; batched vs per-firing"
 HBM_PEAK = 8.0e12                 # B/s, MI355X HBM3E
-# FP32 FMA issue: 256 CUs x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz.  Packed FP32
-# (two FMAs per lane per cycle, 157.3 TFLOP/s) is disabled at compile time.
+# MI355X's published FP32 vector peak (packed FP32: two FMAs per lane per
+# cycle), the roofline's peak.  Every object here is compiled with packed
+# FP32 disabled, so the issue ceiling of this code is half of it:
+# 256 CUs x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz = 78.6 TFLOP/s.
+FP32_PEAK = 157.3e12
 VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
-VALU_PEAK_PACKED = 2 * VALU_PEAK
 
 
 # HBM traffic of the dominant kernel, from two rocprofv3 counter runs
@@ -234,7 +236,8 @@ def bench_motion(D, Graph, torch, steps=3, warmup=1):
                 emit_fraction=round(emitted / n, 4),
                 hbm_frac_alg=round(bytes_alg / (body * 1e-3) / HBM_PEAK, 4),
                 achieved_GBps=round(bytes_alg / (body * 1e-3) / 1e9, 1),
-                hbm_frac_of_copy=num(bytes_alg / (body * 1e-3) / COPY["Bps"]) if COPY["Bps"] else None,
+                hbm_frac_of_best_reference=num(bytes_alg / (body * 1e-3) / COPY["Bps"]) if COPY["Bps"] else None,
+                kernels={"bits": {"algorithmic_bytes": n * wh}, "expand": {"algorithmic_bytes": emitted * (wh + 8)}},
                 per_frame_fps=num(n / (per_ms * 1e-3), 1), speedup_vs_per_frame=num(per_ms / ms, 2))
 
 
@@ -274,7 +277,7 @@ def bench_md_paper(D, Graph, torch, steps=5, warmup=2, n_frames=4096):
     def kernel_entry(t_ms, byt):
         return {"ms": round(t_ms, 4), "algorithmic_bytes": byt, "GBps": round(byt / (t_ms * 1e-3) / 1e9, 1),
                 "frac": round(byt / (t_ms * 1e-3) / HBM_PEAK, 4),
-                "frac_of_copy": num(byt / (t_ms * 1e-3) / COPY["Bps"]) if COPY["Bps"] else None}
+                "frac_of_best_reference": num(byt / (t_ms * 1e-3) / COPY["Bps"]) if COPY["Bps"] else None}
 
     ms_sep = timed(lambda: p.fire_all(G, nf))
     kern = {}
@@ -486,8 +489,10 @@ def bench_instances(D, Graph, torch, steps=2):
                 msps_per_actor=round(total / (res["many"] * 1e-3) / 1e6, 1),
                 msps_per_firing=num(total / (res["per_firing"] * 1e-3) / 1e6, 1),
                 ms=dict((k, num(v)) for k, v in res.items()),
-                persistent_valu_frac=round(flops / (body * 1e-3) / VALU_PEAK, 4),
+                persistent_fp32_frac=round(flops / (body * 1e-3) / FP32_PEAK, 4),
+                persistent_frac_of_nonpacked_issue=round(flops / (body * 1e-3) / VALU_PEAK, 4),
                 persistent_hbm_frac=round(16 * total / (body * 1e-3) / HBM_PEAK, 4),
+                algorithmic_bytes=16 * total, algorithmic_flops=flops,
                 speedup_graph_vs_per_firing=num(res["per_firing"] / res["graph"], 1))
 
 
@@ -535,16 +540,73 @@ def bench_adaptation(D, torch, steps=10, warmup=2):
     return dict(workload="adaptation 64 streams x 65536, DPD 10x16 learnable, PA orders 1..7 x 4 taps",
                 step_ms=round(step_ms, 4), loss_first=losses[0], loss_after=losses[-1],
                 coeff_adjoint_ms=round(adj_ms, 4),
-                coeff_adjoint_valu_frac=round(adj_flops / (adj_ms * 1e-3) / VALU_PEAK, 4))
+                coeff_adjoint_fp32_frac=round(adj_flops / (adj_ms * 1e-3) / FP32_PEAK, 4),
+                coeff_adjoint_frac_of_nonpacked_issue=round(adj_flops / (adj_ms * 1e-3) / VALU_PEAK, 4),
+                coeff_adjoint_algorithmic_bytes=16 * S * L, coeff_adjoint_algorithmic_flops=adj_flops)
+
+
+def hbm_reference(D, torch, nbytes, reps=10):
+    """Achievable HBM bandwidth: the four reference access mixes over nbytes
+    (bytes moved / time, HIP events on the launching stream); the best of
+    them is the ceiling the actor kernels' fractions are taken against."""
+    src = torch.ones(2 * nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    res = {"bytes": nbytes, "kernel": "k_hbm_ref<mode>"}
+    moved = {D.HBM_REF_COPY: 2 * nbytes, D.HBM_REF_READ: nbytes, D.HBM_REF_WRITE: nbytes,
+             D.HBM_REF_2R1W: 3 * nbytes}
+    names = {D.HBM_REF_COPY: "copy", D.HBM_REF_READ: "read", D.HBM_REF_WRITE: "write",
+             D.HBM_REF_2R1W: "two_reads_one_write"}
+    best = 0.0
+    for mode in (D.HBM_REF_COPY, D.HBM_REF_READ, D.HBM_REF_WRITE, D.HBM_REF_2R1W):
+        D.df_hbm_ref(mode, src, dst, nbytes, stream=st)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            D.df_hbm_ref(mode, src, dst, nbytes, stream=st)
+        ev1.record()
+        torch.cuda.synchronize()
+        bps = moved[mode] / (ev0.elapsed_time(ev1) * 1e-3 / reps)
+        res[names[mode] + "_GBps"] = round(bps / 1e9, 1)
+        best = max(best, bps)
+    COPY["Bps"] = best
+    res["best_GBps"] = round(best / 1e9, 1)
+    res["best_frac_of_peak"] = round(best / HBM_PEAK, 4)
+    del src, dst
+    return res
 
 
 def cpu_baseline(budget_s=12.0):
-    """The oracle network on the same workload, one host core: a prefix of
-    the batch sized to about budget_s, or whole batches repeated until
-    budget_s has elapsed."""
+    """The oracle network on the same workload, pinned to one host core
+    (the process's affinity is narrowed to one CPU for the timing, BLAS and
+    OpenMP threads 1): a prefix of the batch sized to about budget_s, or
+    whole batches repeated until budget_s has elapsed."""
     from oracle import dpd as odpd
     from workloads import dpd_scale
     w = dpd_scale()
+    old_aff = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    if old_aff:
+        os.sched_setaffinity(0, {min(old_aff)})
+    try:
+        return _cpu_baseline(odpd, w, budget_s, old_aff)
+    finally:
+        if old_aff:
+            os.sched_setaffinity(0, old_aff)
+
+
+def _host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _cpu_baseline(odpd, w, budget_s, old_aff):
     r = w.r
     n = 16
     t0 = time.perf_counter()
@@ -563,181 +625,157 @@ def cpu_baseline(budget_s=12.0):
     what = (f"first {n} firings ({n * r} samples) of the 2^24-sample workload" if n < w.n_firings
             else f"the whole 2^24-sample batch (4096 firings), {reps} passes")
     return dict(value=round(samples / dt / 1e6, 4), unit="Msamples/s", cores=1, kind="oracle",
-                sample=f"{what}, FP64 sequential dataflow scheduler, {dt:.1f} s")
+                sample=f"{what}, FP64 sequential dataflow scheduler, {dt:.1f} s",
+                pinned_cpu=min(old_aff) if old_aff else None, cpu_model=_host_cpu_model(),
+                host_nproc=os.cpu_count(), affinity_cpus=len(old_aff) if old_aff else None)
 
 
-def summarize_pmc(fetch_csv, write_csv, bench_json, sq_csv=None):
-    """Traffic summary: per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the
-    actor body and of the stream copy, scaled by the copy's bytes; with a
-    third run's SQ counters, the body's VALU issue share."""
+# ------------------------------------------------------------ counter summaries
+#
+# Each group: the profile file it writes, the bench legs its profiled runs
+# need, and its kernels as (label, substring of the rocprofv3 kernel name,
+# function of the bench JSON giving (algorithmic bytes, algorithmic FLOPs)
+# per launch).  Counter runs are separate rocprofv3 passes over the same
+# bench command: FETCH_SIZE, WRITE_SIZE, and the SQ pass below.
+
+SQ_PASS = "SQ_INSTS_VALU SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_INSTS_VMEM_RD SQ_INSTS_LDS"
+REF_COPY_KERNEL = "k_hbm_ref<0>"
+
+
+def _md(b, k):
+    return b["md_paper"]["kernels"][k]["algorithmic_bytes"], 0.0
+
+
+COUNTER_GROUPS = {
+    "dpd_scale": dict(
+        file="k_dpd_tiled_dpd_scale_2p24_traffic.md", only="",
+        title="k_dpd_tiled<16,4,10>, 2^24-sample workload (4096 firings of 4096, B 1..10, M 16)",
+        kernels=[("body", "k_dpd_tiled<16, 4, 10>",
+                  lambda b: (b["roofline"]["algorithmic_bytes_per_launch"],
+                             b["roofline"]["algorithmic_flops_per_launch"]))]),
+    "motion": dict(
+        file="k_motion_bits_expand_motion_300x1080p_counters.md", only="motion",
+        title="motion actor passes, 300 frames of 1920x1080 per launch (self-delay form)",
+        kernels=[("bits", "k_motion_bits<4, true>", lambda b: (b["motion"]["kernels"]["bits"]["algorithmic_bytes"], 0.0)),
+                 ("expand", "k_motion_expand<true>",
+                  lambda b: (b["motion"]["kernels"]["expand"]["algorithmic_bytes"], 0.0))]),
+    "instances": dict(
+        file="k_pers_body_instances_1024_counters.md", only="instances",
+        title="persistent body over the 1024-instance workload (26.7 M samples, r 1024, M 16)",
+        kernels=[("body", "k_pers_body<16",
+                  lambda b: (b["instances"]["algorithmic_bytes"], b["instances"]["algorithmic_flops"]))]),
+    "adaptation": dict(
+        file="k_adj_partial_adaptation_64x65536_counters.md", only="adaptation",
+        title="coefficient adjoint, 64 streams x 65536 samples, 10 branches x 16 taps",
+        kernels=[("coeff_adjoint", "k_adj_partial<10>",
+                  lambda b: (b["adaptation"]["coeff_adjoint_algorithmic_bytes"],
+                             b["adaptation"]["coeff_adjoint_algorithmic_flops"]))]),
+    "md_paper": dict(
+        file="md_paper_pipeline_traffic.md", only="md_paper",
+        title="paper motion-detection pipeline kernels, 4096 frames of 320x240 per launch",
+        kernels=[("gauss", "k_gauss5_w<4, true, true>", lambda b: _md(b, "gauss")),
+                 ("thres", "k_thres_v", lambda b: _md(b, "thres")),
+                 ("med", "k_med5_w<4, true>", lambda b: _md(b, "med")),
+                 ("fused", "k_mdp_fused<16>", lambda b: _md(b, "fused"))]),
+}
+
+
+def profile_command(group, label, counters):
+    g = COUNTER_GROUPS[group]
+    only = f"--only {g['only']} " if g["only"] else "--no-extras "
+    regex = "|".join(sorted({k[1].split("<")[0] for k in g["kernels"]} | {"k_hbm_ref"}))
+    return (f"rocprofv3 --pmc {counters} --kernel-include-regex '{regex}' -d pmc_{label} -o {label} "
+            f"--output-format csv -- python3 /root/repo/bench.py --no-cpu {only}--no-per-firing --steps 3 "
+            f"--warmup 1 > {label}.json")
+
+
+def summarize_counters(group, bench_json, *csvs):
+    """Counter summary of one kernel group from rocprofv3 --pmc CSVs (any
+    passes) and the JSON line of the same bench command: per kernel the
+    dispatches, mean duration under the profiler, HBM read and write bytes
+    per launch (FETCH_SIZE / WRITE_SIZE divided by what the same counter
+    reads per byte the copy reference moves), their ratio to the
+    algorithmic bytes, and the SQ figures (VALU issue share: a wave64 VALU
+    instruction occupies a 16-lane SIMD for 4 cycles; 1024 SIMDs at
+    2.4 GHz)."""
     import csv
-
-    def per_dispatch(path, counter):
-        vals = {}
+    g = COUNTER_GROUPS[group]
+    with open(bench_json) as fh:
+        b = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    labels = [("ref", REF_COPY_KERNEL)] + [(k[0], k[1]) for k in g["kernels"]]
+    ctr, dur = {}, {}
+    for path in csvs:
         with open(path) as fh:
             for row in csv.DictReader(fh):
-                if row["Counter_Name"] != counter:
-                    continue
                 name = row["Kernel_Name"]
-                key = "copy" if "k_stream_copy" in name else ("dpd" if "k_dpd_tiled<16, 4, 10>" in name else None)
-                if key:
-                    vals.setdefault(key, {}).setdefault(row["Dispatch_Id"], 0.0)
-                    vals[key][row["Dispatch_Id"]] += float(row["Counter_Value"])
-        return {k: (sum(v.values()) / len(v), len(v)) for k, v in vals.items()}
-
-    with open(bench_json) as fh:
-        line = [ln for ln in fh if ln.startswith("{")][-1]
-    b = json.loads(line)
-    copy_bytes = b["hbm_copy"]["bytes_read"]
-    alg = b["roofline"]["algorithmic_bytes_per_launch"]
-    f = per_dispatch(fetch_csv, "FETCH_SIZE")
-    w = per_dispatch(write_csv, "WRITE_SIZE")
-    fr = f["copy"][0] * 1024 / copy_bytes        # counter bytes per copied byte (read side)
-    fw = w["copy"][0] * 1024 / copy_bytes
-    rd = f["dpd"][0] * 1024 / fr
-    wr = w["dpd"][0] * 1024 / fw
-    lines = [
-        "# HBM traffic of k_dpd_tiled<16,4,10>, 2^24-sample workload (4096 firings of 4096, B 1..10, M 16)",
-        "",
-        "Commands (on the GPU host, from the repository root; `cd /tmp && export TMPDIR=/tmp` first):",
-        "",
-        "    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'k_dpd_tiled|k_stream_copy' -d pmc_fetch -o fetch "
-        "--output-format csv -- python3 /root/repo/bench.py --no-cpu --no-extras --no-per-firing --steps 5 "
-        "--warmup 1 > fetch.json",
-        "    rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'k_dpd_tiled|k_stream_copy' -d pmc_write -o write "
-        "--output-format csv -- python3 /root/repo/bench.py --no-cpu --no-extras --no-per-firing --steps 5 "
-        "--warmup 1 > write.json",
-        "    python3 /root/repo/bench.py --summarize-pmc pmc_fetch/fetch_counter_collection.csv "
-        "pmc_write/write_counter_collection.csv fetch.json",
-        "",
-        f"Stream copy of {copy_bytes} bytes (k_stream_copy, {f['copy'][1]} dispatches): "
-        f"FETCH_SIZE {f['copy'][0]:.1f} KiB, WRITE_SIZE {w['copy'][0]:.1f} KiB per dispatch; "
-        f"scale factors {fr:.4f} (read) and {fw:.4f} (write) counter bytes per byte moved.",
-        "",
-        f"k_dpd_tiled<16,4,10> ({f['dpd'][1]} / {w['dpd'][1]} dispatches): FETCH_SIZE {f['dpd'][0]:.1f} KiB, "
-        f"WRITE_SIZE {w['dpd'][0]:.1f} KiB per dispatch.",
-        "",
-        f"- hbm_read_bytes_per_launch: {rd:.0f}",
-        f"- hbm_write_bytes_per_launch: {wr:.0f}",
-        f"- hbm_bytes_per_launch: {rd + wr:.0f}",
-        f"- algorithmic_bytes_per_launch: {alg:.0f}",
-        f"- traffic_over_algorithmic: {(rd + wr) / alg:.4f}",
-        f"- source_sha256: {b['roofline']['kernel_sources_sha256']}",
-        "",
-    ]
-    if sq_csv:
-        sq, durs = {}, {}
-        with open(sq_csv) as fh:
-            for row in csv.DictReader(fh):
-                if "k_dpd_tiled<16, 4, 10>" not in row["Kernel_Name"]:
+                key = next((lab for lab, pat in labels if pat in name), None)
+                if key is None:
                     continue
-                d = sq.setdefault(row["Dispatch_Id"], {})
+                d = ctr.setdefault(key, {}).setdefault((path, row["Dispatch_Id"]), {})
                 d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
-                durs[row["Dispatch_Id"]] = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-9
-        ids = list(sq)
-        valu = sum(sq[i].get("SQ_INSTS_VALU", 0.0) for i in ids) / len(ids)
-        dur = sum(durs[i] for i in ids) / len(ids)
-        lines += [
-            "Third run (`--pmc SQ_INSTS_VALU SQ_WAVES`, same command, `-d pmc_sq -o sq`): "
-            f"{valu:.4e} VALU instructions per dispatch over {dur * 1e6:.1f} us; at 4 cycles per wave64 "
-            f"instruction on 1024 SIMDs at 2.4 GHz that is a VALU issue share of "
-            f"{valu * 4 / (1024 * 2.4e9 * dur):.3f}.",
-            "",
-        ]
-    with open(TRAFFIC_FILE, "w") as fh:
-        fh.write("\n".join(lines))
-    print("\n".join(lines))
+                dur.setdefault(key, {})[(path, row["Dispatch_Id"])] = \
+                    (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-9
 
+    def mean(key, counter):
+        v = [d[counter] for d in ctr.get(key, {}).values() if counter in d]
+        return (sum(v) / len(v), len(v)) if v else (None, 0)
 
-MD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "md_paper_pipeline_traffic.md")
-MD_KERNELS = (("gauss", "k_gauss5_w<4, true, true>"), ("thres", "k_thres_v"), ("med", "k_med5_w<4, true>"),
-              ("fused", "k_mdp_fused<16>"))
+    copy_bytes = b["hbm_ref"]["bytes"]
+    fr = mean("ref", "FETCH_SIZE")[0] * 1024 / copy_bytes
+    fw = mean("ref", "WRITE_SIZE")[0] * 1024 / copy_bytes
+    lines = [f"# Counters: {g['title']}", "",
+             "Commands (on the GPU host from the repository root, after `cd /tmp && export TMPDIR=/tmp`; "
+             "each pass its own run):", ""]
+    for lab, c in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"), ("sq", SQ_PASS)):
+        lines.append("    " + profile_command(group, lab, c))
+    lines += ["    python3 /root/repo/bench.py --summarize-counters " + group +
+              " fetch.json pmc_fetch/fetch_counter_collection.csv pmc_write/write_counter_collection.csv "
+              "pmc_sq/sq_counter_collection.csv", "",
+              f"Copy reference ({REF_COPY_KERNEL}, {copy_bytes} bytes read and written): FETCH_SIZE "
+              f"{mean('ref', 'FETCH_SIZE')[0]:.1f} KiB, WRITE_SIZE {mean('ref', 'WRITE_SIZE')[0]:.1f} KiB per "
+              f"dispatch; scale {fr:.4f} (read) and {fw:.4f} (write) counter bytes per byte moved.", "",
+              "| kernel | dispatches | mean us (profiler) | HBM read B | HBM write B | algorithmic B | "
+              "traffic / algorithmic | algorithmic GB/s | VALU issue share | waves | mean resident waves per CU |",
+              "|---|---|---|---|---|---|---|---|---|---|---|"]
+    kv = {}
+    for lab, pat, fn in g["kernels"]:
+        alg, flops = fn(b)
+        f, nf = mean(lab, "FETCH_SIZE")
+        w, nw = mean(lab, "WRITE_SIZE")
+        rd = f * 1024 / fr if f is not None else None
+        wr = w * 1024 / fw if w is not None else None
+        ds = list(dur.get(lab, {}).values())
+        t = sum(ds) / len(ds) if ds else None
+        valu = mean(lab, "SQ_INSTS_VALU")[0]
+        waves = mean(lab, "SQ_WAVES")[0]
+        wcyc = mean(lab, "SQ_WAVE_CYCLES")[0]
+        # SQ_WAVE_CYCLES counts resident wave-cycles in units of 4 cycles, per XCD-summed SQ
+        occ = wcyc * 4 / (t * 2.4e9 * 256) if (wcyc is not None and t) else None
+        issue = valu * 4 / (1024 * 2.4e9 * t) if (valu is not None and t) else None
 
-
-def summarize_pmc_md(fetch_csv, write_csv, bench_json, sq_csv=None):
-    """Traffic summary of the paper-pipeline kernels (Gauss, Thres, Med, fused)
-    from two rocprofv3 --pmc runs, scaled by the stream copy like
-    summarize_pmc; with a third run's SQ counters, the VALU issue use of each
-    kernel (a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles)."""
-    import csv
-
-    def per_dispatch(path, counter):
-        vals = {}
-        with open(path) as fh:
-            for row in csv.DictReader(fh):
-                if row["Counter_Name"] != counter:
-                    continue
-                name = row["Kernel_Name"]
-                key = "copy" if "k_stream_copy" in name else None
-                for k, pat in MD_KERNELS:
-                    if pat in name:
-                        key = k
-                if key:
-                    vals.setdefault(key, {}).setdefault(row["Dispatch_Id"], 0.0)
-                    vals[key][row["Dispatch_Id"]] += float(row["Counter_Value"])
-        return {k: (sum(v.values()) / len(v), len(v)) for k, v in vals.items()}
-
-    with open(bench_json) as fh:
-        line = [ln for ln in fh if ln.startswith("{")][-1]
-    b = json.loads(line)
-    copy_bytes = b["hbm_copy"]["bytes_read"]
-    f = per_dispatch(fetch_csv, "FETCH_SIZE")
-    w = per_dispatch(write_csv, "WRITE_SIZE")
-    fr = f["copy"][0] * 1024 / copy_bytes
-    fw = w["copy"][0] * 1024 / copy_bytes
-    cmd = ("rocprofv3 --pmc {c} --kernel-include-regex 'k_gauss5|k_thres|k_med5|k_mdp_fused|k_stream_copy' "
-           "-d pmc_{l} -o {l} --output-format csv -- python3 /root/repo/bench.py --no-cpu --only md_paper "
-           "--no-per-firing --steps 5 --warmup 2 > {l}.json")
-    lines = [
-        "# HBM traffic of the paper's motion-detection pipeline kernels, 4096 frames of 320x240 per launch",
-        "",
-        "Commands (on the GPU host, from the repository root; `cd /tmp && export TMPDIR=/tmp` first):",
-        "",
-        "    " + cmd.format(c="FETCH_SIZE", l="fetch"),
-        "    " + cmd.format(c="WRITE_SIZE", l="write"),
-        "    " + cmd.format(c="SQ_INSTS_VALU SQ_WAVES", l="sq"),
-        "    python3 /root/repo/bench.py --summarize-pmc-md pmc_fetch/fetch_counter_collection.csv "
-        "pmc_write/write_counter_collection.csv fetch.json pmc_sq/sq_counter_collection.csv",
-        "",
-        f"Stream copy of {copy_bytes} bytes: FETCH_SIZE {f['copy'][0]:.1f} KiB, WRITE_SIZE {w['copy'][0]:.1f} KiB "
-        f"per dispatch; scale factors {fr:.4f} (read) and {fw:.4f} (write) counter bytes per byte moved.",
-        "",
-        "| kernel | dispatches | HBM read B/launch | HBM write B/launch | algorithmic B/launch | traffic / algorithmic |",
-        "|---|---|---|---|---|---|",
-    ]
-    for k, pat in MD_KERNELS:
-        rd = f[k][0] * 1024 / fr
-        wr = w[k][0] * 1024 / fw
-        alg = b["md_paper"]["kernels"][k]["algorithmic_bytes"]
-        lines.append(f"| {pat} | {f[k][1]} / {w[k][1]} | {rd:.0f} | {wr:.0f} | {alg} | {(rd + wr) / alg:.4f} |")
+        def fmt(v, f_="{:.0f}"):
+            return "n/a" if v is None else f_.format(v)
+        lines.append(f"| {pat} | {nf} / {nw} | {fmt(t * 1e6 if t else None, '{:.1f}')} | {fmt(rd)} | {fmt(wr)} | "
+                     f"{alg:.0f} | {fmt((rd + wr) / alg if rd is not None and wr is not None else None, '{:.4f}')} | "
+                     f"{fmt(alg / t / 1e9 if t else None, '{:.1f}')} | {fmt(issue, '{:.3f}')} | {fmt(waves)} | "
+                     f"{fmt(occ, '{:.1f}')} |")
+        kv[lab] = dict(rd=rd, wr=wr, alg=alg, flops=flops, t=t, valu=valu)
     lines.append("")
-    if sq_csv:
-        sq = {}
-        durs = {}
-        with open(sq_csv) as fh:
-            for row in csv.DictReader(fh):
-                for k, pat in MD_KERNELS:
-                    if pat in row["Kernel_Name"]:
-                        d = sq.setdefault(k, {}).setdefault(row["Dispatch_Id"], {})
-                        d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
-                        durs.setdefault(k, {})[row["Dispatch_Id"]] = (int(row["End_Timestamp"]) -
-                                                                     int(row["Start_Timestamp"])) * 1e-9
-        simds = 256 * 4
-        lines += ["VALU issue (third run, `--pmc SQ_INSTS_VALU SQ_WAVES`, same bench command): "
-                  "share of the 1024 SIMDs' cycles at 2.4 GHz spent issuing VALU instructions "
-                  "(4 cycles per wave64 instruction), over the dispatch's duration under the profiler.", "",
-                  "| kernel | waves | VALU instructions | duration us | VALU issue share |", "|---|---|---|---|---|"]
-        for k, pat in MD_KERNELS:
-            if k not in sq:
-                continue
-            ids = list(sq[k])
-            valu = sum(sq[k][i].get("SQ_INSTS_VALU", 0.0) for i in ids) / len(ids)
-            waves = sum(sq[k][i].get("SQ_WAVES", 0.0) for i in ids) / len(ids)
-            dur = sum(durs[k][i] for i in ids) / len(ids)
-            lines.append(f"| {pat} | {waves:.0f} | {valu:.3e} | {dur * 1e6:.1f} | "
-                         f"{valu * 4 / (simds * 2.4e9 * dur):.3f} |")
-        lines.append("")
-    with open(MD_TRAFFIC_FILE, "w") as fh:
+    for lab, pat, _ in g["kernels"]:
+        d = kv[lab]
+        if d["rd"] is not None and d["wr"] is not None:
+            lines.append(f"- {lab}.hbm_bytes_per_launch: {d['rd'] + d['wr']:.0f}")
+        lines.append(f"- {lab}.algorithmic_bytes_per_launch: {d['alg']:.0f}")
+        if d["flops"]:
+            lines.append(f"- {lab}.algorithmic_flops_per_launch: {d['flops']:.0f}")
+    if group == "dpd_scale":
+        d = kv["body"]
+        if d["rd"] is not None and d["wr"] is not None:
+            lines.append(f"- hbm_bytes_per_launch: {d['rd'] + d['wr']:.0f}")
+        lines.append(f"- source_sha256: {b['roofline']['kernel_sources_sha256']}")
+    lines.append("")
+    out = os.path.join(ROOT, "profiles", g["file"])
+    with open(out, "w") as fh:
         fh.write("\n".join(lines))
     print("\n".join(lines))
 
@@ -753,22 +791,20 @@ def main():
     ap.add_argument("--no-per-firing", action="store_true", help="skip the per-firing launch comparisons")
     ap.add_argument("--calibrate-copy", type=int, default=1024, metavar="MIB",
                     help="stream-copy reference size in MiB (bandwidth and traffic-counter reference; 0: off)")
-    ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV_OR_JSON",
-                    help="FETCH_CSV WRITE_CSV BENCH_JSON [SQ_CSV]: write the traffic summary from the "
-                         "rocprofv3 --pmc runs of this script (no GPU)")
-    ap.add_argument("--summarize-pmc-md", nargs="+", metavar="CSV_OR_JSON",
-                    help="FETCH_CSV WRITE_CSV BENCH_JSON [SQ_CSV]: same for the paper-pipeline kernels "
-                         "(runs with --only md_paper)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="ARG",
+                    help="GROUP BENCH_JSON CSV...: write profiles/ counter summary of a kernel group "
+                         f"({', '.join(COUNTER_GROUPS)}) from rocprofv3 --pmc runs of this script (no GPU)")
+    ap.add_argument("--print-profile-commands", metavar="GROUP",
+                    help="print the rocprofv3 commands of a counter group's passes")
     args = ap.parse_args()
-    if args.summarize_pmc:
-        if len(args.summarize_pmc) not in (3, 4):
-            ap.error("--summarize-pmc takes FETCH_CSV WRITE_CSV BENCH_JSON [SQ_CSV]")
-        summarize_pmc(*args.summarize_pmc)
+    if args.summarize_counters:
+        if len(args.summarize_counters) < 3 or args.summarize_counters[0] not in COUNTER_GROUPS:
+            ap.error("--summarize-counters takes GROUP BENCH_JSON CSV...")
+        summarize_counters(*args.summarize_counters)
         return
-    if args.summarize_pmc_md:
-        if len(args.summarize_pmc_md) not in (3, 4):
-            ap.error("--summarize-pmc-md takes FETCH_CSV WRITE_CSV BENCH_JSON [SQ_CSV]")
-        summarize_pmc_md(*args.summarize_pmc_md)
+    if args.print_profile_commands:
+        for lab, c in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"), ("sq", SQ_PASS)):
+            print(profile_command(args.print_profile_commands, lab, c))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on one "
@@ -792,37 +828,23 @@ def main():
         "config": {"workload": "dpd at scale: 2^24 complex64 OFDM-like samples, 4096 firings of 4096, "
                                "control uniform 1..10 branches (odd orders to 19), 16 taps",
                    "n_samples": m["N"], "firing_size": 4096, "n_branches_max": 10, "n_taps": 16},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK / 1e12, 1),
-                     "unit": "TFLOP/s", "frac": round(achieved * 1e12 / VALU_PEAK, 4), "traffic": measured_traffic(),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(FP32_PEAK / 1e12, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved * 1e12 / FP32_PEAK, 4), "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": m["bytes"], "kernel_sources_sha256": kernel_sources_sha256(),
                      "kernel": "k_dpd_tiled<16,4,10>", "kernel_ms": round(m["body_ms"], 4),
                      "algorithmic_flops_per_launch": m["flops"],
-                     "frac_of_packed_peak": round(achieved * 1e12 / VALU_PEAK_PACKED, 4),
+                     "frac_of_nonpacked_issue": round(achieved * 1e12 / VALU_PEAK, 4),
                      "hbm_frac": round(m["bytes"] / body_s / HBM_PEAK, 4)},
         "per_firing": {"ms_per_batch": num(m["per_firing_ms"], 3),
                        "msps": num(m["N"] / (m["per_firing_ms"] * 1e-3) / 1e6, 1),
                        "batched_speedup": num(m["per_firing_ms"] / m["ms"], 1)},
         "outputs_finite": m["finite"],
-        "parity": "tests/test_gpu_dpd.py::test_scale_workload_full_size_sampled (same workload and launch shape)",
+        "parity": "tests/test_gpu_dpd.py::test_scale_workload_full_size (same workload and launch shape, "
+                  "every firing against the oracle)",
     }
     if args.calibrate_copy:
-        nbytes = args.calibrate_copy << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        D.df_stream_copy(src, dst, nbytes)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        reps = 10
-        for _ in range(reps):
-            D.df_stream_copy(src, dst, nbytes, stream=torch.cuda.current_stream())
-        ev1.record()
-        torch.cuda.synchronize()
-        copy_s = ev0.elapsed_time(ev1) * 1e-3 / reps
-        COPY["Bps"] = 2.0 * nbytes / copy_s
-        out["hbm_copy"] = {"kernel": "k_stream_copy", "bytes_read": nbytes, "bytes_written": nbytes,
-                           "GBps": round(COPY["Bps"] / 1e9, 1), "frac_of_peak": round(COPY["Bps"] / HBM_PEAK, 4)}
-        out["roofline"]["hbm_frac_of_copy"] = round(m["bytes"] / body_s / COPY["Bps"], 4)
-        del src, dst
+        out["hbm_ref"] = hbm_reference(D, torch, args.calibrate_copy << 20)
+        out["roofline"]["hbm_frac_of_best_reference"] = round(m["bytes"] / body_s / COPY["Bps"], 4)
     only = set(filter(None, args.only.split(",")))
     extras = [("chain", lambda: bench_chain(D, Graph, torch)),
               ("motion", lambda: bench_motion(D, Graph, torch)),

@@ -200,6 +200,29 @@ df_status df_fifo_create(df_graph *g, df_dtype dt, int64_t elems_per_token,
                          int64_t capacity_tokens, int64_t n_initial,
                          const void *initial_host, int32_t *fifo_out);
 
+/* Create a channel in the paper's own layout (Sec. 3.2): capacity exactly as
+ * Eq. (1), for a channel whose every write and read moves `rate` tokens.
+ * Without a delay token (n_initial = 0) it is a double buffer of 2*rate
+ * slots.  With one (n_initial = 1) it has 3*rate + 1 slots and the access
+ * pattern of Fig. 2: the delay token sits in slot 0, the writes fill slots
+ * 1..3*rate in turn, the reads take slots 0..3*rate-1 in turn, and after the
+ * write that fills slot 3*rate its token is copied to slot 0.  Token order
+ * is that of any other channel; only the placement differs.  At most
+ * 2*rate (3*rate) tokens are held at once, so a batch on such a channel
+ * admits at most two firings.  Such a channel connects only to the frame
+ * actors (Gauss, Thres, Med) and to the host; a device kernel addresses it
+ * through the same slot rule.  initial_host: the delay token's value (NULL:
+ * zeros).  Errors: DF_EINVAL (bad dtype or size, n_initial not 0 or 1,
+ * rate < 1), DF_ENOMEM. */
+df_status df_fifo_create_paper(df_graph *g, df_dtype dt, int64_t elems_per_token,
+                               int64_t rate, int64_t n_initial, const void *initial_host,
+                               int32_t *fifo_out);
+
+/* Device bytes a channel allocates for its tokens (ring: capacity tokens;
+ * paper layout: 2*rate or 3*rate + 1 tokens), or -1 for a bad id.  Host
+ * only. */
+int64_t df_fifo_bytes(df_graph *g, int32_t fifo);
+
 /* Token counts of a channel.  Synchronises when the producer's rate is
  * data-dependent (the device indices are read back).  read/write indices
  * count tokens since creation; initial tokens occupy write indices
@@ -351,6 +374,12 @@ df_status df_profile_read_actor(df_graph *g, int32_t actor, double *total_ms,
  * ring invariant check of the next counter update.  Stream-ordered.
  * Errors: DF_EINVAL (bad fifo id), DF_EDEVICE. */
 df_status df_debug_set_counters(df_graph *g, int32_t fifo, int64_t read_idx, int64_t write_idx);
+
+/* Test hook: copy a channel's whole slot storage (df_fifo_bytes bytes,
+ * slot-major) to host memory dst of max_bytes bytes, after the graph's
+ * pending work; lets a test check where tokens sit (the Fig. 2 pattern).
+ * Errors: DF_EINVAL (bad id, max_bytes too small), DF_EDEVICE. */
+df_status df_debug_read_slots(df_graph *g, int32_t fifo, void *dst, int64_t max_bytes);
 
 /* Test hook: per-firing tables of the last batch of a DPD actor (device
  * results copied to host arrays of at least cap entries per row):

@@ -22,6 +22,26 @@ __device__ __forceinline__ int64_t *chan_slot(int64_t *ctr) {
   return (int64_t *)((uintptr_t)ctr & ~(uintptr_t)(kCtrWords * sizeof(int64_t) - 1));
 }
 
+// Slot of token position p in a channel, from the channel's slot map m.
+//   m >= 0: a ring of power-of-two capacity, m = capacity - 1 (m = -1: a
+//           linear array, position = slot);
+//   m <= -2: the paper's channel layout (Sec. 3.2, Eq. (1), Fig. 2) with
+//           period P and d in {0, 1} delay tokens, m = -(2P + d + 2): P = 2r
+//           slots (a double buffer) without a delay token; with one, 3r + 1
+//           slots, P = 3r, the delay token in slot 0, writes filling slots
+//           1..P in turn and reads taking slots 0..P-1 in turn (slot P is
+//           copied to slot 0 after the write that fills it).
+__device__ __host__ __forceinline__ int64_t read_slot(int64_t p, int64_t m) {
+  if (m >= -1) return p & m;
+  return p % ((-m - 2) >> 1);
+}
+
+__device__ __host__ __forceinline__ int64_t write_slot(int64_t p, int64_t m) {
+  if (m >= -1) return p & m;
+  const int64_t v = -m - 2, P = v >> 1;
+  return (v & 1) ? 1 + (p - 1) % P : p % P;
+}
+
 // The ring invariant of a channel after a counter update: the reader never
 // passes the writer, and the writer never runs more than a capacity ahead
 // (read <= write <= read + capacity).  A violation sets the sticky kErrIndex.
@@ -174,8 +194,9 @@ struct KTiming {
 
 // One batch of a static frame actor of the motion-detection pipeline
 // (Sec. 4.1): n_frames consecutive tokens of every port.  Frame f of the
-// batch is ring slot (idx[0] + f) & mask of an input channel (its read
-// counter) and (idx[1] + f) & mask of an output channel (its write counter).
+// batch is slot read_slot(idx[0] + f, map) of an input channel (its read
+// counter) and write_slot(idx[1] + f, map) of an output channel (its write
+// counter); the *_mask fields hold each channel's slot map.
 struct MdpArgs {
   const uint8_t *in0;    // Gauss / Med input, Thres current frame
   const int64_t *in0_idx;

@@ -27,13 +27,16 @@ constexpr int kWordThreads = 64;           // word-path workgroup: one wave, lit
 constexpr int kRun = 16;                   // output rows per word-path work item
 constexpr int64_t kMaxBlocks = 1 << 23;    // per launch: threads stay below 2^31
 
-__device__ inline const uint8_t *in_frame(const uint8_t *ring, const int64_t *idx, int64_t mask, int64_t f,
+// Frame f of the batch in an input channel (from its read counter) or an
+// output channel (from its write counter); `map` is the channel's slot map
+// (a ring mask, or the paper's layout).
+__device__ inline const uint8_t *in_frame(const uint8_t *ring, const int64_t *idx, int64_t map, int64_t f,
                                           int64_t WH) {
-  return ring + ((idx[0] + f) & mask) * WH;
+  return ring + read_slot(idx[0] + f, map) * WH;
 }
 
-__device__ inline uint8_t *out_frame(uint8_t *ring, const int64_t *idx, int64_t mask, int64_t f, int64_t WH) {
-  return ring + ((idx[1] + f) & mask) * WH;
+__device__ inline uint8_t *out_frame(uint8_t *ring, const int64_t *idx, int64_t map, int64_t f, int64_t WH) {
+  return ring + write_slot(idx[1] + f, map) * WH;
 }
 
 typedef __attribute__((address_space(1))) uint32_t gu32;
@@ -420,7 +423,7 @@ __global__ __launch_bounds__(256) void k_mdp_fused(MdpFusedArgs a, int32_t waves
   // and odd pixels
   uint32_t gpE[R + 2], gpO[R + 2];
   if (f_begin == 0) {
-    const uint32_t *pg = (const uint32_t *)(a.delay + (d_read & a.delay_mask) * WH);
+    const uint32_t *pg = (const uint32_t *)(a.delay + read_slot(d_read, a.delay_mask) * WH);
 #pragma unroll
     for (int j = 0; j < R + 2; ++j) {
       const uint32_t w = pg[(uint32_t)(min(max(q.y0 - 1 + j, 0), a.H - 1) * q.Wq) + q.col];
@@ -428,15 +431,15 @@ __global__ __launch_bounds__(256) void k_mdp_fused(MdpFusedArgs a, int32_t waves
       gpO[j] = (w >> 8) & swar::kLo;
     }
   } else {
-    fused_frame<R, true>(q, (const uint32_t *)(a.in + ((in0 + f_begin - 1) & a.in_mask) * WH), nullptr, nullptr,
+    fused_frame<R, true>(q, (const uint32_t *)(a.in + read_slot(in0 + f_begin - 1, a.in_mask) * WH), nullptr, nullptr,
                          gpE, gpO);
   }
   for (int64_t f = f_begin; f < f_end; ++f) {
     // the delay channel keeps the last frame's Gauss output as its one token
-    uint32_t *dg = f == a.n_frames - 1 ? (uint32_t *)(a.delay + ((d_write + a.n_frames - 1) & a.delay_mask) * WH)
+    uint32_t *dg = f == a.n_frames - 1 ? (uint32_t *)(a.delay + write_slot(d_write + a.n_frames - 1, a.delay_mask) * WH)
                                        : nullptr;
-    fused_frame<R, false>(q, (const uint32_t *)(a.in + ((in0 + f) & a.in_mask) * WH),
-                          (uint32_t *)(a.out + ((out0 + f) & a.out_mask) * WH), dg, gpE, gpO);
+    fused_frame<R, false>(q, (const uint32_t *)(a.in + read_slot(in0 + f, a.in_mask) * WH),
+                          (uint32_t *)(a.out + write_slot(out0 + f, a.out_mask) * WH), dg, gpE, gpO);
   }
 }
 

@@ -199,33 +199,29 @@ df_status dfh::sync_errors(df_graph *g) {
 
 // ------------------------------------------------------------------ FIFOs
 
-extern "C" df_status df_fifo_create(df_graph *g, df_dtype dt, int64_t elems_per_token, int64_t capacity_tokens,
-                                    int64_t n_initial, const void *initial_host, int32_t *fifo_out) {
-  ENTER(g);
-  if (!fifo_out) return fail(g, DF_EINVAL, "df_fifo_create: null output pointer");
+// Register a channel of `cap` logical tokens (the admission capacity) over
+// `slots` allocated slots; period > 0 selects the paper's layout.
+static df_status make_fifo(df_graph *g, df_dtype dt, int64_t elems_per_token, int64_t cap, int64_t slots,
+                           int64_t period, int64_t n_initial, const void *initial_host, int32_t *fifo_out) {
   const int64_t eb = dtype_bytes(dt);
-  if (!eb) return fail(g, DF_EINVAL, "df_fifo_create: bad dtype %d", (int)dt);
-  if (elems_per_token < 1) return fail(g, DF_EINVAL, "df_fifo_create: elems_per_token must be >= 1");
-  if (n_initial < 0 || capacity_tokens < 0) return fail(g, DF_EINVAL, "df_fifo_create: negative size");
   if ((int)g->fifos.size() >= kMaxFifos) return fail(g, DF_ENOMEM, "too many FIFOs (max %d)", kMaxFifos);
-  int64_t cap = capacity_tokens ? capacity_tokens : std::max<int64_t>(2 * n_initial, 1024);
-  cap = next_pow2(cap);
-  if (n_initial > cap) return fail(g, DF_EINVAL, "df_fifo_create: n_initial %lld exceeds capacity %lld",
-                                   (long long)n_initial, (long long)cap);
   Fifo f;
   f.dt = dt;
   f.elem_bytes = eb;
   f.elems_per_token = elems_per_token;
   f.token_bytes = eb * elems_per_token;
   f.cap = cap;
-  f.mask = cap - 1;
+  f.mask = period ? 0 : cap - 1;
+  f.period = period;
+  f.slots = slots;
   f.n_initial = n_initial;
   const int id = (int)g->fifos.size();
   f.idx = g->idx_pool + kCtrWords * id;
-  hipError_t e = hipMalloc(&f.ring, (size_t)(cap * f.token_bytes));
-  if (e != hipSuccess) return fail(g, DF_ENOMEM, "ring allocation of %lld bytes failed",
-                                   (long long)(cap * f.token_bytes));
+  hipError_t e = hipMalloc(&f.ring, (size_t)(slots * f.token_bytes));
+  if (e != hipSuccess) return fail(g, DF_ENOMEM, "channel allocation of %lld bytes failed",
+                                   (long long)(slots * f.token_bytes));
   if (n_initial) {
+    // initial tokens occupy positions 0..n_initial-1 (slot 0 in the paper's layout)
     if (initial_host)
       e = hipMemcpy(f.ring, initial_host, (size_t)(n_initial * f.token_bytes), hipMemcpyHostToDevice);
     else
@@ -246,6 +242,39 @@ extern "C" df_status df_fifo_create(df_graph *g, df_dtype dt, int64_t elems_per_
   g->fifos.push_back(f);
   *fifo_out = id;
   return DF_OK;
+}
+
+extern "C" df_status df_fifo_create(df_graph *g, df_dtype dt, int64_t elems_per_token, int64_t capacity_tokens,
+                                    int64_t n_initial, const void *initial_host, int32_t *fifo_out) {
+  ENTER(g);
+  if (!fifo_out) return fail(g, DF_EINVAL, "df_fifo_create: null output pointer");
+  if (!dtype_bytes(dt)) return fail(g, DF_EINVAL, "df_fifo_create: bad dtype %d", (int)dt);
+  if (elems_per_token < 1) return fail(g, DF_EINVAL, "df_fifo_create: elems_per_token must be >= 1");
+  if (n_initial < 0 || capacity_tokens < 0) return fail(g, DF_EINVAL, "df_fifo_create: negative size");
+  int64_t cap = capacity_tokens ? capacity_tokens : std::max<int64_t>(2 * n_initial, 1024);
+  cap = next_pow2(cap);
+  if (n_initial > cap) return fail(g, DF_EINVAL, "df_fifo_create: n_initial %lld exceeds capacity %lld",
+                                   (long long)n_initial, (long long)cap);
+  return make_fifo(g, dt, elems_per_token, cap, cap, 0, n_initial, initial_host, fifo_out);
+}
+
+extern "C" df_status df_fifo_create_paper(df_graph *g, df_dtype dt, int64_t elems_per_token, int64_t rate,
+                                          int64_t n_initial, const void *initial_host, int32_t *fifo_out) {
+  ENTER(g);
+  if (!fifo_out) return fail(g, DF_EINVAL, "df_fifo_create_paper: null output pointer");
+  if (!dtype_bytes(dt)) return fail(g, DF_EINVAL, "df_fifo_create_paper: bad dtype %d", (int)dt);
+  if (elems_per_token < 1) return fail(g, DF_EINVAL, "df_fifo_create_paper: elems_per_token must be >= 1");
+  if (rate < 1) return fail(g, DF_EINVAL, "df_fifo_create_paper: rate must be >= 1");
+  if (n_initial != 0 && n_initial != 1)
+    return fail(g, DF_EINVAL, "df_fifo_create_paper: the paper's layout holds 0 or 1 delay tokens");
+  const int64_t period = n_initial ? 3 * rate : 2 * rate;
+  return make_fifo(g, dt, elems_per_token, period, period + n_initial, period, n_initial, initial_host, fifo_out);
+}
+
+extern "C" int64_t df_fifo_bytes(df_graph *g, int32_t fifo) {
+  if (!g || fifo < 0 || fifo >= (int)g->fifos.size()) return -1;
+  const Fifo &f = g->fifos[fifo];
+  return f.slots * f.token_bytes;
 }
 
 df_status dfh::refresh_fifo(df_graph *g, Fifo &f) {
@@ -401,6 +430,8 @@ extern "C" df_status df_connect(df_graph *g, int32_t actor, int32_t port, int32_
   Fifo &f = g->fifos[fifo];
   PortSpec ps;
   if (!port_spec(a, port, &ps)) return fail(g, DF_EINVAL, "actor %d has no port %d", actor, port);
+  if (f.period && !(a.kind == DF_ACTOR_GAUSS5 || a.kind == DF_ACTOR_THRES || a.kind == DF_ACTOR_MED5))
+    return fail(g, DF_EINVAL, "channels in the paper's layout connect only to Gauss, Thres and Med actors");
   const int64_t want_elems = ps.frame ? frame_elems(a) : 1;
   if (f.dt != ps.dt || f.elems_per_token != want_elems)
     return fail(g, DF_EINVAL, "fifo %d token type does not match port %d", fifo, port);
@@ -440,27 +471,41 @@ extern "C" df_status df_port_rate(df_graph *g, int32_t actor, int32_t port, int6
 
 // ------------------------------------------------------------------ push / pop
 
-// Copy n tokens between a ring (starting at token position pos) and a flat
-// buffer, on stream `st` (the graph's stream when null).
+// Copy n tokens between a channel (starting at token position pos) and a
+// flat buffer, on stream `st` (the graph's stream when null), one
+// hipMemcpyAsync per run of consecutive slots.
 static hipError_t ring_copy(df_graph *g, Fifo &f, int64_t pos, void *flat, int64_t n, bool to_ring,
                             bool flat_on_device, hipStream_t st = nullptr) {
   if (!st) st = g->stream;
-  const int64_t slot = pos & f.mask;
-  const int64_t first = std::min(n, f.cap - slot);
   const size_t tb = (size_t)f.token_bytes;
-  char *ring = f.ring;
-  char *p = (char *)flat;
+  const int64_t map = chan_map(f);
+  // exclusive end of the slots a run may cover before the pattern wraps
+  const int64_t end = !f.period ? f.cap : (to_ring && f.n_initial ? f.period + 1 : f.period);
   hipMemcpyKind kind = to_ring ? (flat_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)
                                : (flat_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
-  hipError_t e;
-  if (to_ring) {
-    e = hipMemcpyAsync(ring + slot * tb, p, first * tb, kind, st);
-    if (e == hipSuccess && n > first) e = hipMemcpyAsync(ring, p + first * tb, (n - first) * tb, kind, st);
-  } else {
-    e = hipMemcpyAsync(p, ring + slot * tb, first * tb, kind, st);
-    if (e == hipSuccess && n > first) e = hipMemcpyAsync(p + first * tb, ring, (n - first) * tb, kind, st);
+  char *p = (char *)flat;
+  for (int64_t done = 0; done < n;) {
+    const int64_t q = pos + done;
+    const int64_t slot = to_ring ? write_slot(q, map) : read_slot(q, map);
+    const int64_t run = std::min(n - done, end - slot);
+    hipError_t e = to_ring ? hipMemcpyAsync(f.ring + slot * tb, p + done * tb, run * tb, kind, st)
+                           : hipMemcpyAsync(p + done * tb, f.ring + slot * tb, run * tb, kind, st);
+    if (e != hipSuccess) return e;
+    done += run;
   }
-  return e;
+  return hipSuccess;
+}
+
+// The paper's delay-token layout: after writes of positions [pos, pos + n),
+// copy slot P to slot 0 if one of them filled slot P (Sec. 3.2, Fig. 2).
+// Admission keeps n <= P, so at most one position of the batch lands there.
+static hipError_t paper_fixup(df_graph *g, const Fifo &f, int64_t pos, int64_t n) {
+  if (!f.period || !f.n_initial || n <= 0) return hipSuccess;
+  const int64_t P = f.period;
+  const int64_t first = pos + ((P - (pos % P)) % P);   // first position >= pos that is a multiple of P
+  if (first >= pos + n || first == 0) return hipSuccess;
+  const size_t tb = (size_t)f.token_bytes;
+  return hipMemcpyAsync(f.ring, f.ring + P * tb, tb, hipMemcpyDeviceToDevice, g->stream);
 }
 
 extern "C" df_status df_push(df_graph *g, int32_t fifo, const void *src, int64_t n, int src_on_device) {
@@ -483,6 +528,7 @@ extern "C" df_status df_push(df_graph *g, int32_t fifo, const void *src, int64_t
         return fail(g, DF_EINVAL, "control token %d at %lld outside 0..%d", v[i], (long long)i, bm);
   }
   HIPCHK(g, ring_copy(g, f, f.write_hi, (void *)src, n, true, src_on_device != 0));
+  HIPCHK(g, paper_fixup(g, f, f.write_hi, n));
   HIPCHK(g, launch_advance(f.idx + 1, n, g->err_dev, g->stream));
   f.write_lo += n;
   f.write_hi += n;
@@ -784,19 +830,19 @@ static df_status fire_frames(df_graph *g, Actor &a, int64_t n, int flags, int64_
   MdpArgs ma{};
   ma.in0 = (const uint8_t *)in[0]->ring;
   ma.in0_idx = in[0]->idx;
-  ma.in0_mask = in[0]->mask;
+  ma.in0_mask = chan_map(*in[0]);
   if (in[1]) {
     ma.in1 = (const uint8_t *)in[1]->ring;
     ma.in1_idx = in[1]->idx;
-    ma.in1_mask = in[1]->mask;
+    ma.in1_mask = chan_map(*in[1]);
   }
   ma.out0 = (uint8_t *)out[0]->ring;
   ma.out0_idx = out[0]->idx;
-  ma.out0_mask = out[0]->mask;
+  ma.out0_mask = chan_map(*out[0]);
   if (out[1]) {
     ma.out1 = (uint8_t *)out[1]->ring;
     ma.out1_idx = out[1]->idx;
-    ma.out1_mask = out[1]->mask;
+    ma.out1_mask = chan_map(*out[1]);
   }
   ma.W = p.width;
   ma.H = p.height;
@@ -811,6 +857,8 @@ static df_status fire_frames(df_graph *g, Actor &a, int64_t n, int flags, int64_
     HIPCHK(g, launch_thres(ma, g->stream, tp));
   else
     HIPCHK(g, launch_med5(ma, g->stream, tp));
+  for (int i = 0; i < n_out; ++i)
+    if (out[i]) HIPCHK(g, paper_fixup(g, *out[i], out[i]->write_hi, k));
   int64_t *ctr[4];
   int nc = 0;
   for (int i = 0; i < n_in; ++i) ctr[nc++] = in[i]->idx + 0;
@@ -891,13 +939,13 @@ static df_status fire_pipeline(df_graph *g, int32_t gauss, int32_t thres, int32_
   MdpFusedArgs fa{};
   fa.in = (const uint8_t *)fin.ring;
   fa.in_idx = fin.idx;
-  fa.in_mask = fin.mask;
+  fa.in_mask = chan_map(fin);
   fa.delay = (uint8_t *)fdel->ring;
   fa.delay_idx = fdel->idx;
-  fa.delay_mask = fdel->mask;
+  fa.delay_mask = chan_map(*fdel);
   fa.out = (uint8_t *)fout.ring;
   fa.out_idx = fout.idx;
-  fa.out_mask = fout.mask;
+  fa.out_mask = chan_map(fout);
   fa.W = gp.width;
   fa.H = gp.height;
   fa.thr = tp.threshold;
@@ -905,6 +953,9 @@ static df_status fire_pipeline(df_graph *g, int32_t gauss, int32_t thres, int32_
   KTiming kt;
   HIPCHK(g, prof_pair(g, &kt, gauss));
   HIPCHK(g, launch_mdp_fused(fa, g->stream, g->prof ? &kt : nullptr));
+  // the one token the delay channel keeps is written at position write + k - 1
+  HIPCHK(g, paper_fixup(g, *fdel, fdel->write_hi + k - 1, 1));
+  HIPCHK(g, paper_fixup(g, fout, fout.write_hi, k));
   int64_t *ctr[8] = {fin.idx + 0, fcur.idx + 0, fcur.idx + 1, fdel->idx + 0, fdel->idx + 1,
                      fthr.idx + 0, fthr.idx + 1, fout.idx + 1};
   HIPCHK(g, launch_advance_n(ctr, 8, k, g->err_dev, g->stream));
@@ -1074,6 +1125,17 @@ extern "C" df_status df_set_tile(df_graph *g, int32_t tile_outputs, int32_t outp
   if (outputs_per_thread) g->outputs_per_thread = outputs_per_thread;
   if (tile_outputs) g->tile = tile_outputs;
   if (blocks_per_cu) g->blocks_per_cu = blocks_per_cu;
+  return DF_OK;
+}
+
+extern "C" df_status df_debug_read_slots(df_graph *g, int32_t fifo, void *dst, int64_t max_bytes) {
+  ENTER(g);
+  if (fifo < 0 || fifo >= (int)g->fifos.size()) return fail(g, DF_EINVAL, "bad fifo id %d", fifo);
+  const Fifo &f = g->fifos[fifo];
+  const int64_t bytes = f.slots * f.token_bytes;
+  if (!dst || max_bytes < bytes) return fail(g, DF_EINVAL, "destination holds fewer than %lld bytes", (long long)bytes);
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  HIPCHK(g, hipMemcpy(dst, f.ring, (size_t)bytes, hipMemcpyDeviceToHost));
   return DF_OK;
 }
 

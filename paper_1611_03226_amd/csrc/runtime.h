@@ -26,9 +26,18 @@ struct Fifo {
   int64_t *idx = nullptr;
   int64_t read_h = 0, write_lo = 0, write_hi = 0;
   int64_t n_initial = 0;
+  // the paper's layout (Sec. 3.2): period P (2r, or 3r with a delay token),
+  // 0 for a ring; `slots` tokens are allocated (cap, or P + 1 with a delay)
+  int64_t period = 0;
+  int64_t slots = 0;
   int writer = -1, writer_port = -1;  // -1: the host
   int reader = -1, reader_port = -1;
 };
+
+// Slot map of a channel as the kernels take it (see read_slot / write_slot).
+inline int64_t chan_map(const Fifo &f) {
+  return f.period ? -(2 * f.period + (f.n_initial ? 1 : 0) + 2) : f.mask;
+}
 
 struct Actor {
   df_actor_kind kind = DF_ACTOR_DPD;
@@ -104,6 +113,27 @@ df_status ensure_dpd_scratch(df_graph *g, Actor &a, int64_t n);
 df_status dpd_admit(df_graph *g, Actor &a, int64_t n, int64_t *n_adm);
 df_status dpd_enqueue(df_graph *g, Actor &a, int64_t n);
 void destroy_persistent(df_graph *g);
+
+// Scratch of one stateless predistortion forward call: validated branch
+// counts B [n], history sources prev [B_max][n], scan group table grp, head
+// corrections corr [n][M-1] (n = S*len/r firings; without control tokens only
+// corr, [S][M-1]).  Nothing in it needs to start at zero.
+struct FwdScratch {
+  int32_t *B = nullptr;
+  int64_t *prev = nullptr;
+  int64_t *grp = nullptr;
+  float2 *corr = nullptr;
+};
+struct FwdScratchSize {
+  size_t B = 0, prev = 0, grp = 0, corr = 0;
+};
+FwdScratchSize dpd_forward_scratch_size(int64_t S, int64_t len, int64_t r, int32_t B_max, int32_t M,
+                                        bool with_ctrl);
+hipError_t dpd_forward_enqueue(const FwdScratch &sc, hipStream_t s, const void *x, const int32_t *ctrl,
+                               const void *h, void *y, int64_t S, int64_t len, int64_t r, int32_t B_max, int32_t M,
+                               int32_t hist);
+df_status check_dpd_forward_args(const void *x, const void *h, void *y, int64_t S, int64_t len, int64_t r,
+                                 int32_t B_max, int32_t M, int32_t hist, bool *nothing);
 // Event pair around body kernels when profiling is enabled (no-op otherwise).
 hipError_t prof_begin(df_graph *g, int actor = -1);
 // events for one timed launch of `actor` (none if profiling is off)

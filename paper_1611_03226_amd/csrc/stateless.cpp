@@ -75,13 +75,28 @@ int adj_chunk(int64_t r) { return (int)std::min<int64_t>(2048, r); }
 
 }  // namespace
 
-extern "C" df_status df_dpd_forward(void *stream, const void *x, const int32_t *ctrl, const void *h, void *y,
-                                    int64_t S, int64_t len, int64_t r, int32_t B_max, int32_t M, int32_t hist) {
-  df_status st = check_dpd_shape(S, len, r, B_max, M, hist);
-  if (st) return st;
-  if (S == 0 || len == 0) return DF_OK;
-  if (!x || !h || !y) return fail(nullptr, DF_EINVAL, "null pointer");
-  hipStream_t s = (hipStream_t)stream;
+// Bytes of each scratch region one forward call needs (see FwdScratch).
+FwdScratchSize dfh::dpd_forward_scratch_size(int64_t S, int64_t len, int64_t r, int32_t B_max, int32_t M,
+                                             bool with_ctrl) {
+  FwdScratchSize z{};
+  const int64_t L1 = std::max(M - 1, 1);
+  if (!with_ctrl) {
+    z.corr = sizeof(float2) * L1 * S;
+    return z;
+  }
+  const int64_t nf = len / r, n = std::max<int64_t>(S * nf, 1);
+  z.B = sizeof(int32_t) * n;
+  z.prev = sizeof(int64_t) * n * B_max;
+  z.grp = 2 * sizeof(int64_t) * B_max * std::max<int64_t>(scan_groups(S, nf), 1);
+  z.corr = sizeof(float2) * L1 * n;
+  return z;
+}
+
+// The forward kernel chain over caller-provided scratch: control intake and
+// offset scan (with control tokens), head corrections, tiled body.
+hipError_t dfh::dpd_forward_enqueue(const FwdScratch &sc, hipStream_t s, const void *x, const int32_t *ctrl,
+                                    const void *h, void *y, int64_t S, int64_t len, int64_t r, int32_t B_max,
+                                    int32_t M, int32_t hist) {
   DpdArgs a{};
   a.x = (const float2 *)x;
   a.x_mask = -1;
@@ -90,39 +105,69 @@ extern "C" df_status df_dpd_forward(void *stream, const void *x, const int32_t *
   a.h = (const float2 *)h;
   a.B_max = B_max;
   a.M = M;
-  Tables t;
-  hipError_t e;
-  float2 *corr = nullptr;
+  a.corr = sc.corr;
   if (!ctrl) {
     // All branches active in every firing: a row is one convolution.
     a.B_const = B_max;
     a.seg_firings = 1;
     a.n_firings = S;
     a.r = len;
-    e = hipMallocAsync((void **)&corr, sizeof(float2) * std::max(M - 1, 1) * S, s);
-    if (e == hipSuccess) {
-      a.corr = corr;
-      e = launch_dpd_heads(a, s);
-    }
+    hipError_t e = launch_dpd_heads(a, s);
     if (e == hipSuccess) e = launch_dpd_body(a, s, 0, 4);
-  } else {
-    const int64_t nf = len / r;
-    e = make_tables(ctrl, S, nf, r, B_max, hist, s, &t);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&corr, sizeof(float2) * std::max(M - 1, 1) * S * nf, s);
-    if (e == hipSuccess) {
-      a.B = t.B;
-      a.prev = t.prev;
-      a.prev_stride = t.n;
-      a.seg_firings = nf;
-      a.n_firings = S * nf;
-      a.r = r;
-      a.corr = corr;
-      e = launch_dpd_heads(a, s);
-      if (e == hipSuccess) e = launch_dpd_body(a, s, 0, 4);
-    }
-    free_tables(&t, s);
+    return e;
   }
-  if (corr) (void)hipFreeAsync(corr, s);
+  const int64_t nf = len / r, n = S * nf;
+  ScanArgs sa{};
+  sa.ctrl = ctrl;
+  sa.ctrl_idx = nullptr;
+  sa.ctrl_mask = -1;
+  sa.seg_firings = nf;
+  sa.n_segs = (int32_t)S;
+  sa.B_max = B_max;
+  sa.hist_mode = hist;
+  sa.B_out = sc.B;
+  sa.prev_out = sc.prev;
+  sa.off_out = nullptr;
+  sa.grp = sc.grp;
+  sa.stride = n;
+  sa.r = r;
+  hipError_t e = launch_scan(sa, s);
+  if (e != hipSuccess) return e;
+  a.B = sc.B;
+  a.prev = sc.prev;
+  a.prev_stride = n;
+  a.seg_firings = nf;
+  a.n_firings = n;
+  a.r = r;
+  e = launch_dpd_heads(a, s);
+  if (e == hipSuccess) e = launch_dpd_body(a, s, 0, 4);
+  return e;
+}
+
+df_status dfh::check_dpd_forward_args(const void *x, const void *h, void *y, int64_t S, int64_t len, int64_t r,
+                                      int32_t B_max, int32_t M, int32_t hist, bool *nothing) {
+  df_status st = check_dpd_shape(S, len, r, B_max, M, hist);
+  if (st) return st;
+  *nothing = S == 0 || len == 0;
+  if (!*nothing && (!x || !h || !y)) return fail(nullptr, DF_EINVAL, "null pointer");
+  return DF_OK;
+}
+
+extern "C" df_status df_dpd_forward(void *stream, const void *x, const int32_t *ctrl, const void *h, void *y,
+                                    int64_t S, int64_t len, int64_t r, int32_t B_max, int32_t M, int32_t hist) {
+  bool nothing = false;
+  df_status st = check_dpd_forward_args(x, h, y, S, len, r, B_max, M, hist, &nothing);
+  if (st || nothing) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const FwdScratchSize z = dpd_forward_scratch_size(S, len, r, B_max, M, ctrl != nullptr);
+  FwdScratch sc{};
+  hipError_t e = hipMallocAsync((void **)&sc.corr, z.corr, s);
+  if (e == hipSuccess && z.B) e = hipMallocAsync((void **)&sc.B, z.B, s);
+  if (e == hipSuccess && z.prev) e = hipMallocAsync((void **)&sc.prev, z.prev, s);
+  if (e == hipSuccess && z.grp) e = hipMallocAsync((void **)&sc.grp, z.grp, s);
+  if (e == hipSuccess) e = dpd_forward_enqueue(sc, s, x, ctrl, h, y, S, len, r, B_max, M, hist);
+  for (void *p : {(void *)sc.corr, (void *)sc.B, (void *)sc.prev, (void *)sc.grp})
+    if (p) (void)hipFreeAsync(p, s);
   if (e != hipSuccess) return fail_hip(nullptr, e, "df_dpd_forward");
   return DF_OK;
 }

@@ -63,6 +63,9 @@ _SIGS = {
     "df_version": ([], C.c_char_p),
     "df_fifo_create": ([_P, C.c_int, _I64, _I64, _I64, _P, C.POINTER(_I32)], _I32),
     "df_fifo_status": ([_P, _I32, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)], _I32),
+    "df_fifo_create_paper": ([_P, C.c_int, _I64, _I64, _I64, _P, C.POINTER(_I32)], _I32),
+    "df_fifo_bytes": ([_P, _I32], _I64),
+    "df_debug_read_slots": ([_P, _I32, _P, _I64], _I32),
     "df_fifo_info": ([_P, _I32, C.POINTER(_I32), C.POINTER(_I64), C.POINTER(_I64)], _I32),
     "df_port_rate": ([_P, _I32, _I32, C.POINTER(_I64)], _I32),
     "df_actor_create": ([_P, C.c_int, _P, C.c_size_t, C.POINTER(_I32)], _I32),
@@ -256,6 +259,33 @@ def df_fifo_create(g, dtype: int, elems_per_token: int = 1, capacity: int = 0, n
         ptr = _host_ptr(initial)
     _check(_lib.df_fifo_create(g, dtype, elems_per_token, capacity, n_initial, ptr, C.byref(out)), g)
     return out.value
+
+
+def df_fifo_create_paper(g, dtype: int, elems_per_token: int, rate: int, n_initial: int = 0,
+                         initial: np.ndarray | None = None) -> int:
+    """A channel in the paper's layout: 2*rate slots, or 3*rate + 1 with one delay token."""
+    out = C.c_int32()
+    ptr = None
+    if initial is not None:
+        initial = np.ascontiguousarray(initial, dtype=_NP_DTYPE[dtype])
+        if initial.size != n_initial * elems_per_token:
+            raise ValueError("initial has the wrong number of elements")
+        ptr = _host_ptr(initial)
+    _check(_lib.df_fifo_create_paper(g, dtype, elems_per_token, rate, n_initial, ptr, C.byref(out)), g)
+    return out.value
+
+
+def df_fifo_bytes(g, fifo: int) -> int:
+    return int(_lib.df_fifo_bytes(g, fifo))
+
+
+def df_debug_read_slots(g, fifo: int) -> np.ndarray:
+    """Raw slot storage of a channel as a [slots, elems_per_token] array."""
+    dt, ept, tb = df_fifo_info(g, fifo)
+    nbytes = df_fifo_bytes(g, fifo)
+    out = np.zeros(nbytes // tb * ept, _NP_DTYPE[dt])
+    _check(_lib.df_debug_read_slots(g, fifo, _host_ptr(out), out.nbytes), g)
+    return out.reshape(-1, ept)
 
 
 def df_fifo_status(g, fifo: int):

@@ -156,24 +156,34 @@ class Graph:
         return MotionChain(a, fc, fp, fm, fi, width, height)
 
     def paper_motion_pipeline(self, width, height, threshold=20, rate=4, cap=0,
-                              second_output=True, cap_io=0) -> PaperMotionPipeline:
+                              second_output=True, cap_io=0, layout="ring") -> PaperMotionPipeline:
         """Gauss, Thres and Med actors with their five channels; the three
         inner channels hold ``cap`` frames (0: 16), the host-facing input and
         output channels ``cap_io`` (0: same as cap).  With
         second_output=False Gauss writes one channel only and Thres's
-        previous-frame channel must be fed by the caller."""
+        previous-frame channel must be fed by the caller.  layout="paper"
+        builds every channel in the paper's layout instead (Eq. (1): double
+        buffers of 2*rate frames, the delay channel 3*rate + 1 frames with
+        the Fig. 2 access pattern); batches then hold at most two firings."""
         wh = width * height
         p = D.FrameParams(width, height, rate, threshold)
         ga = D.df_actor_create(self.g, D.DF_ACTOR_GAUSS5, p)
         ta = D.df_actor_create(self.g, D.DF_ACTOR_THRES, p)
         ma = D.df_actor_create(self.g, D.DF_ACTOR_MED5, p)
-        c = cap or 16
-        cio = cap_io or c
-        f_in = self.fifo(D.DF_U8, wh, cio)
-        f_cur = self.fifo(D.DF_U8, wh, c)
-        f_del = self.fifo(D.DF_U8, wh, c, 1)         # the one-frame delay
-        f_thr = self.fifo(D.DF_U8, wh, c)
-        f_out = self.fifo(D.DF_U8, wh, cio)
+        if layout == "paper":
+            def pf(n_initial=0):
+                return D.df_fifo_create_paper(self.g, D.DF_U8, wh, rate, n_initial)
+            f_in, f_cur, f_del, f_thr, f_out = pf(), pf(), pf(1), pf(), pf()
+        elif layout == "ring":
+            c = cap or 16
+            cio = cap_io or c
+            f_in = self.fifo(D.DF_U8, wh, cio)
+            f_cur = self.fifo(D.DF_U8, wh, c)
+            f_del = self.fifo(D.DF_U8, wh, c, 1)         # the one-frame delay
+            f_thr = self.fifo(D.DF_U8, wh, c)
+            f_out = self.fifo(D.DF_U8, wh, cio)
+        else:
+            raise ValueError(f"unknown layout {layout!r}")
         D.df_connect(self.g, ga, D.DF_GAUSS_IN, f_in)
         D.df_connect(self.g, ga, D.DF_GAUSS_OUT, f_cur)
         if second_output:

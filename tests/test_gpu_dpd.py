@@ -75,12 +75,12 @@ CASES = [
     (47, 33, 2048, 10, 16, 4, 0, "branch", [33], 0),         # tiles of 1024 in a firing
     (48, 9, 15, 2, 16, 0, 0, "branch", [4, 5], 128),         # r = M - 1 exactly, wrap
     # n_branches_max 11..16: the tiled kernels' 16-branch instantiations
-    (70, 24, 300, 11, 16, 2, 0, "branch", [10, 14], 4096),   # B_max 11, M 16, ragged tile, wrap
+    (70, 24, 300, 11, 16, 2, 0, "branch", [6, 6, 6, 6], 2048),  # B_max 11, M 16, ragged tile, wrap
     (71, 20, 1100, 13, 16, 0, 1, "shared", [20], 0),         # B_max 13, M 16, ragged tail tile
     (72, 32, 257, 16, 16, 3, 0, "branch", [5, 27], 8192),    # B_max 16, M 16, delay, wrap
-    (73, 28, 96, 16, 8, 1, 0, "branch", [28], 2048),         # B_max 16, M 8, wrap
+    (73, 28, 96, 16, 8, 1, 0, "branch", [10, 9, 9], 1024),   # B_max 16, M 8, wrap
     (74, 36, 70, 13, 8, 0, 0, "shared", [9, 9, 18], 0),      # B_max 13, M 8
-    (75, 40, 50, 16, 4, 2, 0, "branch", [40], 1024),         # B_max 16, M 4, wrap
+    (75, 40, 50, 16, 4, 2, 0, "branch", [13, 14, 13], 1024), # B_max 16, M 4, wrap
     (76, 30, 33, 11, 4, 0, 1, "branch", [1] * 30, 64),       # B_max 11, M 4, per-firing
 ]
 
