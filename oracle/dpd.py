@@ -203,19 +203,21 @@ def run_dpd_streams(x, ctrl, h, r, hist="branch", control="count") -> np.ndarray
 
 # ------------------------------------------------------------- rate / offset tables
 
-def writes_branch(ctrl, b, hist="branch") -> np.ndarray:
-    """Firings that write channel s_b: those with B_j > b ("branch"), every
-    firing ("shared")."""
+def writes_branch(ctrl, b, hist="branch", control="count") -> np.ndarray:
+    """Firings that write channel s_b: those in which branch b is active
+    ("branch"), every firing ("shared")."""
     ctrl = np.asarray(ctrl)
     if hist == "shared":
         return np.ones(len(ctrl), bool)
-    return ctrl > b
+    return np.array([active(c, b, control) for c in ctrl], bool)
 
 
-def firing_tables(ctrl, n_branches_max, r, hist="branch"):
+def firing_tables(ctrl, n_branches_max, r, hist="branch", control="count"):
     """Per-firing tables implied by the firing rule (Sec. 2.2), by plain loops:
 
-    rates[b][j]   token rate of A's input port u_b in firing j: r if b < B_j else 0
+    rates[b][j]   token rate of A's input port u_b in firing j: r if branch b
+                  is active in firing j (b < B_j for count tokens, bit b set
+                  for mask tokens), else 0
     offsets[b][j] token offset of firing j's block on channel s_b: r times the
                   number of earlier firings that wrote s_b
     prev[b][j]    last earlier firing that wrote s_b (-1: none); its tail is
@@ -231,11 +233,12 @@ def firing_tables(ctrl, n_branches_max, r, hist="branch"):
         written = 0
         lastw = -1
         for j in range(n):
-            B = _check_ctrl(ctrl[j], n_branches_max)
-            rates[b, j] = r if b < B else 0
+            B = _check_ctrl(ctrl[j], n_branches_max, control)
+            on = active(B, b, control)
+            rates[b, j] = r if on else 0
             offsets[b, j] = r * written
             prev[b, j] = lastw
-            if hist == "shared" or B > b:
+            if hist == "shared" or on:
                 written += 1
                 lastw = j
         last[b] = lastw

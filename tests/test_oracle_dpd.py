@@ -234,3 +234,31 @@ def test_out_of_range_mask_is_rejected():
     w = dpd_random(44, 2, 4, 3, 2)
     with pytest.raises(ValueError):
         dpd.run_dpd(w.x, np.array([1, 8]), w.h, w.r, control="mask")
+
+
+@pytest.mark.parametrize("hist", ["branch", "shared"])
+def test_mask_tables_against_bit_cumsums_and_network(hist):
+    """Tables for mask tokens: rates = r on set bits, offsets and history
+    sources = cumulative sum / maximum of the bit flags (np.cumsum,
+    np.maximum.accumulate), token conservation against the mask network's
+    channels, and prefix masks giving the count tables exactly."""
+    rng = np.random.default_rng(45)
+    w = dpd_random(45, n_firings=50, r=8, n_branches_max=6, n_taps=3)
+    masks = rng.integers(0, 64, 50)
+    rates, offsets, prev, last = dpd.firing_tables(masks, 6, w.r, hist, control="mask")
+    net = dpd.DPDNetwork(w.x, masks, w.h, w.r, hist=hist, control="mask")
+    net.run()
+    n = 50
+    for b in range(6):
+        bit = ((masks >> b) & 1).astype(bool)
+        fed = np.ones(n, bool) if hist == "shared" else bit
+        np.testing.assert_array_equal(rates[b], np.where(bit, w.r, 0))
+        np.testing.assert_array_equal(offsets[b], w.r * np.concatenate([[0], np.cumsum(fed)[:-1]]))
+        incl = np.maximum.accumulate(np.where(fed, np.arange(n), -1))
+        np.testing.assert_array_equal(prev[b], np.concatenate([[-1], incl[:-1]]))
+        assert last[b] == incl[-1]
+        assert net.fs[b].n_written == w.r * fed.sum()
+    counts = rng.integers(0, 7, 50)
+    for t_c, t_m in zip(dpd.firing_tables(counts, 6, w.r, hist),
+                        dpd.firing_tables((1 << counts) - 1, 6, w.r, hist, control="mask")):
+        np.testing.assert_array_equal(t_c, t_m)
