@@ -401,6 +401,23 @@ df_status df_debug_last_batch(df_graph *g, int32_t actor, int32_t *rates,
  * complex64 [B_max][M].  len must be a multiple of r, r >= M-1.
  * Errors: DF_EINVAL (sizes), DF_EDEVICE (launch failure). */
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the same
+ * operation and arguments as df_dpd_forward, with identical results, but
+ * its scratch (branch counts, history sources, scan group table, head
+ * corrections) is a fixed device array of df_dpd_forward_noalloc_max_bytes()
+ * bytes (12 MiB; enough for any call of up to 16384 firings, n_branches_max
+ * <= 16, n_taps <= 32) that each GPU holds until the process ends.  Calls no
+ * allocator.  A call needing more scratch returns DF_EINVAL and does nothing.
+ * All calls on one GPU share that array: calls that overlap in time on one
+ * GPU (different streams, or host threads) race and must be serialised by
+ * the caller; calls ordered on one stream are safe.  Nothing in the array
+ * needs clearing between calls. */
+df_status df_dpd_forward_noalloc(void *stream, const void *x, const int32_t *ctrl,
+                                 const void *h, void *y, int64_t n_streams, int64_t len,
+                                 int64_t r, int32_t B_max, int32_t M, int32_t hist);
+int64_t df_dpd_forward_noalloc_max_bytes(void);
+
 /* y = DPD_h(x) (the predistortion actor body above). */
 df_status df_dpd_forward(void *stream, const void *x, const int32_t *ctrl,
                          const void *h, void *y, int64_t n_streams, int64_t len,

@@ -25,7 +25,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdfhip.so")
 
 SOURCES = ["runtime.cpp", "stateless.cpp", "k_scan.hip", "k_dpd.hip", "k_motion.hip",
-           "k_adjoint.hip", "persist.hip", "k_copy.hip", "k_mdp.hip", "k_dpd_net.hip"]
+           "k_adjoint.hip", "persist.hip", "k_copy.hip", "k_mdp.hip", "k_dpd_net.hip", "noalloc.hip"]
 
 
 def hipcc() -> str:

@@ -83,6 +83,8 @@ _SIGS = {
     "df_debug_last_batch": ([_P, _I32, _P, _P, _P, _I64, C.POINTER(_I64)], _I32),
     "df_debug_set_counters": ([_P, _I32, _I64, _I64], _I32),
     "df_dpd_forward": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
+    "df_dpd_forward_noalloc": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
+    "df_dpd_forward_noalloc_max_bytes": ([], _I64),
     "df_dpd_forward_network": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32], _I32),
     "df_dpd_coeff_adjoint": ([_P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _I32, _P, _I64], _I32),
     "df_dpd_coeff_adjoint_work_bytes": ([_I64, _I64, _I64, _I32, _I32], _I64),
@@ -450,6 +452,20 @@ def df_dpd_forward(x, ctrl, h, y, r: int, hist: int = DF_HIST_BRANCH, stream=Non
     B, M = h.shape
     _check(_lib.df_dpd_forward(_stream_ptr(stream), _dev_ptr(x), None if ctrl is None else _dev_ptr(ctrl),
                                _dev_ptr(h), _dev_ptr(y), S, L, r, B, M, hist))
+
+
+def df_dpd_forward_noalloc(x, ctrl, h, y, r: int, hist: int = DF_HIST_BRANCH, stream=None) -> None:
+    """df_dpd_forward without any allocation (fixed per-GPU scratch; calls
+    overlapping on one GPU race)."""
+    check_dpd_tensors(x, ctrl, h, y, r)
+    S, L = x.shape
+    B, M = h.shape
+    _check(_lib.df_dpd_forward_noalloc(_stream_ptr(stream), _dev_ptr(x), None if ctrl is None else _dev_ptr(ctrl),
+                                       _dev_ptr(h), _dev_ptr(y), S, L, r, B, M, hist))
+
+
+def df_dpd_forward_noalloc_max_bytes() -> int:
+    return int(_lib.df_dpd_forward_noalloc_max_bytes())
 
 
 def df_dpd_forward_network(x, ctrl, h, y, r: int, mask: bool = False, stream=None) -> None:
