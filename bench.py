@@ -362,6 +362,49 @@ def bench_dpd_network(D, torch, steps=5, warmup=2):
                 parity="tests/test_gpu_dpd_network.py::test_scale_workload_sampled_and_against_fused_body")
 
 
+def bench_dpd_mask(D, Graph, torch, steps=10, warmup=2):
+    """The scale workload (2^24 samples, 4096 firings of 4096, B_max 10,
+    M 16) with bit-mask control tokens: each firing's token an arbitrary
+    set of active branches, uniform over the 1023 non-empty sets (seeded).
+    One step = one df_fire of the 4096 firings, inputs resident in HBM."""
+    from workloads import dpd_scale
+    w = dpd_scale()
+    N, r, nf, M = len(w.x), w.r, w.n_firings, w.n_taps
+    masks = np.random.default_rng(12).integers(1, 1 << 10, nf).astype(np.int32)
+    nb = warmup + steps
+    G = Graph(0)
+    ch = G.dpd_chain(w.h, r, cap_x=pow2(nb * N), cap_ctrl=pow2(nb * nf), cap_y=pow2(nb * N), control="mask")
+    x_dev = torch.from_numpy(w.x).cuda()
+    c_dev = torch.from_numpy(masks).cuda()
+    torch.cuda.synchronize()
+    for _ in range(nb):
+        G.push(ch.x, x_dev)
+        G.push(ch.ctrl, c_dev)
+    for _ in range(warmup):
+        G.fire(ch.actor, nf)
+    G.sync()
+    D.df_profile_enable(G.g, True)
+    D.df_profile_read(G.g)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        G.fire(ch.actor, nf)
+    G.sync()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    body_ms, nl = D.df_profile_read(G.g)
+    G.close()
+    body = body_ms / max(nl, 1)
+    # work done: Horner over the highest active branch, zero terms included
+    L = np.array([int(m).bit_length() for m in masks])
+    flops = dpd_flops(L, r, M)
+    return dict(workload="dpd at scale with bit-mask control tokens (arbitrary branch sets, uniform over the "
+                         "1023 non-empty sets of 10 branches), 4096 firings of 4096, 16 taps",
+                msps=round(N / (ms * 1e-3) / 1e6, 1), ms_per_step=round(ms, 4), body_ms=round(body, 4),
+                mean_active_branches=round(float(np.mean([bin(int(m)).count("1") for m in masks])), 2),
+                mean_horner_length=round(float(L.mean()), 2),
+                body_fp32_frac=round(flops / (body * 1e-3) / FP32_PEAK, 4),
+                parity="tests/test_gpu_dpd_mask.py (mask tokens through df_fire and df_fire_many)")
+
+
 def bench_host_io(D, Graph, torch, steps=3, warmup=1):
     """PCIe-inclusive rates: each step pushes its batch from host memory,
     fires it, and pops the outputs back to host memory (the boundary's host
@@ -748,10 +791,12 @@ def summarize_counters(group, bench_json, *csvs):
         t = sum(ds) / len(ds) if ds else None
         valu = mean(lab, "SQ_INSTS_VALU")[0]
         waves = mean(lab, "SQ_WAVES")[0]
-        wcyc = mean(lab, "SQ_WAVE_CYCLES")[0]
-        # SQ_WAVE_CYCLES counts resident wave-cycles in units of 4 cycles, per XCD-summed SQ
-        occ = wcyc * 4 / (t * 2.4e9 * 256) if (wcyc is not None and t) else None
-        issue = valu * 4 / (1024 * 2.4e9 * t) if (valu is not None and t) else None
+        # per-dispatch ratios over the SQ pass's own durations
+        sq = [(d, dur[lab][k]) for k, d in ctr.get(lab, {}).items() if "SQ_INSTS_VALU" in d and dur[lab][k] > 0]
+        issue = (sum(d["SQ_INSTS_VALU"] * 4 / (1024 * 2.4e9 * t_) for d, t_ in sq) / len(sq)) if sq else None
+        # SQ_WAVE_CYCLES: resident wave-cycles in units of 4 cycles, summed over the chip
+        occ_l = [d["SQ_WAVE_CYCLES"] * 4 / (t_ * 2.4e9 * 256) for d, t_ in sq if "SQ_WAVE_CYCLES" in d]
+        occ = sum(occ_l) / len(occ_l) if occ_l else None
 
         def fmt(v, f_="{:.0f}"):
             return "n/a" if v is None else f_.format(v)
@@ -780,6 +825,53 @@ def summarize_counters(group, bench_json, *csvs):
     print("\n".join(lines))
 
 
+STATS_RUNS = {
+    # file, title, bench arguments of the traced run
+    "dpd_scale": ("k_dpd_tiled_dpd_scale_2p24_kernel_stats.md",
+                  "predistortion actor at scale (2^24 samples, 4096 firings of 4096, B 1..10, M 16), "
+                  "20 timed + 3 warm-up batches",
+                  "--no-cpu --no-extras --no-per-firing --steps 20 --warmup 3"),
+    "extras": ("motion_instances_adaptation_kernel_stats.md",
+               "motion (300 x 1920x1080), mask tokens at scale, 1024 lognormal DPD instances (persistent / "
+               "graph / per-actor), adaptation step; plus the main line at 3 batches",
+               "--no-cpu --no-per-firing --only motion,dpd_mask,instances,adaptation --steps 3 --warmup 1"),
+    "md_paper": ("md_paper_pipeline_kernel_stats.md",
+                 "paper motion-detection pipeline, 4096 frames of 320x240 per step (three actors and fused), "
+                 "5 timed + 2 warm-up steps; plus the main line",
+                 "--no-cpu --no-per-firing --only md_paper --steps 5 --warmup 2"),
+}
+
+
+def stats_command(run):
+    return (f"rocprofv3 --kernel-trace --stats -d kt_{run} -o kt_{run} --output-format csv -- python3 "
+            f"/root/repo/bench.py {STATS_RUNS[run][2]} > kt_{run}.json")
+
+
+def summarize_kernel_stats(run, stats_csv):
+    """profiles/ summary of a rocprofv3 --kernel-trace --stats run (the
+    kernel_stats.csv it writes): per kernel the calls and durations."""
+    import csv
+    fname, title, _ = STATS_RUNS[run]
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# Kernel trace: {title}", "",
+             "Command (on the GPU host, after `cd /tmp && export TMPDIR=/tmp`):", "",
+             "    " + stats_command(run),
+             f"    python3 /root/repo/bench.py --summarize-kernel-stats {run} kt_{run}/kt_{run}_kernel_stats.csv", "",
+             "rocprofv3 kernel statistics (durations in microseconds):", "",
+             "| kernel | calls | total us | average us | min us | max us | % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows[:24]:
+        name = r["Name"][:110]
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    lines.append("")
+    with open(os.path.join(ROOT, "profiles", fname), "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -787,7 +879,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,md_paper,dpd_network,host_io,instances,adaptation")
+    ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,md_paper,dpd_network,dpd_mask,host_io,instances,"
+                         "adaptation")
     ap.add_argument("--no-per-firing", action="store_true", help="skip the per-firing launch comparisons")
     ap.add_argument("--calibrate-copy", type=int, default=1024, metavar="MIB",
                     help="stream-copy reference size in MiB (bandwidth and traffic-counter reference; 0: off)")
@@ -796,11 +889,20 @@ def main():
                          f"({', '.join(COUNTER_GROUPS)}) from rocprofv3 --pmc runs of this script (no GPU)")
     ap.add_argument("--print-profile-commands", metavar="GROUP",
                     help="print the rocprofv3 commands of a counter group's passes")
+    ap.add_argument("--summarize-kernel-stats", nargs=2, metavar=("RUN", "STATS_CSV"),
+                    help=f"write the profiles/ kernel-trace summary of a traced run ({', '.join(STATS_RUNS)})")
+    ap.add_argument("--print-stats-command", metavar="RUN", help="print the rocprofv3 kernel-trace command of a run")
     args = ap.parse_args()
     if args.summarize_counters:
         if len(args.summarize_counters) < 3 or args.summarize_counters[0] not in COUNTER_GROUPS:
             ap.error("--summarize-counters takes GROUP BENCH_JSON CSV...")
         summarize_counters(*args.summarize_counters)
+        return
+    if args.summarize_kernel_stats:
+        summarize_kernel_stats(*args.summarize_kernel_stats)
+        return
+    if args.print_stats_command:
+        print(stats_command(args.print_stats_command))
         return
     if args.print_profile_commands:
         for lab, c in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"), ("sq", SQ_PASS)):
@@ -850,6 +952,7 @@ def main():
               ("motion", lambda: bench_motion(D, Graph, torch)),
               ("md_paper", lambda: bench_md_paper(D, Graph, torch)),
               ("dpd_network", lambda: bench_dpd_network(D, torch)),
+              ("dpd_mask", lambda: bench_dpd_mask(D, Graph, torch)),
               ("host_io", lambda: bench_host_io(D, Graph, torch)),
               ("instances", lambda: bench_instances(D, Graph, torch)),
               ("adaptation", lambda: bench_adaptation(D, torch))]

@@ -97,8 +97,16 @@ enum { DF_FIRE_PERSISTENT = 1, DF_FIRE_GRAPH = 2 };
  * where s_b is branch b's input sample stream under history_mode.  Branches
  * b >= B have token rate 0 in this firing (Sec. 2.2: a dynamic actor's
  * regular ports take rate 0 or r per firing, fixed by the control token).
+ * control_mode DF_CTRL_COUNT reads B as above (the prefix of branches 0..B-1
+ * active); DF_CTRL_MASK reads a token as a bit mask, branch b active when
+ * bit b is set, 0 <= token < 2^n_branches_max: any set of branches (Sec. 4.2
+ * lets the configuration actor select which set of FIR filters runs, and
+ * Sec. 3.1 leaves the mapping of control tokens to rates open).  The sum
+ * above then runs over the set's branches.
  * Constraint: firing_size >= n_taps - 1.
  */
+/* How a predistortion actor reads its control tokens. */
+enum { DF_CTRL_COUNT = 0, DF_CTRL_MASK = 1 };
 typedef struct {
   int32_t n_branches_max;   /* 1..16                                            */
   int32_t n_taps;           /* 1..32                                            */
@@ -107,7 +115,10 @@ typedef struct {
                                host or device (coeffs_on_device); copied        */
   int32_t coeffs_on_device;
   int32_t history_mode;     /* DF_HIST_BRANCH or DF_HIST_SHARED                 */
-} df_dpd_params;
+  int32_t control_mode;     /* DF_CTRL_COUNT or DF_CTRL_MASK                    */
+  int32_t reserved;         /* 0                                                */
+} df_dpd_params;            /* df_actor_create also takes the struct without
+                               the last two fields (count tokens)               */
 
 /*
  * Motion actor (frame difference, threshold, 3x3 opening; Sec. 4.1 builds
@@ -436,7 +447,6 @@ df_status df_dpd_forward(void *stream, const void *x, const int32_t *ctrl,
  * only (the FIR actors' own delay lines, DF_HIST_BRANCH); ctrl must not be
  * NULL.  With count tokens the results equal df_dpd_forward's up to FP32
  * rounding order.  Errors as df_dpd_forward. */
-enum { DF_CTRL_COUNT = 0, DF_CTRL_MASK = 1 };
 df_status df_dpd_forward_network(void *stream, const void *x, const int32_t *ctrl,
                                  const void *h, void *y, int64_t n_streams, int64_t len,
                                  int64_t r, int32_t B_max, int32_t M, int32_t ctrl_mode);

@@ -52,13 +52,33 @@ __device__ __forceinline__ void check_chan(const int64_t *slot, int32_t *err) {
 
 // ---------------------------------------------------------------- DPD
 //
+// Active branches of a firing as the kernels carry them: a bit set, bit b
+// set when branch b runs (Sec. 4.2: the configuration selects which set of
+// FIR filters takes part).  A count token B (the prefix reading) is the set
+// {0, .., B-1}; a mask token is its own bits.  The Horner length of a set is
+// its highest member + 1.
+enum : int32_t { kCtrlCount = 0, kCtrlMask = 1 };
+
+__device__ __host__ __forceinline__ uint32_t prefix_set(int B) { return B >= 32 ? ~0u : (1u << B) - 1u; }
+__device__ __host__ __forceinline__ bool in_set(uint32_t s, int b) { return (s >> b) & 1u; }
+__device__ __forceinline__ int set_len(uint32_t s) { return s ? 32 - __builtin_clz(s) : 0; }
+
+// Validated branch set of control token v: count tokens 0..B_max, mask
+// tokens 0..2^B_max - 1; anything else is the empty set and sets *bad.
+__device__ __forceinline__ uint32_t token_set(int32_t v, int32_t mode, int32_t B_max, bool *bad) {
+  const bool ok = mode == kCtrlMask ? (v >= 0 && v < (1 << B_max)) : (v >= 0 && v <= B_max);
+  *bad = !ok;
+  if (!ok) return 0u;
+  return mode == kCtrlMask ? (uint32_t)v : prefix_set(v);
+}
+//
 // One batch of predistortion firings.  Firing g (0 <= g < n_firings) reads
 // r input samples starting at sample position xpos(g) and writes r output
 // samples at ypos(g):
 //   actor mode:      xpos(g) = R_x + g*r (ring, masked), ypos(g) = W_y + g*r
 //   stateless mode:  xpos(g) = g*r, ypos(g) = g*r (rows of length
 //                    seg_firings*r concatenated; no wrap: mask = -1)
-// B[g] is the firing's validated branch count (nullptr: B_const).
+// B[g] is the firing's validated branch set (nullptr: branches 0..B_const-1).
 // prev[b*prev_stride + g] is the firing whose tail is branch b's FIR history
 // (-1: carried state `hist` [b][M-1], nullptr history = zeros).  With
 // prev == nullptr the history firing is g-1 inside its segment of
@@ -90,8 +110,8 @@ struct DpdArgs {
   int64_t y_mask;
   const float2 *h;        // [B_max][M]
   const float2 *hist;     // [B_max][M-1] or nullptr
-  const int32_t *B;       // [n_firings] or nullptr
-  int32_t B_const;
+  const int32_t *B;       // [n_firings] branch sets, or nullptr
+  int32_t B_const;        // branch count of every firing when B is nullptr
   const int64_t *prev;    // [B_max][prev_stride] or nullptr
   int64_t prev_stride;
   int64_t seg_firings;
@@ -109,6 +129,7 @@ struct DpdArgs {
   int64_t *tab_prev;      // [B_max][prev_stride]
   int64_t *tab_off;       // [B_max][prev_stride] or nullptr
   int32_t hist_mode;
+  int32_t masked;         // branch sets may be non-prefix (bit-mask control tokens)
   int32_t *ticket;        // tiled kernel: the last workgroup to finish runs `commit` (nullptr: none)
   DpdCommitArgs commit;
 };
@@ -123,11 +144,12 @@ struct ScanArgs {
   int32_t n_segs;
   int32_t B_max;
   int32_t hist_mode;      // 0 branch, 1 shared
-  int32_t *B_out;         // [n_segs*seg_firings]
+  int32_t ctrl_mode;      // kCtrlCount or kCtrlMask
+  int32_t *B_out;         // [n_segs*seg_firings] validated branch sets
   int64_t *prev_out;      // [B_max][stride]
   int64_t *off_out;       // [B_max][stride] (may be nullptr)
   int64_t *last_out;      // [n_segs][B_max] (may be nullptr)
-  int32_t *order_out;     // [n][2] (firing, B) grouped by B, largest first (one segment), or nullptr
+  int32_t *order_out;     // [n][2] (firing, set) grouped by Horner length, largest first (one segment), or nullptr
   int64_t *grp;           // [scan_groups][B_max][2] scratch: count and last feeder before each 64-firing group
   int64_t stride;
   int64_t r;
@@ -165,7 +187,7 @@ struct MotionArgs {
 struct AdjArgs {
   const float2 *x;        // [n_firings * r]
   const float2 *G;        // [n_firings * r]
-  const int32_t *B;       // [n_firings] or nullptr (all B_max branches)
+  const int32_t *B;       // [n_firings] branch sets, or nullptr (all B_max branches)
   const int64_t *prev;    // [B_max][prev_stride] or nullptr
   int64_t prev_stride;
   int64_t seg_firings;
@@ -259,7 +281,7 @@ struct DpdNetArgs {
   int32_t B_max, M;
   float2 *chan;          // [B_max][S][nf*r] Poly -> FIR_b channels
   float2 *firo;          // [B_max][S][nf*r] FIR_b -> Adder channels
-  int32_t mask_mode;     // 0: B[g] counts (branches b < B active), 1: B[g] is a bit mask
+  int32_t mask_mode;     // tokens are bit masks (k_mask_tables validates them); B holds branch sets either way
 };
 hipError_t launch_dpd_network(const DpdNetArgs &a, hipStream_t s, const KTiming *t = nullptr);
 // Tables for bit-mask control tokens: validated masks (out of range -> 0)

@@ -5,6 +5,8 @@
 // branch sum is evaluated per tap as a polynomial in p = |x|^2 (Horner over
 // branches, Sec. 4.2 actor body):
 //   y[t] = sum_m x[t-m] * P_m(p[t-m]),   P_m(p) = sum_{b<B} h[b][m] p^b.
+// With a branch set that is not a prefix, the coefficients of the inactive
+// branches below the highest active one enter the polynomial as zeros.
 // The samples before the firing start are staged as zeros; the taps that
 // reach there read branch b's own history and are added per branch.
 #pragma once
@@ -30,6 +32,14 @@ __device__ __forceinline__ float2 ldc(cfloat2p p, int i) {
   return make_float2(f[2 * i], f[2 * i + 1]);
 }
 
+// Element i, or +0 when `keep` is clear (all-ones / all-zero word: the
+// select is a bitwise AND on the uniform coefficient words).
+__device__ __forceinline__ float2 ldc_masked(cfloat2p p, int i, uint32_t keep) {
+  const float2 v = ldc(p, i);
+  return make_float2(__builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v.x) & keep),
+                     __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v.y) & keep));
+}
+
 // LDS slot of window sample i: one pad slot per 8 samples, so the K-strided
 // register-window reads of a wavefront fall on distinct banks.
 __host__ __device__ constexpr int lds_slot(int i) { return i + (i >> 3); }
@@ -42,13 +52,20 @@ __host__ __device__ constexpr int lds_window(int n) { return lds_slot(n) + 1; }
 // Reads stay inside the window buffer (index < tile+M-1); in a partial tile,
 // slots past the staged samples only feed outputs that are not stored.
 // hg: the firing's coefficients [B][M] (uniform address: scalar loads).
+// MASKED: set is the firing's branch set (B = its Horner length) and the
+// coefficients of branches outside it read as zero; without MASKED the set
+// is the prefix 0..B-1 and the coefficients are used as loaded.
 // Software pipeline of depth one: tap m+1's coefficients and sample are
 // loaded before tap m's arithmetic; a compiler fence after each tap keeps
 // later loads from being hoisted (which would keep every tap's
 // coefficients live at once and spill).
-template <int M, int K, int B>
-__device__ __forceinline__ void horner_taps(cfloat2p hg, const float2 *sx, int q0, float (&ar)[K],
+template <int M, int K, int B, bool MASKED>
+__device__ __forceinline__ void horner_taps(cfloat2p hg, uint32_t set, const float2 *sx, int q0, float (&ar)[K],
                                             float (&ai)[K]) {
+  auto coef = [&](int b, int i) {
+    if constexpr (MASKED) return ldc_masked(hg, i, 0u - ((set >> b) & 1u));
+    else return ldc(hg, i);
+  };
   float2 wv[K];
   float pv[K];
 #pragma unroll
@@ -58,14 +75,14 @@ __device__ __forceinline__ void horner_taps(cfloat2p hg, const float2 *sx, int q
   }
   float2 hc[B];
 #pragma unroll
-  for (int b = 0; b < B; ++b) hc[b] = ldc(hg, b * M);
+  for (int b = 0; b < B; ++b) hc[b] = coef(b, b * M);
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     float2 hn[B];
     float2 wn = make_float2(0.f, 0.f);
     if (m + 1 < M) {
 #pragma unroll
-      for (int b = 0; b < B; ++b) hn[b] = ldc(hg, b * M + m + 1);
+      for (int b = 0; b < B; ++b) hn[b] = coef(b, b * M + m + 1);
       wn = sx[lds_slot(q0 + M - 2 - m)];
     }
 #pragma unroll
@@ -135,42 +152,55 @@ __device__ __forceinline__ void head_taps(cfloat2p hg, int b, float psr, float p
 // accumulated branch by branch.  All history loads are issued at once; psi
 // values move inside a row by DPP row shifts; the coefficients are the same
 // for every row (uniform scalar loads).
-//   B_of(row) -> branch count of the row's firing (0: no correction)
+//   B_of(row) -> branch set of the row's firing (empty: no correction)
 //   src_of(row, b) -> history source firing of branch b (-1: carried state)
 //   sample(row, b, pf, i) -> sample i of branch b's history
-//   out(row) -> where the row's M-1 corrections go
-template <int M, int ROWS, class BOf, class SrcOf, class Sample, class Out>
-__device__ __forceinline__ void head_correction(cfloat2p hg, BOf B_of, SrcOf src_of, Sample sample, Out out) {
+// Only branches b_first, b_first + b_step, ... are evaluated (a head pass may
+// split a firing's branches over several wavefronts); for each, in
+// increasing b, emit(b, active, sr, si) receives the lane's sum over that
+// branch's taps (active: b is in the row's branch set).  The correction of
+// (row, output i) is the sum of the active branches' values in increasing
+// b, starting from 0 (every caller keeps that order, so all head passes
+// round alike); it is meaningful where head_live() holds.
+template <int M, int ROWS>
+__device__ __forceinline__ bool head_live(uint32_t set) {
+  const int lane = threadIdx.x & 63, row = lane >> 4, i = lane & 15;
+  return row < ROWS && i < M - 1 && set != 0u;
+}
+
+template <int M, int ROWS, class BOf, class SrcOf, class Sample, class Emit>
+__device__ __forceinline__ void head_correction(cfloat2p hg, BOf B_of, SrcOf src_of, Sample sample, int b_first,
+                                                int b_step, Emit emit) {
   constexpr int L = M - 1;
   static_assert(L < 16, "one row of 16 lanes per firing");
   const int lane = threadIdx.x & 63, row = lane >> 4, i = lane & 15;
   const bool live = row < ROWS && i < L;
-  const int B = row < ROWS ? B_of(row) : 0;
-  int Bw = B;                                          // largest B of the wavefront
+  const uint32_t all = row < ROWS ? (uint32_t)B_of(row) : 0u;
+  uint32_t pick = 0u;                                  // branches of this pass
+  for (int b = b_first; b < kMaxBranches; b += b_step) pick |= 1u << b;
+  const uint32_t set = all & pick;
+  const int B = set_len(set);
+  int Bw = B;                                          // largest Horner length of the wavefront
 #pragma unroll
   for (int o = 16; o < 64; o <<= 1) Bw = max(Bw, __shfl_xor(Bw, o));
   Bw = __builtin_amdgcn_readfirstlane(Bw);
   int64_t pf[kMaxBranches];
 #pragma unroll
-  for (int b = 0; b < kMaxBranches; ++b) pf[b] = (b < B && live) ? src_of(row, b) : -1;
+  for (int b = 0; b < kMaxBranches; ++b) pf[b] = (in_set(set, b) && live) ? src_of(row, b) : -1;
   float2 xs[kMaxBranches];
 #pragma unroll
-  for (int b = 0; b < kMaxBranches; ++b) xs[b] = (b < B && live) ? sample(row, b, pf[b], i) : make_float2(0.f, 0.f);
-  float cr = 0.f, ci = 0.f;
+  for (int b = 0; b < kMaxBranches; ++b)
+    xs[b] = (in_set(set, b) && live) ? sample(row, b, pf[b], i) : make_float2(0.f, 0.f);
 #pragma unroll
   for (int b = 0; b < kMaxBranches; ++b) {
-    if (b >= Bw) continue;                             // uniform
+    if (b >= Bw || !in_set(pick, b)) continue;         // uniform
     const float pp = fmaf(xs[b].x, xs[b].x, xs[b].y * xs[b].y);
     float pb = 1.f;
     for (int e = 0; e < b; ++e) pb *= pp;
     float sr = 0.f, si = 0.f;
     head_taps<M, 1>(hg, b, pb * xs[b].x, pb * xs[b].y, sr, si);
-    if (b < B) {
-      cr += sr;
-      ci += si;
-    }
+    emit(b, in_set(set, b), sr, si);
   }
-  if (live && B > 0) out(row)[i] = make_float2(cr, ci);
 }
 
 // The tile pipeline.  A workgroup of NT threads computes tiles of K*NT
@@ -193,7 +223,8 @@ struct Job {
   int64_t xb, yb;         // ring positions of the firing's first input / output sample
   int t0;                 // first output of the tile within the firing
   int nout;               // outputs in the tile
-  int B;                  // active branches of the firing
+  uint32_t set;           // active branches of the firing (bit set)
+  int B;                  // its Horner length (highest active branch + 1)
   int head;               // first tile of a firing with active branches (0/1)
 };
 
@@ -226,9 +257,10 @@ __device__ __forceinline__ void commit_tile(float2 *sx, float2 *sc, const TileRe
 }
 
 // The tile's main arithmetic (window in sx) for this thread's K outputs.
-// BC: largest branch count compiled (10 or 16; fewer unrolled paths keep
-// the register budget of the common configurations small).
-template <int M, int K, int BC>
+// BC: largest Horner length compiled (10 or 16; fewer unrolled paths keep
+// the register budget of the common configurations small).  MASKED: tiles
+// may carry branch sets that are not prefixes (bit-mask control tokens).
+template <int M, int K, int BC, bool MASKED>
 __device__ __forceinline__ void tile_compute(const float2 *sx, cfloat2p hg, const Job &j, float (&ar)[K],
                                              float (&ai)[K]) {
   const int q0 = threadIdx.x * K;
@@ -238,7 +270,7 @@ __device__ __forceinline__ void tile_compute(const float2 *sx, cfloat2p hg, cons
   switch (j.B) {
 #define DF_CASE(n) \
   case n:                                                  \
-    if constexpr (n <= BC) horner_taps<M, K, n>(hg, sx, q0, ar, ai); \
+    if constexpr (n <= BC) horner_taps<M, K, n, MASKED>(hg, j.set, sx, q0, ar, ai); \
     break;
     DF_CASE(1) DF_CASE(2) DF_CASE(3) DF_CASE(4) DF_CASE(5) DF_CASE(6) DF_CASE(7) DF_CASE(8)
     DF_CASE(9) DF_CASE(10) DF_CASE(11) DF_CASE(12) DF_CASE(13) DF_CASE(14) DF_CASE(15) DF_CASE(16)
@@ -281,7 +313,7 @@ __device__ __forceinline__ uint64_t qword_at(uint32_t dv, int w) {
 // src.fetch(k) loads tile k's raw descriptor lane-distributed into one
 // register (a vector load, two tiles ahead); src.expand(dv, k, job) turns it
 // into the uniform Job (lane reads) when the tile's loads are issued.
-template <int M, int K, int BC, class Src>
+template <int M, int K, int BC, bool MASKED, class Src>
 __device__ __forceinline__ void run_tiles(float2 *sx, float2 *sc, int64_t n_items, Src &src) {
   const int64_t s = gridDim.x;
   int64_t item = blockIdx.x;
@@ -299,7 +331,7 @@ __device__ __forceinline__ void run_tiles(float2 *sx, float2 *sc, int64_t n_item
     if (has_next) load_tile<M, K>(regs, nxt);
     const uint32_t dv_nn = has_nn ? src.fetch(item + 2 * s) : 0u;
     float ar[K], ai[K];
-    tile_compute<M, K, BC>(sx, as_const(cur.h), cur, ar, ai);
+    tile_compute<M, K, BC, MASKED>(sx, as_const(cur.h), cur, ar, ai);
     tile_store<M, K>(sc, cur, ar, ai);
     if (!has_next) break;
     __syncthreads();

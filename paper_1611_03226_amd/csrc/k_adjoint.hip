@@ -55,16 +55,23 @@ __global__ __launch_bounds__(512) void k_adj_partial(AdjArgs a) {
   const int64_t c = blockIdx.x - g * a.chunks_per_firing;
   const int64_t n0 = c * a.chunk;
   const int nout = (int)min((int64_t)a.chunk, a.r - n0);
-  const int B = a.B ? a.B[g] : BM;
+  const uint32_t set = a.B ? (uint32_t)a.B[g] : prefix_set(BM);
+  const int B = set_len(set);
   const int64_t xb = g * a.r;
+  // G of the chunk's outputs, staged with M-1 zeros before and M+2 after, so
+  // that every (sample, tap) pair of the loop below reads a defined value
+  // (zero where the output lies outside the chunk, or the tap past M in the
+  // last wavefront's group of 4) and the loop carries no bounds checks
+  const int gpad = M - 1, gpost = M + 2;
   float2 *sx = lds;                       // window: nout + M - 1 samples
-  float2 *sg = lds + a.chunk + M - 1;     // G of the chunk's outputs
-  float2 *red = sg + a.chunk;             // [BM][M] reduced sums
+  float2 *sg = lds + a.chunk + M - 1 + gpad;
+  float2 *red = sg + a.chunk + gpost;     // [BM][M] reduced sums
   for (int i = threadIdx.x; i < nout + M - 1; i += blockDim.x) {
     const int64_t pos = n0 - (M - 1) + i;
     sx[i] = pos >= 0 ? a.x[xb + pos] : make_float2(0.f, 0.f);
   }
-  for (int i = threadIdx.x; i < nout; i += blockDim.x) sg[i] = a.G[xb + n0 + i];
+  for (int i = threadIdx.x - gpad; i < nout + gpost; i += blockDim.x)
+    sg[i] = (i >= 0 && i < nout) ? a.G[xb + n0 + i] : make_float2(0.f, 0.f);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int m0 = (threadIdx.x >> 6) * 4;  // first tap of this wavefront
@@ -83,17 +90,15 @@ __global__ __launch_bounds__(512) void k_adj_partial(AdjArgs a) {
     for (int b = 1; b < BM; ++b) pw[b] = pw[b - 1] * p;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int m = m0 + q;
-      const int o = i - (M - 1) + m;      // output index within the chunk
-      if (m < M && o >= 0 && o < nout) {
-        const float2 gv = sg[o];
-        const float zr = fmaf(gv.x, xv.x, gv.y * xv.y);   // G conj(x)
-        const float zi = fmaf(gv.y, xv.x, -(gv.x * xv.y));
+      // output index within the chunk: -(M-1) <= o < nout + M + 2 (zeros outside)
+      const int o = i - (M - 1) + m0 + q;
+      const float2 gv = sg[o];
+      const float zr = fmaf(gv.x, xv.x, gv.y * xv.y);     // G conj(x)
+      const float zi = fmaf(gv.y, xv.x, -(gv.x * xv.y));
 #pragma unroll
-        for (int b = 0; b < BM; ++b) {
-          accr[q][b] = fmaf(zr, pw[b], accr[q][b]);
-          acci[q][b] = fmaf(zi, pw[b], acci[q][b]);
-        }
+      for (int b = 0; b < BM; ++b) {
+        accr[q][b] = fmaf(zr, pw[b], accr[q][b]);
+        acci[q][b] = fmaf(zi, pw[b], acci[q][b]);
       }
     }
   }
@@ -131,7 +136,7 @@ __global__ __launch_bounds__(512) void k_adj_partial(AdjArgs a) {
   for (int t = threadIdx.x; t < BM * M; t += blockDim.x) {
     const int b = t / M, mm = t - b * M;
     float sr = 0.f, si = 0.f;
-    if (b < B) {
+    if (in_set(set, b)) {
       sr = red[t].x;
       si = red[t].y;
       if (n0 == 0) {
@@ -180,7 +185,8 @@ hipError_t launch_adj(const AdjArgs &a, hipStream_t s) {
   const int64_t blocks = a.n_firings * a.chunks_per_firing;
   if (blocks > 0) {
     const int threads = 64 * ((a.M + 3) / 4);          // one wavefront per 4 taps
-    const size_t lds = sizeof(float2) * ((size_t)2 * a.chunk + a.M - 1 + (size_t)a.B_max * (2 * a.M - 1));
+    const size_t lds = sizeof(float2) * ((size_t)2 * a.chunk + a.M - 1 + (a.M - 1) + (a.M + 2) +
+                                         (size_t)a.B_max * (2 * a.M - 1));
     switch (a.B_max) {
 #define DF_CASE(n) \
   case n: hipLaunchKernelGGL(k_adj_partial<n>, dim3((unsigned)blocks), dim3(threads), lds, s, a); break;

@@ -1,8 +1,10 @@
 // HBM bandwidth references (no operation of the method): the achievable
 // bandwidth against which the actor kernels are measured, and the scale for
 // the FETCH_SIZE / WRITE_SIZE traffic counters.  Four access mixes, all with
-// 16-byte streaming (non-temporal) accesses and a persistent grid-stride
-// loop that keeps eight independent 16-byte loads per thread in flight:
+// 16-byte streaming (non-temporal) accesses, eight independent 16-byte
+// accesses per thread in flight, and one workgroup per 32 KiB span (a grid
+// as large as the data: the measured best; the grid-stride loop only runs
+// past one span when the grid limit is reached):
 //   copy   dst[i] = src[i]                 (1 read : 1 write)
 //   read   XOR-fold of src                 (read only)
 //   write  dst[i] = pattern                (write only)
@@ -70,8 +72,7 @@ __global__ __launch_bounds__(kRefThreads) void k_hbm_ref(const v4 *__restrict__ 
 template <int MODE>
 hipError_t launch_ref(const void *src, void *dst, int64_t n, hipStream_t s) {
   const int64_t want = (n + kRefStep - 1) / kRefStep;
-  const int64_t resident = resident_blocks((const void *)k_hbm_ref<MODE>, kRefThreads, 0);
-  const int64_t blocks = std::max<int64_t>(1, std::min(want, 4 * resident));
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(want, 1 << 30));
   hipLaunchKernelGGL(k_hbm_ref<MODE>, dim3((unsigned)blocks), dim3(kRefThreads), 0, s, (const v4 *)src, (v4 *)dst, n);
   return hipGetLastError();
 }

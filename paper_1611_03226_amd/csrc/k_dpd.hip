@@ -38,11 +38,12 @@ __global__ __launch_bounds__(256) void k_dpd_generic(DpdArgs a) {
   if (t >= a.n_firings * a.r) return;
   const int64_t g = t / a.r;
   const int64_t i = t - g * a.r;
-  const int B = a.B ? a.B[g] : a.B_const;
+  const uint32_t set = a.B ? (uint32_t)a.B[g] : prefix_set(a.B_const);
   const int64_t Rx = a.x_idx ? a.x_idx[0] : 0;
   const int64_t Wy = a.y_idx ? a.y_idx[1] : 0;
   float ar = 0.f, ai = 0.f;
-  for (int b = 0; b < B; ++b) {
+  for (int b = 0; b < kMaxBranches; ++b) {
+    if (!in_set(set, b)) continue;
     const int64_t pf = (i < a.M - 1) ? prev_of(a, b, g) : -1;
     for (int m = 0; m < a.M; ++m) {
       const int64_t ii = i - m;
@@ -93,8 +94,13 @@ __device__ __forceinline__ void dpd_commit_block(const DpdCommitArgs &a) {
 // plus the group's entry (count and last feeder before it) gives them.
 template <int M, bool TABLES>
 __global__ __launch_bounds__(256) void k_dpd_heads(DpdArgs a) {
-  const int64_t g0 = ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * 4;
-  if (g0 >= a.n_firings) return;                     // uniform per wavefront
+  // The workgroup's four wavefronts share four firings; wavefront w takes
+  // branches w, w+4, w+8, w+12 (more wavefronts in flight, a quarter of the
+  // serial work each); each branch's sum goes to LDS and one wavefront adds
+  // them in increasing branch order, as a single pass would.
+  __shared__ float2 part[kMaxBranches][64];
+  const int64_t g0 = (int64_t)blockIdx.x * 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t Rx = a.x_idx ? as_const(a.x_idx)[0] : 0;
   const int lane = threadIdx.x & 63, row = lane >> 4, i = lane & 15;
   const int64_t g = g0 + row;                         // this lane's firing
@@ -103,13 +109,13 @@ __global__ __launch_bounds__(256) void k_dpd_heads(DpdArgs a) {
     const int64_t G = g0 >> 6;
     const int64_t gl = G * 64 + lane;                 // lane's firing of the group
     const bool gin = gl < a.n_firings;
-    const int Bl = gin ? (a.B ? a.B[gl] : a.B_const) : 0;
+    const uint32_t Bl = gin ? (a.B ? (uint32_t)a.B[gl] : prefix_set(a.B_const)) : 0u;
     const uint64_t below_mask = (1ull << ((g0 & 63) + row)) - 1;
 #pragma unroll
     for (int b = 0; b < kMaxBranches; ++b) {
       pf[b] = -1;
-      if (b >= a.B_max) continue;                     // uniform
-      const uint64_t bal = __ballot(gin && (a.hist_mode == 1 || Bl > b));
+      if (b >= a.B_max || (b & 3) != w) continue;     // uniform
+      const uint64_t bal = __ballot(gin && (a.hist_mode == 1 || in_set(Bl, b)));
       const int64_t gi = 2 * (G * a.B_max + b);
       const int64_t cnt0 = as_const(a.grp)[gi], last0 = as_const(a.grp)[gi + 1];
       const uint64_t below = bal & below_mask;
@@ -121,24 +127,35 @@ __global__ __launch_bounds__(256) void k_dpd_heads(DpdArgs a) {
       }
     }
   }
+  const auto B_of = [&](int r) {
+    const int64_t gr = g0 + r;
+    return gr < a.n_firings ? (a.B ? (uint32_t)a.B[gr] : prefix_set(a.B_const)) : 0u;
+  };
   head_correction<M, 4>(
-      as_const(a.h),
-      [&](int r) {
-        const int64_t gr = g0 + r;
-        return gr < a.n_firings ? (a.B ? a.B[gr] : a.B_const) : 0;
-      },
+      as_const(a.h), B_of,
       [&](int r, int b) {
         if constexpr (TABLES) return pf[b];              // this lane's row
         else return prev_of(a, b, g0 + r);
       },
       [&](int r, int b, int64_t p, int q) { return hist_sample(a, Rx, b, g0 + r, p, (int64_t)q - (M - 1)); },
-      [&](int r) { return a.corr + (g0 + r) * (M - 1); });
+      w, 4, [&](int b, bool, float sr, float si) { part[b][lane] = make_float2(sr, si); });
+  __syncthreads();
+  const uint32_t set = B_of(row);
+  if (w == 0 && head_live<M, 4>(set)) {
+    float cr = 0.f, ci = 0.f;
+    for (int b = 0; b < kMaxBranches; ++b)
+      if (in_set(set, b)) {
+        cr += part[b][lane].x;
+        ci += part[b][lane].y;
+      }
+    a.corr[g * (M - 1) + i] = make_float2(cr, ci);
+  }
 }
 
 // ------------------------------------------------------------------ tiled
 // Tile descriptors of a single actor's batch: tile k is tile k % tpf of the
-// (k / tpf)-th firing in processing order (pairs (firing, B) from the
-// scan, or firing order).
+// (k / tpf)-th firing in processing order (pairs (firing, branch set) from
+// the scan, or firing order).
 struct SingleSrc {
   const DpdArgs &a;
   int64_t Rx, Wy;
@@ -147,14 +164,14 @@ struct SingleSrc {
     const int64_t k = it / a.tiles_per_firing;
     if (a.order) return lane < 2 ? (uint32_t)a.order[2 * k + lane] : 0u;
     if (lane == 0) return (uint32_t)k;
-    if (lane == 1) return (uint32_t)(a.B ? a.B[k] : a.B_const);
+    if (lane == 1) return a.B ? (uint32_t)a.B[k] : prefix_set(a.B_const);
     return 0u;
   }
   __device__ void expand(uint32_t dv, int64_t it, Job &j) const {
     const int64_t k = it / a.tiles_per_firing;
     const int64_t tk = it - k * a.tiles_per_firing;
     const int64_t g = dword_at(dv, 0);
-    const int B = (int)dword_at(dv, 1);
+    const uint32_t set = dword_at(dv, 1);
     j.x = a.x;
     j.y = a.y;
     j.h = a.h;
@@ -165,19 +182,20 @@ struct SingleSrc {
     j.yb = Wy + g * a.r;
     j.t0 = (int)(tk * a.tile);
     j.nout = (int)min((int64_t)a.tile, a.r - j.t0);
-    j.B = B;
-    j.head = (j.t0 == 0 && B > 0) ? 1 : 0;
+    j.set = set;
+    j.B = set_len(set);
+    j.head = (j.t0 == 0 && set != 0u) ? 1 : 0;
   }
 };
 
-// Grid-stride loop over the batch's tiles in the B-grouped firing order,
+// Grid-stride loop over the batch's tiles in the length-grouped firing order,
 // pipelined as run_tiles describes.
-template <int M, int K, int BC>
+template <int M, int K, int BC, bool MASKED>
 __global__ __launch_bounds__(256) void k_dpd_tiled(DpdArgs a) {
   extern __shared__ float2 lds[];   // [M-1] head corrections, window
   float2 *sc = lds, *sx = sc + lds_corr(M);
   SingleSrc src{a, a.x_idx ? as_const(a.x_idx)[0] : 0, a.y_idx ? as_const(a.y_idx)[1] : 0};
-  run_tiles<M, K, BC>(sx, sc, a.n_firings * a.tiles_per_firing, src);
+  run_tiles<M, K, BC, MASKED>(sx, sc, a.n_firings * a.tiles_per_firing, src);
   if (!a.ticket) return;
   // The last workgroup to finish commits the batch: every other workgroup
   // has read the channel indices by then (it read them before finishing),
@@ -195,7 +213,7 @@ __global__ __launch_bounds__(256) void k_dpd_tiled(DpdArgs a) {
   }
 }
 
-template <int M, int K, int BC>
+template <int M, int K, int BC, bool MASKED>
 static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile, const KTiming *t) {
   DpdArgs a = a0;
   a.tile = tile;
@@ -204,13 +222,13 @@ static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile, const
   const size_t lds = (size_t)(lds_window(tile + M - 1) + lds_corr(M)) * sizeof(float2);
   const int64_t items = a.n_firings * a.tiles_per_firing;
   if (items <= 0) return hipSuccess;
-  const int64_t resident = resident_blocks((const void *)k_dpd_tiled<M, K, BC>, threads, lds);
+  const int64_t resident = resident_blocks((const void *)k_dpd_tiled<M, K, BC, MASKED>, threads, lds);
   const int64_t blocks = items < resident ? items : resident;
   if (t)
-    hipExtLaunchKernelGGL((k_dpd_tiled<M, K, BC>), dim3((unsigned)blocks), dim3(threads), lds, s, t->start, t->stop,
+    hipExtLaunchKernelGGL((k_dpd_tiled<M, K, BC, MASKED>), dim3((unsigned)blocks), dim3(threads), lds, s, t->start, t->stop,
                           0, a);
   else
-    hipLaunchKernelGGL((k_dpd_tiled<M, K, BC>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_dpd_tiled<M, K, BC, MASKED>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -220,7 +238,7 @@ hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s) {
   if (a.n_firings <= 0 || !dpd_tiled_shape(a.M)) return hipSuccess;
   if (!a.corr) return hipErrorInvalidValue;
   if (a.grp && (a.seg_firings != a.n_firings || !a.tab_prev)) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((a.n_firings + 15) / 16));
+  const dim3 grid((unsigned)((a.n_firings + 3) / 4));
 #define DF_HEADS(m)                                                                     \
   if (a.M == m) {                                                                       \
     if (a.grp)                                                                          \
@@ -254,9 +272,13 @@ hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int output
   tl = (tl / (64 * K)) * (64 * K);
   if (tl < 64 * K) tl = 64 * K;
   if (tl / K > 256) tl = 256 * K;
+  // compiled paths: Horner lengths up to 10 or up to 16; branch sets that are
+  // not prefixes (bit-mask tokens) take the masked paths up to 16
   const bool small = a.B_max <= 10;
 #define DF_TILED(m, k)                                                                      \
-  if (a.M == m && K == k) return small ? launch_tiled<m, k, 10>(a, s, tl, t) : launch_tiled<m, k, 16>(a, s, tl, t);
+  if (a.M == m && K == k)                                                                   \
+    return a.masked ? launch_tiled<m, k, 16, true>(a, s, tl, t)                             \
+                    : (small ? launch_tiled<m, k, 10, false>(a, s, tl, t) : launch_tiled<m, k, 16, false>(a, s, tl, t));
   DF_TILED(16, 4) DF_TILED(16, 8) DF_TILED(8, 4) DF_TILED(8, 8) DF_TILED(4, 4) DF_TILED(4, 8)
 #undef DF_TILED
   return hipErrorInvalidValue;

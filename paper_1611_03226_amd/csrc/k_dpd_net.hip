@@ -2,7 +2,8 @@
 // actor P feeding one channel per branch, one FIR actor per branch, and an
 // Adder A, each a kernel over a whole batch, with the branch channels
 // materialised in device memory at the dynamic rates the control tokens set
-// (branch b receives a firing's r samples only when b < B of that firing).
+// (branch b receives a firing's r samples only when b is in the firing's
+// branch set: b < B for a count token, bit b for a mask token).
 // Offsets into the branch channels come from the offset scan (k_scan
 // tables, or k_mask_tables for bit-mask control tokens, which activate any
 // set of branches).  This is the unfused counterpart of the fused body in
@@ -18,9 +19,9 @@ namespace {
 
 constexpr int kNetThreads = 256;
 
-__device__ inline bool active(int token, int b, int mask_mode) {
-  return mask_mode ? ((token >> b) & 1) != 0 : b < token;
-}
+// The tables hold validated branch sets (from the offset scan, or from
+// k_mask_tables for mask tokens).
+__device__ inline bool active(int set, int b) { return in_set((uint32_t)set, b); }
 
 __device__ inline float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
@@ -38,9 +39,9 @@ __global__ __launch_bounds__(kNetThreads) void k_net_poly(DpdNetArgs a) {
   const float2 x = a.x[t];
   const float p = fmaf(x.x, x.x, x.y * x.y);
   float2 v = x;
-  const int n_b = a.mask_mode ? a.B_max : Bg;
+  const int n_b = a.B_max;
   for (int b = 0; b < n_b; ++b) {
-    if (active(Bg, b, a.mask_mode)) a.chan[(b * a.S + s) * row_len + a.off[b * a.stride + gg] + i] = v;
+    if (active(Bg, b)) a.chan[(b * a.S + s) * row_len + a.off[b * a.stride + gg] + i] = v;
     v = make_float2(v.x * p, v.y * p);
   }
 }
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(kNetThreads) void k_net_fir(DpdNetArgs a) {
   const int b = (int)(bs / a.S);
   const int64_t s = bs - (int64_t)b * a.S;
   const int64_t g_last = s * a.nf + a.nf - 1;
-  const int64_t K = a.off[b * a.stride + g_last] + (active(a.B[g_last], b, a.mask_mode) ? a.r : 0);
+  const int64_t K = a.off[b * a.stride + g_last] + (active(a.B[g_last], b) ? a.r : 0);
   if (t >= K) return;
   const float2 *c = a.chan + bs * row_len;
   const float2 *hb = a.h + (int64_t)b * a.M;
@@ -78,9 +79,9 @@ __global__ __launch_bounds__(kNetThreads) void k_net_add(DpdNetArgs a) {
   const int64_t gg = s * a.nf + g;
   const int Bg = a.B[gg];
   float2 acc = make_float2(0.f, 0.f);
-  const int n_b = a.mask_mode ? a.B_max : Bg;
+  const int n_b = a.B_max;
   for (int b = 0; b < n_b; ++b) {
-    if (!active(Bg, b, a.mask_mode)) continue;
+    if (!active(Bg, b)) continue;
     const float2 v = a.firo[(b * a.S + s) * row_len + a.off[b * a.stride + gg] + i];
     acc.x += v.x;
     acc.y += v.y;

@@ -3,11 +3,14 @@
 // Sec. 2.2: a dynamic actor first consumes one control token, which fixes
 // the rate (0 or r) of each regular port for that firing.  For the
 // predistortion actor the token B activates branches b < B.  From the
-// per-firing rates this pass derives, for every branch b:
+// per-firing rates this pass derives, for every branch b (a mask token
+// activates the branches of its set bits instead; the kernels carry every
+// token as its branch set):
 //   off_b(j)  = r * #{i < j : firing i feeds branch b}   (exclusive sum)
 //   prev_b(j) = max{i < j : firing i feeds branch b}     (exclusive max, -1 none)
 //   last_b    = max{i < n : firing i feeds branch b}
-// where "feeds" is B_i > b (branch history) or always (shared history).
+// where "feeds" is "b active in firing i" (branch history) or always
+// (shared history).
 //
 // Two kernels.  k_scan: one workgroup per segment of firings; a pass
 // covers kScanChunks firings per thread (all control loads in flight at
@@ -36,7 +39,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
   __shared__ int tot[kScanChunks * kScanWaves][kMaxBranches], lst[kScanChunks * kScanWaves][kMaxBranches];
   __shared__ int pass_cnt[kMaxBranches], pass_last[kMaxBranches];
   __shared__ int64_t carry_cnt[kMaxBranches], carry_last[kMaxBranches];
-  __shared__ int hist[kMaxBranches + 1], cursor[kMaxBranches + 1];
+  __shared__ int tab[kScanChunks * kScanWaves][kMaxBranches + 1], pre[kScanChunks * kScanWaves][kMaxBranches + 1];
+  __shared__ int cursor[kMaxBranches + 1], run[kMaxBranches + 1], pass_tot[kMaxBranches + 1];
   const int seg = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nw = blockDim.x >> 6;
@@ -45,7 +49,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
   const int64_t gps = (a.seg_firings + 63) / 64;     // groups per segment
   const int E = kScanChunks * nw;                    // groups per pass
   if (tid < a.B_max) carry_cnt[tid] = 0, carry_last[tid] = -1;
-  if (tid <= kMaxBranches) hist[tid] = 0;
   const int64_t per_pass = (int64_t)kScanChunks * blockDim.x;
   int Bv[kScanChunks];
   for (int64_t p0 = 0; p0 < a.seg_firings; p0 += per_pass) {
@@ -54,11 +57,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
       const int64_t j = p0 + (int64_t)c * blockDim.x + tid;   // segment-local firing
       int v = 0;
       if (j < a.seg_firings) {
-        v = a.ctrl[(R + g0 + j) & a.ctrl_mask];
-        if (v < 0 || v > a.B_max) {
-          if (a.err) atomicOr(a.err, (int32_t)kErrControl);
-          v = 0;
-        }
+        bool bad;
+        v = (int)token_set(a.ctrl[(R + g0 + j) & a.ctrl_mask], a.ctrl_mode, a.B_max, &bad);
+        if (bad && a.err) atomicOr(a.err, (int32_t)kErrControl);
       }
       Bv[c] = v;
     }
@@ -66,10 +67,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
 #pragma unroll
     for (int c = 0; c < kScanChunks; ++c) {
       const int64_t j = p0 + (int64_t)c * blockDim.x + tid;
-      if (j < a.seg_firings) {
-        a.B_out[g0 + j] = Bv[c];
-        if (a.order_out) atomicAdd(&hist[Bv[c]], 1);
-      }
+      if (j < a.seg_firings) a.B_out[g0 + j] = Bv[c];
     }
     // A: group counts and last feeders (pass-local index); row c*nw + wave
     // is the 64-firing group starting at p0 + c*blockDim + 64*wave
@@ -77,7 +75,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
     for (int c = 0; c < kScanChunks; ++c) {
       const bool in = p0 + (int64_t)c * blockDim.x + tid < a.seg_firings;
       for (int b = 0; b < a.B_max; ++b) {
-        const uint64_t bal = __ballot(in && (a.hist_mode == 1 || Bv[c] > b));
+        const uint64_t bal = __ballot(in && (a.hist_mode == 1 || in_set((uint32_t)Bv[c], b)));
         if (lane == 0) {
           tot[c * nw + wave][b] = __popcll(bal);
           lst[c * nw + wave][b] = bal ? c * (int)blockDim.x + 64 * wave + 63 - __clzll((long long)bal) : -1;
@@ -121,32 +119,95 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
   if (tid < a.B_max && a.last_out)
     a.last_out[(int64_t)seg * a.B_max + tid] = carry_last[tid] >= 0 ? g0 + carry_last[tid] : -1;
   if (!a.order_out) return;
-  // group by B, largest first: cursors from the histogram, then scatter
-  if (tid == 0) {
-    int run = 0;
-    for (int v = a.B_max; v >= 0; --v) {
-      cursor[v] = run;
-      run += hist[v];
-    }
-  }
-  __syncthreads();
-  if (a.seg_firings <= per_pass) {                   // one pass: the tokens are still in registers
+  // Group the firings by Horner length (largest first), in firing order
+  // inside a length, with no atomics and no serial loops: the segment is
+  // taken in passes of kScanChunks*blockDim firings (64 chunks of 64); per
+  // chunk one ballot per length gives its count (LDS table) and each lane's
+  // rank inside the chunk; wavefront v scans column v of the table over the
+  // 64 chunks with lane shuffles.  Pass A only totals the lengths (to place
+  // each length's run); pass B places the firings.
+  const int NV = a.B_max + 1;                        // lengths 0..B_max
+  const int E2 = kScanChunks * nw;                   // chunks per pass (64: one per lane)
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  // a segment of one pass still holds its tokens in registers
+  const bool in_regs = a.seg_firings <= per_pass;
+  auto sets_of = [&](int64_t p0, int (&S)[kScanChunks]) {
 #pragma unroll
     for (int c = 0; c < kScanChunks; ++c) {
-      const int64_t j = (int64_t)c * blockDim.x + tid;
-      if (j < a.seg_firings) {
-        const int k = atomicAdd(&cursor[Bv[c]], 1);
-        a.order_out[2 * k] = (int32_t)j;
-        a.order_out[2 * k + 1] = Bv[c];
-      }
+      const int64_t j = p0 + (int64_t)c * blockDim.x + tid;
+      S[c] = j >= a.seg_firings ? -1 : (in_regs ? Bv[c] : a.B_out[g0 + j]);
     }
-    return;
+  };
+  // chunk counts of one pass into tab[chunk][v]; ranks of this thread's firings
+  auto count_pass = [&](const int (&S)[kScanChunks], int (&rank)[kScanChunks]) {
+#pragma unroll
+    for (int c = 0; c < kScanChunks; ++c) {
+      const int L = S[c] >= 0 ? set_len((uint32_t)S[c]) : -1;
+      int cnt = 0;
+      rank[c] = 0;
+      for (int v = 0; v < NV; ++v) {
+        const uint64_t bal = __ballot(L == v);
+        if (L == v) rank[c] = __popcll(bal & below);
+        if (lane == v) cnt = __popcll(bal);
+      }
+      if (lane < NV) tab[c * nw + wave][lane] = cnt;
+    }
+  };
+  // column scans: pre[chunk][v] = count of length v in earlier chunks of the
+  // pass, pass_tot[v] = the pass's count of length v
+  auto scan_columns = [&]() {
+    for (int v = wave; v < NV; v += nw) {
+      const int x = lane < E2 ? tab[lane][v] : 0;
+      int sc = x;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(sc, o);
+        if (lane >= o) sc += t;
+      }
+      if (lane < E2) pre[lane][v] = sc - x;
+      if (lane == 63) pass_tot[v] = sc;
+    }
+  };
+  int S[kScanChunks], rank[kScanChunks];
+  if (tid <= kMaxBranches) run[tid] = 0;             // pass A: totals per length
+  for (int64_t p0 = 0; p0 < a.seg_firings; p0 += per_pass) {
+    sets_of(p0, S);
+    count_pass(S, rank);
+    __syncthreads();
+    scan_columns();
+    __syncthreads();
+    if (tid < NV) run[tid] += pass_tot[tid];
+    __syncthreads();
   }
-  for (int64_t j = tid; j < a.seg_firings; j += blockDim.x) {
-    const int v = a.B_out[g0 + j];
-    const int k = atomicAdd(&cursor[v], 1);
-    a.order_out[2 * k] = (int32_t)j;
-    a.order_out[2 * k + 1] = v;
+  if (wave == 0) {                                   // cursor[v]: first slot of length v, longest first
+    const int t = lane < NV ? run[lane] : 0;
+    int sc = t;                                      // inclusive scan from the top length down
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_down(sc, o);
+      if (lane + o < 64) sc += u;
+    }
+    if (lane < NV) cursor[lane] = sc - t;
+  }
+  __syncthreads();
+  if (tid < NV) run[tid] = cursor[tid];              // pass B: place
+  for (int64_t p0 = 0; p0 < a.seg_firings; p0 += per_pass) {
+    sets_of(p0, S);
+    count_pass(S, rank);
+    __syncthreads();
+    scan_columns();
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kScanChunks; ++c) {
+      if (S[c] < 0) continue;
+      const int L = set_len((uint32_t)S[c]);
+      const int k = run[L] + pre[c * nw + wave][L] + rank[c];
+      a.order_out[2 * k] = (int32_t)(p0 + (int64_t)c * blockDim.x + tid);
+      a.order_out[2 * k + 1] = S[c];
+    }
+    __syncthreads();
+    if (tid < NV) run[tid] += pass_tot[tid];
+    __syncthreads();
   }
 }
 
@@ -163,7 +224,7 @@ __global__ __launch_bounds__(256) void k_scan_tables(ScanArgs a, int64_t n_group
   const int Bv = in ? a.B_out[g0 + j] : 0;
   const uint64_t below_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
   for (int b = 0; b < a.B_max; ++b) {
-    const uint64_t bal = __ballot(in && (a.hist_mode == 1 || Bv > b));
+    const uint64_t bal = __ballot(in && (a.hist_mode == 1 || in_set((uint32_t)Bv, b)));
     const uint64_t below = bal & below_mask;
     const int64_t gi = G * a.B_max + b;
     const int64_t cnt = a.grp[2 * gi] + __popcll(below);

@@ -42,7 +42,7 @@ struct InstDesc {
   int32_t B_max;
   int32_t hist_mode;
   int32_t tpf;            // tiles per firing
-  int32_t pad;
+  int32_t ctrl_mode;      // kCtrlCount or kCtrlMask
 };
 
 // Work-item descriptor (what the body needs about one tile).
@@ -53,7 +53,9 @@ struct PItem {
   const float2 *corr;     // head corrections of the firing [M-1]
   int64_t x_mask, y_mask;
   int64_t xb, yb;         // ring positions of the firing's first input / output sample
-  int32_t t0, nout, B, head;
+  int32_t t0, nout;
+  uint32_t set;           // the firing's branch set
+  int32_t head;
 };
 
 static_assert(sizeof(PItem) % 4 == 0 && sizeof(PItem) / 4 <= 64, "descriptor fits one register");
@@ -77,6 +79,7 @@ struct PersArgs {
   int32_t M;
   int32_t *err;
   int32_t tile;
+  int32_t masked;         // some instance reads bit-mask control tokens
 };
 
 // One wavefront: exclusive scans of the firing counts (firing bases) and of
@@ -107,8 +110,9 @@ __global__ __launch_bounds__(64) void k_pers_prep(PersArgs a) {
   }
 }
 
-// Processing order of the instances, grouped by the branch count of their
-// first firing (largest first), and the work-item bases in that order.  The
+// Processing order of the instances, grouped by the Horner length of their
+// first firing's branch set (largest first), and the work-item bases in that
+// order.  The
 // body compiles one unrolled code path per branch count; grouping keeps the
 // workgroups resident on a compute unit on few paths (instruction cache).
 // The order never changes a result.
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(1024) void k_pers_order(PersArgs a) {
   __shared__ int64_t wsum[16];
   if (threadIdx.x <= kMaxBranches) hist[threadIdx.x] = 0;
   __syncthreads();
-  auto key = [&](int i) { return a.n_fire[i] > 0 ? a.B_all[a.fire_base[i]] : 0; };
+  auto key = [&](int i) { return a.n_fire[i] > 0 ? set_len((uint32_t)a.B_all[a.fire_base[i]]) : 0; };
   for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) atomicAdd(&hist[key(i)], 1);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -175,17 +179,14 @@ __global__ __launch_bounds__(1024) void k_pers_scan(PersArgs a) {
   for (int64_t c = 0; c < n; c += 64) {
     const int64_t j = c + lane;
     const bool in = j < n;
-    int32_t B = 0;
+    uint32_t set = 0u;
     if (in) {
-      int32_t v = d.ctrl[(R + j) & d.ctrl_mask];
-      if (v < 0 || v > d.B_max) {
-        if (b == 0) atomicOr(a.err, (int32_t)kErrControl);
-        v = 0;
-      }
-      B = v;
-      if (b == 0) a.B_all[base + j] = B;
+      bool bad;
+      set = token_set(d.ctrl[(R + j) & d.ctrl_mask], d.ctrl_mode, d.B_max, &bad);
+      if (bad && b == 0) atomicOr(a.err, (int32_t)kErrControl);
+      if (b == 0) a.B_all[base + j] = (int32_t)set;
     }
-    const bool fed = in && (d.hist_mode == 1 || B > b);
+    const bool fed = in && (d.hist_mode == 1 || in_set(set, b));
     const uint64_t bal = __ballot(fed);
     const uint64_t below = bal & below_mask;
     if (in) a.prev_all[(int64_t)b * a.cap + base + j] = below ? (c + 63 - __clzll((long long)below)) : lastw;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(256) void k_pers_items(PersArgs a) {
     const int64_t j = local / d.tpf;
     const int64_t t0 = (local - j * d.tpf) * a.tile;
     const int64_t gf = a.fire_base[i] + j;
-    const int B = a.B_all[gf];
+    const uint32_t set = (uint32_t)a.B_all[gf];
     const int64_t Rx = d.x_idx[0];
     PItem p;
     p.x = d.x;
@@ -225,8 +226,8 @@ __global__ __launch_bounds__(256) void k_pers_items(PersArgs a) {
     p.yb = d.y_idx[1] + j * d.r;
     p.t0 = (int32_t)t0;
     p.nout = (int32_t)min((int64_t)a.tile, d.r - t0);
-    p.B = B;
-    p.head = (t0 == 0 && B > 0) ? 1 : 0;
+    p.set = set;
+    p.head = (t0 == 0 && set != 0u) ? 1 : 0;
     a.items[it] = p;
   }
 }
@@ -250,17 +251,31 @@ struct ItemSrc {
     j.yb = (int64_t)qword_at(dv, offsetof(PItem, yb) / 4);
     j.t0 = (int)dword_at(dv, offsetof(PItem, t0) / 4);
     j.nout = (int)dword_at(dv, offsetof(PItem, nout) / 4);
-    j.B = (int)dword_at(dv, offsetof(PItem, B) / 4);
+    j.set = dword_at(dv, offsetof(PItem, set) / 4);
+    j.B = set_len(j.set);
     j.head = (int)dword_at(dv, offsetof(PItem, head) / 4);
   }
 };
 
 // Head corrections of all instances' firings: one wavefront per four
-// consecutive firings of one instance (rows), from the head-pass map.
+// consecutive firings of one instance (rows), from the head-pass map.  The
+// number of such wavefronts is read from the device (head_base[n_inst],
+// written by k_pers_prep), and a fixed grid walks them with a stride, so
+// the launch does not depend on the batch's firing counts.
 template <int M>
-__global__ __launch_bounds__(256) void k_pers_heads(PersArgs a, int64_t n_heads) {
-  const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (w >= n_heads) return;                          // uniform per wavefront
+__device__ __forceinline__ void pers_head(const PersArgs &a, int64_t w);
+
+template <int M>
+__global__ __launch_bounds__(256) void k_pers_heads(PersArgs a) {
+  const int64_t n_heads = as_const(a.head_base)[a.n_inst];
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  for (int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); w < n_heads;
+       w += stride)                                   // uniform per wavefront
+    pers_head<M>(a, w);
+}
+
+template <int M>
+__device__ __forceinline__ void pers_head(const PersArgs &a, int64_t w) {
   const int i = as_const(a.head_inst)[w];
   const auto *inst = as_const(a.inst) + i;
   const int64_t j0 = 4 * (w - as_const(a.head_base)[i]);
@@ -270,23 +285,31 @@ __global__ __launch_bounds__(256) void k_pers_heads(PersArgs a, int64_t n_heads)
   const float2 *hist = inst->hist;
   const int64_t x_mask = inst->x_mask, r = inst->r;
   const int64_t Rx = as_const(inst->x_idx)[0];
+  const auto B_of = [&](int row) { return j0 + row < nf ? (uint32_t)a.B_all[f0 + row] : 0u; };
+  float cr = 0.f, ci = 0.f;
   head_correction<M, 4>(
-      as_const(inst->h), [&](int row) { return j0 + row < nf ? a.B_all[f0 + row] : 0; },
-      [&](int row, int b) { return a.prev_all[(int64_t)b * a.cap + f0 + row]; },
+      as_const(inst->h), B_of, [&](int row, int b) { return a.prev_all[(int64_t)b * a.cap + f0 + row]; },
       [&](int, int b, int64_t pf, int q) {
         if (pf >= 0) return x[(Rx + pf * r + r - (M - 1) + q) & x_mask];
         return hist[b * (M - 1) + q];
       },
-      [&](int row) { return a.corr_all + (f0 + row) * (M - 1); });
+      0, 1, [&](int, bool on, float sr, float si) {
+        if (on) {
+          cr += sr;
+          ci += si;
+        }
+      });
+  const int lane = threadIdx.x & 63, row = lane >> 4, q = lane & 15;
+  if (head_live<M, 4>(B_of(row))) a.corr_all[(f0 + row) * (M - 1) + q] = make_float2(cr, ci);
 }
 
 // Persistent body: a grid-stride walk over the work items (run_tiles).
-template <int M, int K, int BC>
+template <int M, int K, int BC, bool MASKED>
 __global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
   extern __shared__ float2 lds[];   // [M-1] head corrections, window
   float2 *sc = lds, *sx = sc + lds_corr(M);
   ItemSrc src{a};
-  run_tiles<M, K, BC>(sx, sc, as_const(a.tile_base)[a.n_inst], src);
+  run_tiles<M, K, BC, MASKED>(sx, sc, as_const(a.tile_base)[a.n_inst], src);
 }
 
 __global__ __launch_bounds__(256) void k_pers_commit(PersArgs a, int M) {
@@ -328,6 +351,7 @@ struct Persistent {
   int64_t *head_base = nullptr;
   int32_t *head_inst = nullptr;
   int64_t cap = 0, items_cap = 0, heads_cap = 0, n_heads = 0;
+  int64_t captures = 0;   // graph captures so far (diagnostics)
   int tile = 0, K = 0, bpc = 0, ncu = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -362,13 +386,13 @@ void destroy_persistent(df_graph *g) {
   g->pers = nullptr;
 }
 
-template <int M, int K, int BC>
+template <int M, int K, int BC, bool MASKED>
 static hipError_t launch_pers_body(const PersArgs &a, int threads, int blocks, hipStream_t s, const KTiming *t) {
   const size_t lds = (size_t)(lds_window(a.tile + M - 1) + lds_corr(M)) * sizeof(float2);
   if (t)
-    hipExtLaunchKernelGGL((k_pers_body<M, K, BC>), dim3(blocks), dim3(threads), lds, s, t->start, t->stop, 0, a);
+    hipExtLaunchKernelGGL((k_pers_body<M, K, BC, MASKED>), dim3(blocks), dim3(threads), lds, s, t->start, t->stop, 0, a);
   else
-    hipLaunchKernelGGL((k_pers_body<M, K, BC>), dim3(blocks), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_pers_body<M, K, BC, MASKED>), dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -378,12 +402,14 @@ static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pers_scan, dim3(a.n_inst), dim3(64 * a.Bg), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int64_t nh = p->n_heads;
-  if (nh > 0) {
-    const dim3 hg((unsigned)((nh + 3) / 4));
-    if (p->M == 16) hipLaunchKernelGGL(k_pers_heads<16>, hg, dim3(256), 0, s, a, nh);
-    else if (p->M == 8) hipLaunchKernelGGL(k_pers_heads<8>, hg, dim3(256), 0, s, a, nh);
-    else hipLaunchKernelGGL(k_pers_heads<4>, hg, dim3(256), 0, s, a, nh);
+  {
+    // a grid that covers the head-pass capacity in one sweep, at most a few
+    // workgroups per compute unit (the kernel strides over the device count)
+    const int64_t want = (p->heads_cap + 3) / 4;
+    const dim3 hg((unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 8 * p->ncu)));
+    if (p->M == 16) hipLaunchKernelGGL(k_pers_heads<16>, hg, dim3(256), 0, s, a);
+    else if (p->M == 8) hipLaunchKernelGGL(k_pers_heads<8>, hg, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_pers_heads<4>, hg, dim3(256), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_pers_order, dim3(1), dim3(1024), 0, s, a);
@@ -398,7 +424,9 @@ static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s,
   const bool small = a.Bg <= 10;
 #define DF_PERS(m, k)                                                                              \
   if (p->M == m && p->K == k)                                                                      \
-    e = small ? launch_pers_body<m, k, 10>(a, threads, blocks, s, tp) : launch_pers_body<m, k, 16>(a, threads, blocks, s, tp); \
+    e = a.masked ? launch_pers_body<m, k, 16, true>(a, threads, blocks, s, tp)                    \
+        : (small ? launch_pers_body<m, k, 10, false>(a, threads, blocks, s, tp)                    \
+                 : launch_pers_body<m, k, 16, false>(a, threads, blocks, s, tp));               \
   else
   DF_PERS(16, 4) DF_PERS(16, 8) DF_PERS(8, 4) DF_PERS(8, 8) DF_PERS(4, 4) DF_PERS(4, 8)
   return hipErrorInvalidValue;
@@ -560,6 +588,7 @@ static df_status fire_many(df_graph *g, int32_t n_actors, const int32_t *actors,
       d.r = a.dp.firing_size;
       d.B_max = a.dp.n_branches_max;
       d.hist_mode = a.dp.history_mode;
+      d.ctrl_mode = a.dp.control_mode;
       d.tpf = (int32_t)((d.r + tile - 1) / tile);
       desc[i] = d;
     }
@@ -567,12 +596,11 @@ static df_status fire_many(df_graph *g, int32_t n_actors, const int32_t *actors,
     p->n_host.clear();
   }
   if (p->n_host.size() != (size_t)n_actors || !std::equal(p->n_host.begin(), p->n_host.end(), n_firings)) {
-    // Counts changed: upload synchronously (the batch shape is normally
-    // stable); the head pass grid depends on the total, so a captured graph
-    // is rebuilt.
-    HIPCHK(g, hipStreamSynchronize(g->stream));
-    drop_graph(p);
-    HIPCHK(g, hipMemcpy(p->n_dev, n_firings, sizeof(int64_t) * n_actors, hipMemcpyHostToDevice));
+    // Counts changed: every kernel of the chain reads them from the device
+    // (grids are sized by the capacities above), so a stream-ordered upload
+    // is all it takes; a captured graph stays valid.  The copy is from
+    // pageable memory, so n_firings may be reused once this call returns.
+    HIPCHK(g, hipMemcpyAsync(p->n_dev, n_firings, sizeof(int64_t) * n_actors, hipMemcpyHostToDevice, g->stream));
     p->n_host.assign(n_firings, n_firings + n_actors);
     p->n_heads = n_heads;
   }
@@ -595,6 +623,9 @@ static df_status fire_many(df_graph *g, int32_t n_actors, const int32_t *actors,
   pa.inst_order = p->inst_order;
   pa.err = g->err_dev;
   pa.tile = p->tile;
+  pa.masked = 0;
+  for (int i = 0; i < n_actors; ++i)
+    if (g->actors[actors[i]].dp.control_mode == DF_CTRL_MASK) pa.masked = 1;
   if (flags & DF_FIRE_GRAPH) {
     if (!p->exec) {
       HIPCHK(g, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -605,6 +636,8 @@ static df_status fire_many(df_graph *g, int32_t n_actors, const int32_t *actors,
       if (e2 != hipSuccess) return fail_hip(g, e2, "hipStreamEndCapture");
       p->graph = graph;
       HIPCHK(g, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+      ++p->captures;
+      dlog(g, 1, "persistent chain captured (capture %lld)", (long long)p->captures);
     }
     HIPCHK(g, prof_begin(g));
     HIPCHK(g, hipGraphLaunch(p->exec, g->stream));

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -14,6 +15,7 @@
 
 #include "common.h"
 #include "dfhip.h"
+#include "host_logic.h"
 #include "runtime.h"
 
 using namespace dfh;
@@ -52,10 +54,14 @@ df_status dfh::fail_hip(df_graph *g, hipError_t e, const char *what) {
     if (e0_ != hipSuccess) return fail_hip((g), e0_, "hipSetDevice");     \
   } while (0)
 
-static int64_t next_pow2(int64_t v) {
-  int64_t p = 1;
-  while (p < v) p <<= 1;
-  return p;
+using host::next_pow2;
+
+static host::SlotMap slot_map(const Fifo &f) {
+  host::SlotMap m;
+  m.cap = f.cap;
+  m.period = f.period;
+  m.delay = f.n_initial != 0;
+  return m;
 }
 
 static int64_t dtype_bytes(int dt) {
@@ -322,8 +328,14 @@ extern "C" df_status df_actor_create(df_graph *g, df_actor_kind kind, const void
   a.kind = kind;
   hipError_t e;
   if (kind == DF_ACTOR_DPD) {
-    if (params_size != sizeof(df_dpd_params)) return fail(g, DF_EINVAL, "df_actor_create: params_size mismatch");
-    const df_dpd_params &p = *(const df_dpd_params *)params;
+    // the struct without control_mode / reserved is accepted too (count tokens)
+    const size_t short_size = offsetof(df_dpd_params, control_mode);
+    if (params_size != sizeof(df_dpd_params) && params_size != short_size)
+      return fail(g, DF_EINVAL, "df_actor_create: params_size mismatch");
+    df_dpd_params p{};
+    memcpy(&p, params, params_size);
+    if (p.control_mode != DF_CTRL_COUNT && p.control_mode != DF_CTRL_MASK)
+      return fail(g, DF_EINVAL, "bad control_mode %d", p.control_mode);
     if (p.n_branches_max < 1 || p.n_branches_max > kMaxBranches)
       return fail(g, DF_EINVAL, "n_branches_max %d outside 1..%d", p.n_branches_max, kMaxBranches);
     if (p.n_taps < 1 || p.n_taps > kMaxTaps) return fail(g, DF_EINVAL, "n_taps %d outside 1..%d", p.n_taps, kMaxTaps);
@@ -478,20 +490,16 @@ static hipError_t ring_copy(df_graph *g, Fifo &f, int64_t pos, void *flat, int64
                             bool flat_on_device, hipStream_t st = nullptr) {
   if (!st) st = g->stream;
   const size_t tb = (size_t)f.token_bytes;
-  const int64_t map = chan_map(f);
-  // exclusive end of the slots a run may cover before the pattern wraps
-  const int64_t end = !f.period ? f.cap : (to_ring && f.n_initial ? f.period + 1 : f.period);
+  const host::SlotMap m = slot_map(f);
   hipMemcpyKind kind = to_ring ? (flat_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)
                                : (flat_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
   char *p = (char *)flat;
   for (int64_t done = 0; done < n;) {
-    const int64_t q = pos + done;
-    const int64_t slot = to_ring ? write_slot(q, map) : read_slot(q, map);
-    const int64_t run = std::min(n - done, end - slot);
-    hipError_t e = to_ring ? hipMemcpyAsync(f.ring + slot * tb, p + done * tb, run * tb, kind, st)
-                           : hipMemcpyAsync(p + done * tb, f.ring + slot * tb, run * tb, kind, st);
+    const host::Run run = host::next_run(m, pos + done, n - done, to_ring);
+    hipError_t e = to_ring ? hipMemcpyAsync(f.ring + run.slot * tb, p + done * tb, run.count * tb, kind, st)
+                           : hipMemcpyAsync(p + done * tb, f.ring + run.slot * tb, run.count * tb, kind, st);
     if (e != hipSuccess) return e;
-    done += run;
+    done += run.count;
   }
   return hipSuccess;
 }
@@ -500,12 +508,10 @@ static hipError_t ring_copy(df_graph *g, Fifo &f, int64_t pos, void *flat, int64
 // copy slot P to slot 0 if one of them filled slot P (Sec. 3.2, Fig. 2).
 // Admission keeps n <= P, so at most one position of the batch lands there.
 static hipError_t paper_fixup(df_graph *g, const Fifo &f, int64_t pos, int64_t n) {
-  if (!f.period || !f.n_initial || n <= 0) return hipSuccess;
-  const int64_t P = f.period;
-  const int64_t first = pos + ((P - (pos % P)) % P);   // first position >= pos that is a multiple of P
-  if (first >= pos + n || first == 0) return hipSuccess;
+  if (!f.period || !f.n_initial) return hipSuccess;
+  if (host::fixup_position(pos, n, f.period) < 0) return hipSuccess;
   const size_t tb = (size_t)f.token_bytes;
-  return hipMemcpyAsync(f.ring, f.ring + P * tb, tb, hipMemcpyDeviceToDevice, g->stream);
+  return hipMemcpyAsync(f.ring, f.ring + f.period * tb, tb, hipMemcpyDeviceToDevice, g->stream);
 }
 
 extern "C" df_status df_push(df_graph *g, int32_t fifo, const void *src, int64_t n, int src_on_device) {
@@ -522,10 +528,11 @@ extern "C" df_status df_push(df_graph *g, int32_t fifo, const void *src, int64_t
   if (f.reader >= 0 && f.reader_port == DF_DPD_CTRL && g->actors[f.reader].kind == DF_ACTOR_DPD &&
       !src_on_device) {
     const int32_t *v = (const int32_t *)src;
-    const int32_t bm = g->actors[f.reader].dp.n_branches_max;
+    const df_dpd_params &dp = g->actors[f.reader].dp;
+    const int32_t hi = dp.control_mode == DF_CTRL_MASK ? (1 << dp.n_branches_max) - 1 : dp.n_branches_max;
     for (int64_t i = 0; i < n; ++i)
-      if (v[i] < 0 || v[i] > bm)
-        return fail(g, DF_EINVAL, "control token %d at %lld outside 0..%d", v[i], (long long)i, bm);
+      if (v[i] < 0 || v[i] > hi)
+        return fail(g, DF_EINVAL, "control token %d at %lld outside 0..%d", v[i], (long long)i, hi);
   }
   HIPCHK(g, ring_copy(g, f, f.write_hi, (void *)src, n, true, src_on_device != 0));
   HIPCHK(g, paper_fixup(g, f, f.write_hi, n));
@@ -629,6 +636,7 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   sa.n_segs = 1;
   sa.B_max = bm;
   sa.hist_mode = a.dp.history_mode;
+  sa.ctrl_mode = a.dp.control_mode;
   sa.B_out = a.B;
   sa.prev_out = a.prev;
   sa.off_out = a.off;
@@ -662,6 +670,7 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   da.B_max = bm;
   da.M = M;
   da.corr = a.corr;
+  da.masked = a.dp.control_mode == DF_CTRL_MASK;
   if (heads_tables) {
     da.grp = a.grp;
     da.tab_prev = a.prev;
@@ -1043,10 +1052,7 @@ extern "C" df_status df_stream_dpd(df_graph *g, int32_t actor, const void *x_hos
   char *yh = (char *)y_host;
   // the batch whose slots a write of positions up to `last` reuses: the one
   // holding position last - cap, if any (batches start at `base`, n apart)
-  auto reused = [](int64_t last, int64_t cap, int64_t base, int64_t n) -> int64_t {
-    const int64_t p = last - cap;
-    return p < base ? -1 : (p - base) / n;
-  };
+  const auto reused = host::reused_batch;
   // The copy streams carry copies only; every counter update runs on the
   // graph stream, after the copy it accounts for (a kernel on a copy stream
   // would share a hardware queue with the firings and serialise them).
@@ -1165,7 +1171,7 @@ extern "C" df_status df_debug_last_batch(df_graph *g, int32_t actor, int32_t *ra
     std::vector<int32_t> B(n);
     HIPCHK(g, hipMemcpy(B.data(), a.B, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
     for (int b = 0; b < bm; ++b)
-      for (int64_t j = 0; j < n; ++j) rates[b * cap + j] = b < B[j] ? (int32_t)a.dp.firing_size : 0;
+      for (int64_t j = 0; j < n; ++j) rates[b * cap + j] = in_set((uint32_t)B[j], b) ? (int32_t)a.dp.firing_size : 0;
   }
   for (int b = 0; b < bm; ++b) {
     if (offsets)

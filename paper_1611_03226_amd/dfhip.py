@@ -41,7 +41,8 @@ class DFError(RuntimeError):
 
 class DpdParams(C.Structure):
     _fields_ = [("n_branches_max", C.c_int32), ("n_taps", C.c_int32), ("firing_size", C.c_int64),
-                ("coeffs", C.c_void_p), ("coeffs_on_device", C.c_int32), ("history_mode", C.c_int32)]
+                ("coeffs", C.c_void_p), ("coeffs_on_device", C.c_int32), ("history_mode", C.c_int32),
+                ("control_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
 class MotionParams(C.Structure):

@@ -124,11 +124,16 @@ class Graph:
 
     # builders -------------------------------------------------------------
     def dpd_chain(self, h, r, n_delay=0, initial=None, history="branch", cap_x=0, cap_ctrl=0,
-                  cap_y=0) -> DPDChain:
+                  cap_y=0, control="count") -> DPDChain:
+        """A predistortion actor with its control, input and output channels;
+        control="mask" reads control tokens as bit masks of active branches."""
         h = np.ascontiguousarray(h, np.complex64)
         B, M = h.shape
+        if control not in ("count", "mask"):
+            raise ValueError(f"unknown control mode {control!r}")
         p = D.DpdParams(B, M, r, h.ctypes.data, 0,
-                        D.DF_HIST_SHARED if history == "shared" else D.DF_HIST_BRANCH)
+                        D.DF_HIST_SHARED if history == "shared" else D.DF_HIST_BRANCH,
+                        D.DF_CTRL_MASK if control == "mask" else D.DF_CTRL_COUNT, 0)
         a = D.df_actor_create(self.g, D.DF_ACTOR_DPD, p)
         fc = self.fifo(D.DF_I32, 1, cap_ctrl)
         fx = self.fifo(D.DF_C64, 1, cap_x, n_delay, initial)

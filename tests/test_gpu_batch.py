@@ -176,16 +176,19 @@ def test_fire_many_validation():
         assert G.status(a.ctrl)[:2] == (0, 2)
 
 
-def test_graph_replay_with_changing_firing_counts():
+def test_graph_replay_with_changing_firing_counts(monkeypatch, capfd):
     """Persistent graph mode when the firing counts change between batches
-    (the captured chain is rebuilt) equals per-actor launches bit for bit."""
+    equals per-actor launches bit for bit, and the chain is captured once:
+    the counts reach the replayed graph through device memory."""
     from paper_1611_03226_amd.graph import Graph
+    monkeypatch.setenv("DFHIP_LOG", "1")
     r = 256
     insts = _instances(62, 10, r, 5)
     rng = np.random.default_rng(3)
     plans = [[d["nf"] for d in insts], [max(1, d["nf"] - 1) for d in insts], [d["nf"] for d in insts]]
     plans[1][0] = 0                                   # one instance idle in the second batch
     outs = {}
+    capfd.readouterr()
     for mode in ("many", "graph"):
         say(f"batch changing counts {mode}")
         with Graph(0) as G:
@@ -206,6 +209,8 @@ def test_graph_replay_with_changing_firing_counts():
                     ys[i].append(y)
             G.sync()
         outs[mode] = [np.concatenate(v) for v in ys]
+    err = capfd.readouterr().err
+    assert err.count("persistent chain captured") == 1, err[-2000:]
     for a, b in zip(outs["many"], outs["graph"]):
         assert np.array_equal(a.view(np.float32), b.view(np.float32))
     for d, y in zip(insts, outs["graph"]):
