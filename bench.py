@@ -362,7 +362,7 @@ def bench_dpd_network(D, torch, steps=5, warmup=2):
                 parity="tests/test_gpu_dpd_network.py::test_scale_workload_sampled_and_against_fused_body")
 
 
-def bench_dpd_mask(D, Graph, torch, steps=10, warmup=2):
+def bench_dpd_mask(D, Graph, torch, steps=40, warmup=10):
     """The scale workload (2^24 samples, 4096 firings of 4096, B_max 10,
     M 16) with bit-mask control tokens: each firing's token an arbitrary
     set of active branches, uniform over the 1023 non-empty sets (seeded).
@@ -875,8 +875,8 @@ def summarize_kernel_stats(run, stats_csv):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only", default="", help="comma list of extras to run: chain,motion,md_paper,dpd_network,dpd_mask,host_io,instances,"

@@ -101,6 +101,32 @@ struct DpdCommitArgs {
   int32_t *err;           // sticky error word (ring invariant), may be nullptr
 };
 
+// Control intake + offset scan over segments of firings (one wavefront per
+// 64-firing group; the last group of a segment to finish scans the group
+// tables of its segment).
+struct ScanArgs {
+  const int32_t *ctrl;    // control tokens (ring or linear)
+  const int64_t *ctrl_idx;// device [read, write] or nullptr (position ctrl_pos)
+  int64_t ctrl_pos;       // read position when ctrl_idx is nullptr
+  int64_t ctrl_mask;      // ring mask, -1 for linear
+  int64_t seg_firings;    // firings per segment (< 2^31)
+  int32_t n_segs;
+  int32_t B_max;
+  int32_t hist_mode;      // 0 branch, 1 shared
+  int32_t ctrl_mode;      // kCtrlCount or kCtrlMask
+  int32_t *B_out;         // [n_segs*seg_firings] validated branch sets
+  int64_t *prev_out;      // [B_max][stride]
+  int64_t *off_out;       // [B_max][stride] (may be nullptr)
+  int64_t *last_out;      // [n_segs][B_max] (may be nullptr)
+  int64_t *grp;           // [scan_groups][B_max][2]: count and last feeder before each 64-firing group
+  int32_t *lgrp;          // [scan_groups][B_max+1] (one segment) or nullptr: first processing slot of
+                          // each Horner length in each group (firings grouped by length, longest first)
+  int32_t *ticket;        // [n_segs] finished groups per segment; zero between scans
+  int64_t stride;
+  int64_t r;
+  int32_t *err;           // sticky error word (may be nullptr)
+};
+
 struct DpdArgs {
   const float2 *x;
   const int64_t *x_idx;   // device [read, write] or nullptr (position 0)
@@ -121,41 +147,29 @@ struct DpdArgs {
   int32_t M;
   int32_t tile;           // outputs per workgroup (tiled kernel)
   int32_t tiles_per_firing;
-  const int32_t *order;   // processing order, pairs (firing, B) grouped by B, or nullptr
+  const int32_t *order;   // processing order, pairs (firing, branch set) grouped by Horner length, or nullptr
   float2 *corr;           // [n_firings][M-1] head corrections (tiled kernels)
   // With grp set (one segment), the head pass derives each firing's history
   // sources from the scan's group table and writes the prev/off tables itself.
   const int64_t *grp;     // [groups][B_max][2] from k_scan, or nullptr
   int64_t *tab_prev;      // [B_max][prev_stride]
   int64_t *tab_off;       // [B_max][prev_stride] or nullptr
+  // ... and, with order_out, places each firing in the processing order from
+  // the scan's length table
+  const int32_t *obase;   // ScanArgs::lgrp
+  int32_t *order_out;     // [n_firings][2] or nullptr
   int32_t hist_mode;
   int32_t masked;         // branch sets may be non-prefix (bit-mask control tokens)
   int32_t *ticket;        // tiled kernel: the last workgroup to finish runs `commit` (nullptr: none)
   DpdCommitArgs commit;
+  int32_t *err;           // sticky error word (head pass; may be nullptr)
+  int32_t *err_ahead;     // errors of a scan run ahead of this batch: the head pass adds them to err
+                          // and clears them (nullptr: none)
+  // The head pass with tables can also run the scan of the next batch
+  // (control tokens only): its first ahead_blocks workgroups do it.
+  ScanArgs ahead;
+  int32_t ahead_blocks;
 };
-
-// Control intake + offset scan over segments of firings (one workgroup per
-// segment, one wavefront per branch).
-struct ScanArgs {
-  const int32_t *ctrl;    // control tokens (ring or linear)
-  const int64_t *ctrl_idx;// device [read, write] or nullptr (position 0)
-  int64_t ctrl_mask;      // ring mask, -1 for linear
-  int64_t seg_firings;    // firings per segment
-  int32_t n_segs;
-  int32_t B_max;
-  int32_t hist_mode;      // 0 branch, 1 shared
-  int32_t ctrl_mode;      // kCtrlCount or kCtrlMask
-  int32_t *B_out;         // [n_segs*seg_firings] validated branch sets
-  int64_t *prev_out;      // [B_max][stride]
-  int64_t *off_out;       // [B_max][stride] (may be nullptr)
-  int64_t *last_out;      // [n_segs][B_max] (may be nullptr)
-  int32_t *order_out;     // [n][2] (firing, set) grouped by Horner length, largest first (one segment), or nullptr
-  int64_t *grp;           // [scan_groups][B_max][2] scratch: count and last feeder before each 64-firing group
-  int64_t stride;
-  int64_t r;
-  int32_t *err;           // sticky error word (may be nullptr)
-};
-
 
 // ---------------------------------------------------------------- motion
 struct MotionArgs {
@@ -207,7 +221,15 @@ int64_t resident_blocks(const void *kernel, int threads, size_t lds_bytes);
 
 // ---------------------------------------------------------------- launchers
 int64_t scan_groups(int64_t n_segs, int64_t seg_firings);   // 64-firing groups of a scan
-hipError_t launch_scan(const ScanArgs &a, hipStream_t s, bool tables = true);
+// Scratch of one scan in bytes: segment tickets (int32 [n_segs]), group
+// table (int64 [groups][B_max][2]), and for an ordered scan the length
+// table (int32 [groups][B_max+1]); scan_scratch_assign points the ScanArgs
+// fields into such a buffer (256-byte aligned regions, in that order).
+size_t scan_scratch_bytes(int64_t n_segs, int64_t seg_firings, int32_t B_max, bool ordered);
+void scan_scratch_assign(ScanArgs &a, void *scratch, bool ordered);
+// tables: also write prev/off (else the head pass does); zero_tickets: clear
+// the tickets first (a fill kernel) when the buffer is not known to be zero
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s, bool tables = true, bool zero_tickets = true);
 // Optional start/stop events of one kernel launch (timing rides on the
 // dispatch itself: hipExtLaunchKernel), or none.
 struct KTiming {

@@ -13,6 +13,7 @@
 
 #include "common.h"
 #include "dpd_tile.h"
+#include "scan_dev.h"
 
 namespace dfh {
 
@@ -91,7 +92,8 @@ __device__ __forceinline__ void dpd_commit_block(const DpdCommitArgs &a) {
 // table (one segment) the wavefront also derives the history sources of its
 // four firings and writes their prev/off table entries: the four firings lie
 // in one 64-firing group, so a ballot of the group's feed flags per branch
-// plus the group's entry (count and last feeder before it) gives them.
+// plus the group's entry (count and last feeder before it) gives them;
+// with order_out it also writes the four firings' processing slots.
 template <int M, bool TABLES>
 __global__ __launch_bounds__(256) void k_dpd_heads(DpdArgs a) {
   // The workgroup's four wavefronts share four firings; wavefront w takes
@@ -99,7 +101,22 @@ __global__ __launch_bounds__(256) void k_dpd_heads(DpdArgs a) {
   // serial work each); each branch's sum goes to LDS and one wavefront adds
   // them in increasing branch order, as a single pass would.
   __shared__ float2 part[kMaxBranches][64];
-  const int64_t g0 = (int64_t)blockIdx.x * 4;
+  if constexpr (TABLES) {
+    if ((int)blockIdx.x < a.ahead_blocks) {          // the next batch's scan (whole workgroups)
+      scan_dev::scan_group(a.ahead, (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                           (a.ahead.seg_firings + 63) / 64);
+      return;
+    }
+  }
+  const int64_t hb = (int64_t)blockIdx.x - a.ahead_blocks;
+  if (a.err_ahead && hb == 0 && threadIdx.x == 0) {
+    const int32_t e = *a.err_ahead;
+    if (e) {
+      if (a.err) atomicOr(a.err, e);
+      *a.err_ahead = 0;
+    }
+  }
+  const int64_t g0 = hb * 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t Rx = a.x_idx ? as_const(a.x_idx)[0] : 0;
   const int lane = threadIdx.x & 63, row = lane >> 4, i = lane & 15;
@@ -124,6 +141,25 @@ __global__ __launch_bounds__(256) void k_dpd_heads(DpdArgs a) {
         const int64_t o = (int64_t)b * a.prev_stride + g;
         a.tab_prev[o] = pf[b];
         if (a.tab_off) a.tab_off[o] = a.r * (cnt0 + __popcll(below));
+      }
+    }
+    if (a.order_out && w == 0) {
+      // processing slot of each of the four firings: its length's first
+      // slot in this group plus the firings of that length before it here
+      const int NV = a.B_max + 1;
+      const int Ll = gin ? set_len(Bl) : -1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int lq = (int)(g0 & 63) + q;            // group lane of firing g0 + q
+        if (g0 + q >= a.n_firings) break;             // uniform
+        const uint32_t Sq = (uint32_t)__builtin_amdgcn_readlane((int)Bl, lq);
+        const int Lq = set_len(Sq);
+        const uint64_t bal = __ballot(Ll == Lq);
+        if (lane == q) {
+          const int64_t k = as_const(a.obase)[G * NV + Lq] + __popcll(bal & ((1ull << lq) - 1));
+          a.order_out[2 * k] = (int32_t)(g0 + q);
+          a.order_out[2 * k + 1] = (int32_t)Sq;
+        }
       }
     }
   }
@@ -238,7 +274,10 @@ hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s) {
   if (a.n_firings <= 0 || !dpd_tiled_shape(a.M)) return hipSuccess;
   if (!a.corr) return hipErrorInvalidValue;
   if (a.grp && (a.seg_firings != a.n_firings || !a.tab_prev)) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((a.n_firings + 3) / 4));
+  if (a.ahead_blocks < 0 || (a.ahead_blocks && (!a.grp || a.ahead.n_segs != 1 || !a.ahead.grp || !a.ahead.ticket ||
+                                               a.ahead_blocks != (scan_groups(1, a.ahead.seg_firings) + 3) / 4)))
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((a.n_firings + 3) / 4 + a.ahead_blocks));
 #define DF_HEADS(m)                                                                     \
   if (a.M == m) {                                                                       \
     if (a.grp)                                                                          \

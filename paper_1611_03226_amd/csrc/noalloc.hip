@@ -76,7 +76,7 @@ extern "C" df_status df_dpd_forward_noalloc(void *stream, const void *x, const i
   off += align256(z.B);
   if (z.prev) sc.prev = (int64_t *)(base + off);
   off += align256(z.prev);
-  if (z.grp) sc.grp = (int64_t *)(base + off);
+  if (z.grp) sc.grp = base + off;
   e = dpd_forward_enqueue(sc, (hipStream_t)stream, x, ctrl, h, y, S, len, r, B_max, M, hist);
   if (e != hipSuccess) return fail_hip(nullptr, e, "df_dpd_forward_noalloc");
   return DF_OK;

@@ -485,7 +485,7 @@ static df_status fire_many(df_graph *g, int32_t n_actors, const int32_t *actors,
       Actor &a = g->actors[actors[i]];
       df_status st = ensure_dpd_scratch(g, a, n_firings[i]);
       if (st) return st;
-      if ((st = dpd_enqueue(g, a, n_firings[i]))) return st;
+      if ((st = dpd_enqueue(g, a, n_firings[i], false))) return st;
     }
     return DF_OK;
   }

@@ -122,6 +122,7 @@ extern "C" df_status df_graph_create(df_graph **out, int device, void *stream) {
   }
   if (const char *v = getenv("DFHIP_CHECK_INDICES")) g->check_indices = atoi(v) != 0;
   if (const char *v = getenv("DFHIP_LOG")) g->log_level = atoi(v);
+  if (const char *v = getenv("DFHIP_SCAN_AHEAD")) g->no_scan_ahead = atoi(v) == 0;
   if (const char *v = getenv("DFHIP_TILE")) {
     // "tile_outputs,outputs_per_thread,blocks_per_cu" (0 keeps a default)
     int t = 0, k = 0, b = 0;
@@ -137,14 +138,17 @@ extern "C" df_status df_graph_create(df_graph **out, int device, void *stream) {
 static void free_actor(Actor &a) {
   (void)hipFree(a.h);
   (void)hipFree(a.hist);
-  (void)hipFree(a.B);
   (void)hipFree(a.order);
   (void)hipFree(a.corr);
-  (void)hipFree(a.grp);
   (void)hipFree(a.ticket);
   (void)hipFree(a.prev);
   (void)hipFree(a.off);
-  (void)hipFree(a.last);
+  for (auto &sl : a.scan) {
+    (void)hipFree(sl.B);
+    (void)hipFree(sl.grp);
+    (void)hipFree(sl.last);
+    (void)hipFree(sl.err);
+  }
   (void)hipFree(a.state);
   (void)hipFree(a.count);
   (void)hipFree(a.emit_off);
@@ -349,7 +353,10 @@ extern "C" df_status df_actor_create(df_graph *g, df_actor_kind kind, const void
     const size_t hb = sizeof(float2) * p.n_branches_max * p.n_taps;
     const size_t sb = sizeof(float2) * p.n_branches_max * std::max(p.n_taps - 1, 1);
     if ((e = hipMalloc(&a.h, hb)) != hipSuccess || (e = hipMalloc(&a.hist, sb)) != hipSuccess ||
-        (e = hipMalloc(&a.last, sizeof(int64_t) * p.n_branches_max)) != hipSuccess ||
+        (e = hipMalloc(&a.scan[0].last, sizeof(int64_t) * p.n_branches_max)) != hipSuccess ||
+        (e = hipMalloc(&a.scan[1].last, sizeof(int64_t) * p.n_branches_max)) != hipSuccess ||
+        (e = hipMalloc(&a.scan[0].err, sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&a.scan[1].err, sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&a.ticket, sizeof(int32_t))) != hipSuccess) {
       free_actor(a);
       return fail(g, DF_ENOMEM, "actor allocation failed");
@@ -357,6 +364,8 @@ extern "C" df_status df_actor_create(df_graph *g, df_actor_kind kind, const void
     e = hipMemcpy(a.h, p.coeffs, hb, p.coeffs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(a.hist, 0, sb);
     if (e == hipSuccess) e = hipMemset(a.ticket, 0, sizeof(int32_t));
+    for (auto &sl : a.scan)
+      if (e == hipSuccess) e = hipMemset(sl.err, 0, sizeof(int32_t));
     if (e != hipSuccess) {
       free_actor(a);
       return fail_hip(g, e, "actor init");
@@ -592,15 +601,28 @@ static hipError_t grow(void **p, size_t bytes) {
 df_status dfh::ensure_dpd_scratch(df_graph *g, Actor &a, int64_t n) {
   if (n <= a.scratch_n) return DF_OK;
   HIPCHK(g, hipStreamSynchronize(g->stream));
+  if (a.ahead >= 0) {                                // its results go with the old buffers
+    HIPCHK(g, launch_fill_i32(a.scan[a.ahead].err, 0, 1, g->stream));
+    a.ahead = -1;
+  }
   const int64_t cap = std::max<int64_t>(next_pow2(n), 64);
   const int bm = a.dp.n_branches_max;
-  if (grow((void **)&a.B, sizeof(int32_t) * cap) != hipSuccess ||
-      grow((void **)&a.order, 2 * sizeof(int32_t) * cap) != hipSuccess ||
+  if (grow((void **)&a.order, 2 * sizeof(int32_t) * cap) != hipSuccess ||
       grow((void **)&a.prev, sizeof(int64_t) * bm * cap) != hipSuccess ||
       grow((void **)&a.off, sizeof(int64_t) * bm * cap) != hipSuccess ||
-      grow((void **)&a.corr, sizeof(float2) * std::max(a.dp.n_taps - 1, 1) * cap) != hipSuccess ||
-      grow((void **)&a.grp, 2 * sizeof(int64_t) * bm * scan_groups(1, cap)) != hipSuccess)
+      grow((void **)&a.corr, sizeof(float2) * std::max(a.dp.n_taps - 1, 1) * cap) != hipSuccess)
     return fail(g, DF_ENOMEM, "scratch allocation failed");
+  for (auto &sl : a.scan) {
+    if (grow((void **)&sl.B, sizeof(int32_t) * cap) != hipSuccess ||
+        grow(&sl.grp, scan_scratch_bytes(1, cap, bm, true)) != hipSuccess)
+      return fail(g, DF_ENOMEM, "scratch allocation failed");
+    ScanArgs sa{};                                   // the scan's ticket starts at zero
+    sa.n_segs = 1;
+    sa.seg_firings = cap;
+    sa.B_max = bm;
+    scan_scratch_assign(sa, sl.grp, true);
+    HIPCHK(g, launch_fill_i32(sa.ticket, 0, 1, g->stream));
+  }
   a.scratch_n = cap;
   return DF_OK;
 }
@@ -621,35 +643,70 @@ df_status dfh::dpd_admit(df_graph *g, Actor &a, int64_t n, int64_t *n_adm) {
   return DF_OK;
 }
 
-df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
+// Scan of the batch of n firings whose control tokens start at position
+// pos, into slot sl (tickets at zero); errors to err.
+static ScanArgs scan_args(df_graph *g, Actor &a, Actor::ScanSlot &sl, int64_t pos, int64_t n, bool ordered,
+                          int32_t *err) {
+  const Fifo &fc = g->fifos[a.ports[DF_DPD_CTRL]];
+  ScanArgs sa{};
+  sa.ctrl = (const int32_t *)fc.ring;
+  sa.ctrl_idx = nullptr;                             // the host's read position is exact
+  sa.ctrl_pos = pos;
+  sa.ctrl_mask = fc.mask;
+  sa.seg_firings = n;
+  sa.n_segs = 1;
+  sa.B_max = a.dp.n_branches_max;
+  sa.hist_mode = a.dp.history_mode;
+  sa.ctrl_mode = a.dp.control_mode;
+  sa.B_out = sl.B;
+  sa.prev_out = a.prev;
+  sa.off_out = a.off;
+  sa.last_out = sl.last;
+  sa.stride = a.scratch_n;
+  sa.r = a.dp.firing_size;
+  sa.err = err;
+  scan_scratch_assign(sa, sl.grp, ordered);
+  return sa;
+}
+
+df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n, bool may_run_ahead) {
   Fifo &fc = g->fifos[a.ports[DF_DPD_CTRL]];
   Fifo &fx = g->fifos[a.ports[DF_DPD_IN]];
   Fifo &fy = g->fifos[a.ports[DF_DPD_OUT]];
   const int64_t r = a.dp.firing_size;
   const int bm = a.dp.n_branches_max, M = a.dp.n_taps;
-
-  ScanArgs sa{};
-  sa.ctrl = (const int32_t *)fc.ring;
-  sa.ctrl_idx = fc.idx;
-  sa.ctrl_mask = fc.mask;
-  sa.seg_firings = n;
-  sa.n_segs = 1;
-  sa.B_max = bm;
-  sa.hist_mode = a.dp.history_mode;
-  sa.ctrl_mode = a.dp.control_mode;
-  sa.B_out = a.B;
-  sa.prev_out = a.prev;
-  sa.off_out = a.off;
-  sa.last_out = a.last;
-  sa.stride = a.scratch_n;
-  sa.r = r;
-  sa.err = g->err_dev;
-  const bool ordered = n > 64;                       // grouping pays off only for many workgroups
-  sa.order_out = ordered ? a.order : nullptr;
-  sa.grp = a.grp;
-  // tiled bodies: the head pass fills the prev/off tables from the group table
+  // tiled bodies: the head pass fills the prev/off tables from the group
+  // table, and places the firings in processing order (grouped by Horner
+  // length: pays off only for many workgroups)
   const bool heads_tables = dpd_tiled_shape(M);
-  HIPCHK(g, launch_scan(sa, g->stream, !heads_tables));
+  const bool ordered = heads_tables && n > 64;
+  const int64_t pos = fc.read_h;
+
+  // this batch's scan: the one run ahead if it assumed this batch, else a new one
+  int s = a.cur ^ 1;
+  int32_t *err_ahead = nullptr;
+  bool scanned = false;
+  if (a.ahead >= 0) {
+    s = a.ahead;
+    Actor::ScanSlot &sl = a.scan[s];
+    if (a.ahead_pos == pos && a.ahead_n == n) {
+      err_ahead = sl.err;                            // the head pass merges and clears it
+      scanned = true;
+      dlog(g, 2, "scan run ahead for %lld firings at %lld used", (long long)n, (long long)pos);
+    } else {
+      HIPCHK(g, launch_fill_i32(sl.err, 0, 1, g->stream));
+      dlog(g, 2, "scan run ahead for %lld firings at %lld discarded", (long long)a.ahead_n, (long long)a.ahead_pos);
+    }
+    a.ahead = -1;
+  }
+  Actor::ScanSlot &sl = a.scan[s];
+  if (!scanned)
+    HIPCHK(g, launch_scan(scan_args(g, a, sl, pos, n, ordered, g->err_dev), g->stream, !heads_tables, false));
+  ScanArgs sa{};                                     // where the scan left its tables
+  sa.n_segs = 1;
+  sa.seg_firings = n;
+  sa.B_max = bm;
+  scan_scratch_assign(sa, sl.grp, ordered);
 
   DpdArgs da{};
   da.x = (const float2 *)fx.ring;
@@ -660,7 +717,7 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   da.y_mask = fy.mask;
   da.h = a.h;
   da.hist = a.hist;
-  da.B = a.B;
+  da.B = sl.B;
   da.order = ordered ? a.order : nullptr;
   da.prev = a.prev;
   da.prev_stride = a.scratch_n;
@@ -671,11 +728,26 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   da.M = M;
   da.corr = a.corr;
   da.masked = a.dp.control_mode == DF_CTRL_MASK;
+  da.err = g->err_dev;
+  da.err_ahead = err_ahead;
   if (heads_tables) {
-    da.grp = a.grp;
+    da.grp = sa.grp;
     da.tab_prev = a.prev;
     da.tab_off = a.off;
     da.hist_mode = a.dp.history_mode;
+    da.obase = sa.lgrp;
+    da.order_out = ordered ? a.order : nullptr;
+  }
+  // The next batch's scan, if its control tokens are already in the channel
+  // (pushed before this batch): run by extra workgroups of the head pass into
+  // the other slot (whose last readers, the previous batch's kernels, are
+  // done), beside this batch's head corrections.
+  const bool run_ahead = may_run_ahead && !g->no_scan_ahead && heads_tables && n > 64 &&
+                         fc.write_lo - (pos + n) >= n;
+  if (run_ahead) {
+    const int t = s ^ 1;
+    da.ahead = scan_args(g, a, a.scan[t], pos + n, n, ordered, a.scan[t].err);
+    da.ahead_blocks = (int32_t)((scan_groups(1, n) + 3) / 4);
   }
   HIPCHK(g, launch_dpd_heads(da, g->stream));
   DpdCommitArgs ca{};
@@ -685,7 +757,7 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   ca.ctrl_idx = fc.idx;
   ca.y_idx = fy.idx;
   ca.hist = a.hist;
-  ca.last = a.last;
+  ca.last = sl.last;
   ca.n_firings = n;
   ca.r = r;
   ca.B_max = bm;
@@ -709,6 +781,13 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n) {
   fy.write_hi += n * r;
   a.last_n = n;
   a.fired += n;
+  a.cur = s;
+
+  if (run_ahead) {
+    a.ahead = s ^ 1;
+    a.ahead_pos = pos + n;
+    a.ahead_n = n;
+  }
   return DF_OK;
 }
 
@@ -723,7 +802,7 @@ static df_status fire_dpd(df_graph *g, Actor &a, int64_t n, int flags, int64_t *
   if (n == 0) return DF_OK;
   st = ensure_dpd_scratch(g, a, n);
   if (st) return st;
-  return dpd_enqueue(g, a, n);
+  return dpd_enqueue(g, a, n, true);
 }
 
 static df_status fire_motion(df_graph *g, Actor &a, int64_t n, int flags, int64_t *n_fired) {
@@ -1093,7 +1172,7 @@ extern "C" df_status df_stream_dpd(df_graph *g, int32_t actor, const void *x_hos
     } else {
       HIPCHK(g, launch_advance_by(ctr, delta, nc, g->err_dev, g->stream));
     }
-    st = dpd_enqueue(g, a, nb);
+    st = dpd_enqueue(g, a, nb, false);
     if (st) return st;
     HIPCHK(g, hipEventRecord(ev_fired[k], g->stream));
     // output of batch k
@@ -1169,7 +1248,7 @@ extern "C" df_status df_debug_last_batch(df_graph *g, int32_t actor, int32_t *ra
   if (n == 0) return DF_OK;
   if (rates) {
     std::vector<int32_t> B(n);
-    HIPCHK(g, hipMemcpy(B.data(), a.B, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    HIPCHK(g, hipMemcpy(B.data(), a.scan[a.cur].B, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
     for (int b = 0; b < bm; ++b)
       for (int64_t j = 0; j < n; ++j) rates[b * cap + j] = in_set((uint32_t)B[j], b) ? (int32_t)a.dp.firing_size : 0;
   }

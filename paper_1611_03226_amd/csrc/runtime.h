@@ -49,14 +49,24 @@ struct Actor {
   float2 *h = nullptr;       // [B_max][M]
   float2 *hist = nullptr;    // [B_max][M-1] carried branch histories
   int64_t scratch_n = 0;
-  int32_t *B = nullptr;      // [scratch_n]
-  int32_t *order = nullptr;  // [scratch_n][2] (firing, B) grouped by B
+  int32_t *order = nullptr;  // [scratch_n][2] (firing, branch set) grouped by Horner length
   float2 *corr = nullptr;    // [scratch_n][M-1] head corrections
-  int64_t *grp = nullptr;    // scan group table
   int64_t *prev = nullptr;   // [B_max][scratch_n]
   int64_t *off = nullptr;    // [B_max][scratch_n]
-  int64_t *last = nullptr;   // [B_max]
   int32_t *ticket = nullptr; // finished-workgroup counter of the body (commit by the last one)
+  // Scan results of a batch, in two slots: the scan of the next batch (it
+  // reads control tokens only) runs ahead, inside this batch's head pass,
+  // and is used if the next batch starts where it assumed and has its size.
+  struct ScanSlot {
+    int32_t *B = nullptr;      // [scratch_n] validated branch sets
+    void *grp = nullptr;       // scan scratch: ticket, group table, length table
+    int64_t *last = nullptr;   // [B_max] last feeder of each branch
+    int32_t *err = nullptr;    // control-token errors of a scan run ahead (merged when used)
+  };
+  ScanSlot scan[2];
+  int cur = 0;                 // slot of the last batch
+  int ahead = -1;              // slot holding a scan run ahead, or -1
+  int64_t ahead_pos = 0, ahead_n = 0;
   // motion
   df_motion_params mp{};
   uint8_t *state = nullptr;  // previous frame (self-delay form)
@@ -76,6 +86,7 @@ struct df_graph {
   int device = 0;
   hipStream_t stream = nullptr;
   hipStream_t copy_in = nullptr, copy_out = nullptr;  // host transfers of df_stream_dpd (created on first use)
+  bool no_scan_ahead = false;        // DFHIP_SCAN_AHEAD=0: no scan of the next batch in the head pass
   bool own_stream = false;
   bool poisoned = false;
   std::string last_error;
@@ -111,7 +122,10 @@ df_status after_call(df_graph *g, df_status st);
 void dlog(const df_graph *g, int level, const char *fmt, ...);
 df_status ensure_dpd_scratch(df_graph *g, Actor &a, int64_t n);
 df_status dpd_admit(df_graph *g, Actor &a, int64_t n, int64_t *n_adm);
-df_status dpd_enqueue(df_graph *g, Actor &a, int64_t n);
+// One batch of n firings on the graph stream; with may_run_ahead, the head
+// pass also scans the next batch of n firings (if its control tokens are in
+// the channel).
+df_status dpd_enqueue(df_graph *g, Actor &a, int64_t n, bool may_run_ahead);
 void destroy_persistent(df_graph *g);
 
 // Scratch of one stateless predistortion forward call: validated branch
@@ -121,7 +135,7 @@ void destroy_persistent(df_graph *g);
 struct FwdScratch {
   int32_t *B = nullptr;
   int64_t *prev = nullptr;
-  int64_t *grp = nullptr;
+  void *grp = nullptr;        // scan scratch (scan_scratch_bytes)
   float2 *corr = nullptr;
 };
 struct FwdScratchSize {

@@ -29,7 +29,7 @@ struct Tables {
   int32_t *B = nullptr;
   int64_t *prev = nullptr;
   int64_t *off = nullptr;
-  int64_t *grp = nullptr;
+  void *grp = nullptr;       // scan scratch
   int64_t n = 0;
 };
 
@@ -44,7 +44,7 @@ hipError_t make_tables(const int32_t *ctrl, int64_t S, int64_t nf, int64_t r, in
     e = hipMallocAsync((void **)&t->off, sizeof(int64_t) * std::max<int64_t>(t->n, 1) * B_max, s);
     if (e != hipSuccess) return e;
   }
-  e = hipMallocAsync((void **)&t->grp, 2 * sizeof(int64_t) * B_max * std::max<int64_t>(scan_groups(S, nf), 1), s);
+  e = hipMallocAsync(&t->grp, scan_scratch_bytes(S, nf, B_max, false), s);
   if (e != hipSuccess) return e;
   ScanArgs sa{};
   sa.ctrl = ctrl;
@@ -57,7 +57,7 @@ hipError_t make_tables(const int32_t *ctrl, int64_t S, int64_t nf, int64_t r, in
   sa.B_out = t->B;
   sa.prev_out = t->prev;
   sa.off_out = t->off;
-  sa.grp = t->grp;
+  scan_scratch_assign(sa, t->grp, false);
   sa.stride = t->n;
   sa.r = r;
   return launch_scan(sa, s);
@@ -87,7 +87,7 @@ FwdScratchSize dfh::dpd_forward_scratch_size(int64_t S, int64_t len, int64_t r, 
   const int64_t nf = len / r, n = std::max<int64_t>(S * nf, 1);
   z.B = sizeof(int32_t) * n;
   z.prev = sizeof(int64_t) * n * B_max;
-  z.grp = 2 * sizeof(int64_t) * B_max * std::max<int64_t>(scan_groups(S, nf), 1);
+  z.grp = scan_scratch_bytes(S, nf, B_max, false);
   z.corr = sizeof(float2) * L1 * n;
   return z;
 }
@@ -128,7 +128,7 @@ hipError_t dfh::dpd_forward_enqueue(const FwdScratch &sc, hipStream_t s, const v
   sa.B_out = sc.B;
   sa.prev_out = sc.prev;
   sa.off_out = nullptr;
-  sa.grp = sc.grp;
+  scan_scratch_assign(sa, sc.grp, false);
   sa.stride = n;
   sa.r = r;
   hipError_t e = launch_scan(sa, s);
