@@ -39,6 +39,8 @@ def flags(arch: str) -> list[str]:
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={arch}",
             # packed FP32 VALU ops are disabled for every HIP object
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # matrix-core results in VGPRs (no accumulator-register copies)
+            "-Xarch_device", "-mllvm=-amdgpu-mfma-vgpr-form",
             "-Wall", "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}"]
 
 

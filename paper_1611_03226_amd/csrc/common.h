@@ -160,6 +160,7 @@ struct DpdArgs {
   int32_t *order_out;     // [n_firings][2] or nullptr
   int32_t hist_mode;
   int32_t masked;         // branch sets may be non-prefix (bit-mask control tokens)
+  int32_t mx;             // M = 16 tiled body on the matrix cores (else the VALU form)
   int32_t *ticket;        // tiled kernel: the last workgroup to finish runs `commit` (nullptr: none)
   DpdCommitArgs commit;
   int32_t *err;           // sticky error word (head pass; may be nullptr)
@@ -312,6 +313,11 @@ hipError_t launch_mask_tables(const int32_t *ctrl, int32_t *B, int64_t *off, con
 
 bool dpd_tiled_shape(int M);
 hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s);
+// Body form for M = 16 from the environment: the VALU form, or the
+// matrix-core form with DFHIP_BODY=mx (measured slower on MI355X: the
+// complex products and row combination it leaves on the VALU cost nearly
+// as many instructions as Horner's rule).
+bool dpd_body_mx_env();
 hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int outputs_per_thread,
                            const KTiming *timing = nullptr);
 hipError_t launch_dpd_commit(const DpdCommitArgs &a, hipStream_t s);

@@ -342,4 +342,236 @@ __device__ __forceinline__ void run_tiles(float2 *sx, float2 *sc, int64_t n_item
   }
 }
 
+
+
+// ------------------------------------------------------------------ matrix cores
+// Matrix-core form of a tile for M = 16 taps.  The per-tap polynomial is a
+// matrix product: for a block of 16 window samples s and a chunk of four
+// branches, Q[m][s] = sum_b h_b[m] p_s^b is one v_mfma_f32_16x16x4_f32
+// (rows: taps m, columns: samples s, inner index: branches b; one product
+// for the real and one for the imaginary part of h), accumulated over the
+// ceil(B/4) chunks.  The rest stays on the VALU: Z[m][s] = x_s Q[m][s]
+// (complex), and y[q] = sum_m Z[m][q + 15 - m] (window sample i = q + 15 - m
+// for output q), taken in two steps.  Lane (row rho, column j) holds Z for
+// taps 4 rho + r (r = 0..3, the product's accumulator layout) of sample j;
+// shifting register r by r lanes inside the 16-lane row (DPP) aligns every
+// value on lane u = j + r, so a row sums to
+//   R_rho[16k + u] = sum_r Z[4 rho + r][16k + u - r]   (block k),
+// with positions u >= 16 carried to the next block's first lanes.  Each
+// R_rho is written to LDS, and after a barrier
+//   y[q] = R_0[q + 15] + R_1[q + 11] + R_2[q + 7] + R_3[q + 3].
+// The products are exact float products with float accumulation (the
+// power-basis sum, not Horner's rule), so this form rounds differently from
+// the VALU form; when it is selected (DFHIP_BODY=mx), every kernel that runs
+// M = 16 bodies uses it, so the batching paths stay bit-identical.  On
+// MI355X it is the slower form: the complex products, row combination,
+// powers and LDS staging it leaves on the VALU cost nearly as many VALU
+// instructions as Horner's rule (SQ_INSTS_VALU per launch 60 M + 4 M
+// matrix products against 66 M), and the matrix products add latency.
+
+typedef float mx4 __attribute__((ext_vector_type(4)));
+
+// Lane i of a 16-lane row receives lane i-S of the same row (0 below the
+// row start): one DPP move.
+template <int S>
+__device__ __forceinline__ float row_shr(float v) {
+  if constexpr (S == 0) {
+    return v;
+  } else {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x110 + S, 0xF, 0xF, true));
+  }
+}
+
+// Window and row-sum buffer sizes of a matrix-core tile (float2 slots): the
+// blocks read window samples up to index tile + 30, and one block ahead.
+__host__ __device__ constexpr int mx_window(int tile) { return lds_window(tile + 48); }
+__host__ __device__ constexpr int mx_row(int tile) { return tile + 32; }
+__host__ __device__ constexpr int mx_lds(int tile) { return lds_corr(16) + mx_window(tile) + 4 * mx_row(tile) + 256; }
+
+// Coefficient operand of the tile's firing: lane l holds h_b[m] for branch
+// b = 4c + l/16, tap m = l%16 (zero for branches outside the set).
+struct MxCoef {
+  float hr[4], hi[4];
+};
+
+// The operand passes through LDS (256 float2, written by wavefront 0 at the
+// tile's commit), so that the block loop waits on LDS reads only, never on
+// the next tile's global loads in flight.
+__device__ __forceinline__ void mx_commit_coef(float2 *sh, const MxCoef &c) {
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[64 * k + threadIdx.x] = make_float2(c.hr[k], c.hi[k]);
+  }
+}
+
+__device__ __forceinline__ void mx_read_coef(const float2 *sh, MxCoef &c) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float2 v = sh[64 * k + lane];
+    c.hr[k] = v.x;
+    c.hi[k] = v.y;
+  }
+}
+
+template <bool MASKED>
+__device__ __forceinline__ void mx_load_coef(MxCoef &c, const Job &j) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int b = 4 * k + (lane >> 4);
+    const bool on = b < j.B && (!MASKED || in_set(j.set, b));
+    const float2 v = on ? j.h[b * 16 + (lane & 15)] : make_float2(0.f, 0.f);
+    c.hr[k] = v.x;
+    c.hi[k] = v.y;
+  }
+}
+
+// Row sums of window block k for this wavefront's lanes: main (lane u:
+// position 16k + u) and the part past the block end (lanes 0..2: positions
+// 16k + 16 + u, carried into the next block).
+template <int NCH>
+__device__ __forceinline__ void mx_block(const float2 xv, const MxCoef &c, float &mr, float &mi, float &nr, float &ni) {
+  const int rho = (threadIdx.x & 63) >> 4;
+  const float p = fmaf(xv.x, xv.x, xv.y * xv.y);
+  const float p2 = p * p;
+  // p^(4c + rho): p^rho selected without branches, times p^4 per chunk
+  float bp = ((rho & 1) ? p : 1.f) * ((rho & 2) ? p2 : 1.f);
+  const float p4 = p2 * p2;
+  mx4 qr = {0.f, 0.f, 0.f, 0.f}, qi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    qr = __builtin_amdgcn_mfma_f32_16x16x4f32(c.hr[ch], bp, qr, 0, 0, 0);
+    qi = __builtin_amdgcn_mfma_f32_16x16x4f32(c.hi[ch], bp, qi, 0, 0, 0);
+    if (ch + 1 < NCH) bp *= p4;
+  }
+  float zr[4], zi[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    zr[r] = fmaf(xv.x, qr[r], -(xv.y * qi[r]));
+    zi[r] = fmaf(xv.x, qi[r], xv.y * qr[r]);
+  }
+  mr = zr[0] + row_shr<1>(zr[1]);
+  mi = zi[0] + row_shr<1>(zi[1]);
+  mr = mr + row_shr<2>(zr[2]);
+  mi = mi + row_shr<2>(zi[2]);
+  mr = mr + row_shr<3>(zr[3]);
+  mi = mi + row_shr<3>(zi[3]);
+  nr = row_shl<15>(zr[1]) + row_shl<14>(zr[2]);
+  ni = row_shl<15>(zi[1]) + row_shl<14>(zi[2]);
+  nr = nr + row_shl<13>(zr[3]);
+  ni = ni + row_shl<13>(zi[3]);
+}
+
+// Blocks [k0, k1) of the tile for this wavefront (block k0 - 1 first, for
+// the part of its row sums that falls into block k0).
+template <int NCH>
+__device__ __forceinline__ void mx_blocks(const float2 *sx, float2 *rb, int rs, const MxCoef &c, int k0, int k1) {
+  const int lane = threadIdx.x & 63, j = lane & 15, rho = lane >> 4;
+  float cr = 0.f, ci = 0.f;                          // carried into lanes 0..2 from the block before
+  if (k0 > 0) {
+    float mr, mi;
+    mx_block<NCH>(sx[lds_slot(16 * (k0 - 1) + j)], c, mr, mi, cr, ci);
+  }
+  float2 *dst = rb + rho * rs + j;
+  float2 xv = sx[lds_slot(16 * k0 + j)];             // the next block's sample is read one block ahead
+  for (int k = k0; k < k1; ++k) {
+    const float2 xn = sx[lds_slot(16 * (k + 1) + j)];
+    float mr, mi, nr, ni;
+    mx_block<NCH>(xv, c, mr, mi, nr, ni);
+    dst[16 * k] = make_float2(mr + cr, mi + ci);
+    cr = nr;
+    ci = ni;
+    xv = xn;
+  }
+}
+
+// The tile's outputs q = threadIdx.x + NT*kk from the row sums (and the
+// head corrections of a firing's first M-1 outputs).
+template <int K>
+__device__ __forceinline__ void mx_store(const float2 *sc, const float2 *rb, int rs, const Job &j) {
+  const int nt = blockDim.x;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int q = threadIdx.x + nt * kk;
+    if (q >= j.nout) break;
+    const float2 a = rb[q + 15], b = rb[rs + q + 11], c = rb[2 * rs + q + 7], d = rb[3 * rs + q + 3];
+    float vr = a.x + b.x, vi = a.y + b.y;
+    vr = vr + c.x;
+    vi = vi + c.y;
+    vr = vr + d.x;
+    vi = vi + d.y;
+    if (j.head && q < 15) {
+      vr = vr + sc[q].x;
+      vi = vi + sc[q].y;
+    }
+    j.y[(j.yb + j.t0 + q) & j.y_mask] = make_float2(vr, vi);
+  }
+}
+
+// One tile on the matrix cores: the wavefronts split the tile's blocks,
+// then every thread stores its outputs.
+template <int K, int BC>
+__device__ __forceinline__ void mx_tile(const float2 *sx, const float2 *sc, float2 *rb, const MxCoef &c, const Job &j) {
+  const int rs = mx_row(K * (int)blockDim.x);
+  const int nblk = (j.nout + 14) / 16 + 1;
+  const int nw = blockDim.x >> 6, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int k0 = nblk * w / nw, k1 = nblk * (w + 1) / nw;
+  const int nch = (j.B + 3) >> 2;
+  if (j.B > 0) {
+    switch (nch) {
+      case 1: mx_blocks<1>(sx, rb, rs, c, k0, k1); break;
+      case 2: mx_blocks<2>(sx, rb, rs, c, k0, k1); break;
+      case 3: mx_blocks<3>(sx, rb, rs, c, k0, k1); break;
+      default: if constexpr (BC > 12) mx_blocks<4>(sx, rb, rs, c, k0, k1); break;
+    }
+  }
+  __syncthreads();
+  if (j.B > 0) {
+    mx_store<K>(sc, rb, rs, j);
+  } else {                                           // no active branch: zeros
+    for (int q = threadIdx.x; q < j.nout; q += blockDim.x) j.y[(j.yb + j.t0 + q) & j.y_mask] = make_float2(0.f, 0.f);
+  }
+}
+
+// The pipelined tile loop (as run_tiles) with matrix-core tiles (M = 16).
+// LDS: [15] head corrections, window (mx_window), 4 row-sum rows (mx_row),
+// coefficient operand (256).
+template <int K, int BC, bool MASKED, class Src>
+__device__ __forceinline__ void run_tiles_mx(float2 *sx, float2 *sc, float2 *rb, float2 *sh, int64_t n_items,
+                                             Src &src) {
+  constexpr int M = 16;
+  const int64_t s = gridDim.x;
+  int64_t item = blockIdx.x;
+  if (item >= n_items) return;                       // uniform
+  Job cur, nxt;
+  src.expand(src.fetch(item), item, cur);
+  TileRegs<M, K> regs;
+  MxCoef cl;                                         // coefficient loads of the tile to commit
+  load_tile<M, K>(regs, cur);
+  mx_load_coef<MASKED>(cl, cur);
+  bool has_next = item + s < n_items;
+  if (has_next) src.expand(src.fetch(item + s), item + s, nxt);
+  for (;;) {
+    commit_tile<M, K>(sx, sc, regs, cur);
+    mx_commit_coef(sh, cl);
+    __syncthreads();
+    const bool has_nn = item + 2 * s < n_items;
+    if (has_next) {
+      load_tile<M, K>(regs, nxt);
+      mx_load_coef<MASKED>(cl, nxt);
+    }
+    const uint32_t dv_nn = has_nn ? src.fetch(item + 2 * s) : 0u;
+    MxCoef c;
+    mx_read_coef(sh, c);
+    mx_tile<K, BC>(sx, sc, rb, c, cur);
+    if (!has_next) break;
+    __syncthreads();
+    item += s;
+    cur = nxt;
+    if (has_nn) src.expand(dv_nn, item + s, nxt);
+    has_next = has_nn;
+  }
+}
+
 }  // namespace dfh

@@ -11,6 +11,9 @@
 // state); those terms are added by a per-branch correction.
 #include <hip/hip_ext.h>
 
+#include <cstdlib>
+#include <cstring>
+
 #include "common.h"
 #include "dpd_tile.h"
 #include "scan_dev.h"
@@ -249,6 +252,45 @@ __global__ __launch_bounds__(256) void k_dpd_tiled(DpdArgs a) {
   }
 }
 
+// The same loop with matrix-core tiles (M = 16).
+template <int K, int BC, bool MASKED>
+__global__ __launch_bounds__(256) void k_dpd_tiled_mx(DpdArgs a) {
+  extern __shared__ float2 lds[];   // [15] head corrections, window, 4 row-sum rows, coefficients
+  float2 *sc = lds, *sx = sc + lds_corr(16), *rb = sx + mx_window(a.tile), *sh = rb + 4 * mx_row(a.tile);
+  SingleSrc src{a, a.x_idx ? as_const(a.x_idx)[0] : 0, a.y_idx ? as_const(a.y_idx)[1] : 0};
+  run_tiles_mx<K, BC, MASKED>(sx, sc, rb, sh, a.n_firings * a.tiles_per_firing, src);
+  if (!a.ticket) return;
+  __shared__ int last_block;                         // commit by the last workgroup, as above
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last_block = __hip_atomic_fetch_add(a.ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                 (int)gridDim.x - 1;
+  __syncthreads();
+  if (last_block) {
+    dpd_commit_block(a.commit);
+    if (threadIdx.x == 0) *a.ticket = 0;
+  }
+}
+
+template <int K, int BC, bool MASKED>
+static hipError_t launch_tiled_mx(const DpdArgs &a0, hipStream_t s, int tile, const KTiming *t) {
+  DpdArgs a = a0;
+  a.tile = tile;
+  a.tiles_per_firing = (int32_t)((a.r + tile - 1) / tile);
+  const int threads = tile / K;
+  const size_t lds = (size_t)mx_lds(tile) * sizeof(float2);
+  const int64_t items = a.n_firings * a.tiles_per_firing;
+  if (items <= 0) return hipSuccess;
+  const int64_t resident = resident_blocks((const void *)k_dpd_tiled_mx<K, BC, MASKED>, threads, lds);
+  const int64_t blocks = items < resident ? items : resident;
+  if (t)
+    hipExtLaunchKernelGGL((k_dpd_tiled_mx<K, BC, MASKED>), dim3((unsigned)blocks), dim3(threads), lds, s, t->start,
+                          t->stop, 0, a);
+  else
+    hipLaunchKernelGGL((k_dpd_tiled_mx<K, BC, MASKED>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
 template <int M, int K, int BC, bool MASKED>
 static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile, const KTiming *t) {
   DpdArgs a = a0;
@@ -269,6 +311,11 @@ static hipError_t launch_tiled(const DpdArgs &a0, hipStream_t s, int tile, const
 }
 
 bool dpd_tiled_shape(int M) { return M == 4 || M == 8 || M == 16; }
+
+bool dpd_body_mx_env() {
+  const char *v = getenv("DFHIP_BODY");
+  return v && strcmp(v, "mx") == 0;
+}
 
 hipError_t launch_dpd_heads(const DpdArgs &a, hipStream_t s) {
   if (a.n_firings <= 0 || !dpd_tiled_shape(a.M)) return hipSuccess;
@@ -314,6 +361,13 @@ hipError_t launch_dpd_body(const DpdArgs &a, hipStream_t s, int tile, int output
   // compiled paths: Horner lengths up to 10 or up to 16; branch sets that are
   // not prefixes (bit-mask tokens) take the masked paths up to 16
   const bool small = a.B_max <= 10;
+  if (a.M == 16 && a.mx) {
+    if (K == 4)
+      return a.masked ? launch_tiled_mx<4, 16, true>(a, s, tl, t)
+                      : (small ? launch_tiled_mx<4, 10, false>(a, s, tl, t) : launch_tiled_mx<4, 16, false>(a, s, tl, t));
+    return a.masked ? launch_tiled_mx<8, 16, true>(a, s, tl, t)
+                    : (small ? launch_tiled_mx<8, 10, false>(a, s, tl, t) : launch_tiled_mx<8, 16, false>(a, s, tl, t));
+  }
 #define DF_TILED(m, k)                                                                      \
   if (a.M == m && K == k)                                                                   \
     return a.masked ? launch_tiled<m, k, 16, true>(a, s, tl, t)                             \

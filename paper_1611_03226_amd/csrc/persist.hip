@@ -312,6 +312,15 @@ __global__ __launch_bounds__(512) void k_pers_body(PersArgs a) {
   run_tiles<M, K, BC, MASKED>(sx, sc, as_const(a.tile_base)[a.n_inst], src);
 }
 
+// The same walk with matrix-core tiles (M = 16).
+template <int K, int BC, bool MASKED>
+__global__ __launch_bounds__(512) void k_pers_body_mx(PersArgs a) {
+  extern __shared__ float2 lds[];   // [15] head corrections, window, 4 row-sum rows, coefficients
+  float2 *sc = lds, *sx = sc + lds_corr(16), *rb = sx + mx_window(a.tile), *sh = rb + 4 * mx_row(a.tile);
+  ItemSrc src{a};
+  run_tiles_mx<K, BC, MASKED>(sx, sc, rb, sh, as_const(a.tile_base)[a.n_inst], src);
+}
+
 __global__ __launch_bounds__(256) void k_pers_commit(PersArgs a, int M) {
   const int i = blockIdx.x;
   const InstDesc &d = a.inst[i];
@@ -353,6 +362,7 @@ struct Persistent {
   int64_t cap = 0, items_cap = 0, heads_cap = 0, n_heads = 0;
   int64_t captures = 0;   // graph captures so far (diagnostics)
   int tile = 0, K = 0, bpc = 0, ncu = 0;
+  bool mx = false;         // M = 16 bodies on the matrix cores
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -396,6 +406,16 @@ static hipError_t launch_pers_body(const PersArgs &a, int threads, int blocks, h
   return hipGetLastError();
 }
 
+template <int K, int BC, bool MASKED>
+static hipError_t launch_pers_body_mx(const PersArgs &a, int threads, int blocks, hipStream_t s, const KTiming *t) {
+  const size_t lds = (size_t)mx_lds(a.tile) * sizeof(float2);
+  if (t)
+    hipExtLaunchKernelGGL((k_pers_body_mx<K, BC, MASKED>), dim3(blocks), dim3(threads), lds, s, t->start, t->stop, 0, a);
+  else
+    hipLaunchKernelGGL((k_pers_body_mx<K, BC, MASKED>), dim3(blocks), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
 static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s, df_graph *prof_g) {
   hipLaunchKernelGGL(k_pers_prep, dim3(1), dim3(64), 0, s, a);
   hipError_t e = hipGetLastError();
@@ -422,15 +442,26 @@ static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s,
   if (prof_g && (e = prof_pair(prof_g, &kt)) != hipSuccess) return e;
   const KTiming *tp = (prof_g && prof_g->prof) ? &kt : nullptr;
   const bool small = a.Bg <= 10;
+#define DF_PERS_MX(k)                                                                              \
+  if (p->K == k)                                                                                   \
+    e = a.masked ? launch_pers_body_mx<k, 16, true>(a, threads, blocks, s, tp)                    \
+        : (small ? launch_pers_body_mx<k, 10, false>(a, threads, blocks, s, tp)                    \
+                 : launch_pers_body_mx<k, 16, false>(a, threads, blocks, s, tp));               \
+  else
 #define DF_PERS(m, k)                                                                              \
   if (p->M == m && p->K == k)                                                                      \
     e = a.masked ? launch_pers_body<m, k, 16, true>(a, threads, blocks, s, tp)                    \
         : (small ? launch_pers_body<m, k, 10, false>(a, threads, blocks, s, tp)                    \
                  : launch_pers_body<m, k, 16, false>(a, threads, blocks, s, tp));               \
   else
-  DF_PERS(16, 4) DF_PERS(16, 8) DF_PERS(8, 4) DF_PERS(8, 8) DF_PERS(4, 4) DF_PERS(4, 8)
-  return hipErrorInvalidValue;
+  if (p->M == 16 && p->mx) {
+    DF_PERS_MX(4) DF_PERS_MX(8) return hipErrorInvalidValue;
+  } else {
+    DF_PERS(16, 4) DF_PERS(16, 8) DF_PERS(8, 4) DF_PERS(8, 8) DF_PERS(4, 4) DF_PERS(4, 8)
+    return hipErrorInvalidValue;
+  }
 #undef DF_PERS
+#undef DF_PERS_MX
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pers_commit, dim3(a.n_inst), dim3(256), 0, s, a, p->M);
   return hipGetLastError();
@@ -499,6 +530,7 @@ static df_status fire_many(df_graph *g, int32_t n_actors, const int32_t *actors,
     p = g->pers = new Persistent();
     p->actors.assign(actors, actors + n_actors);
     p->M = M;
+    p->mx = g->body_mx;
     p->Bg = Bg;
     HIPCHK(g, hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, g->device));
     HIPCHK(g, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));

@@ -123,6 +123,7 @@ extern "C" df_status df_graph_create(df_graph **out, int device, void *stream) {
   if (const char *v = getenv("DFHIP_CHECK_INDICES")) g->check_indices = atoi(v) != 0;
   if (const char *v = getenv("DFHIP_LOG")) g->log_level = atoi(v);
   if (const char *v = getenv("DFHIP_SCAN_AHEAD")) g->no_scan_ahead = atoi(v) == 0;
+  g->body_mx = dpd_body_mx_env();
   if (const char *v = getenv("DFHIP_TILE")) {
     // "tile_outputs,outputs_per_thread,blocks_per_cu" (0 keeps a default)
     int t = 0, k = 0, b = 0;
@@ -728,6 +729,7 @@ df_status dfh::dpd_enqueue(df_graph *g, Actor &a, int64_t n, bool may_run_ahead)
   da.M = M;
   da.corr = a.corr;
   da.masked = a.dp.control_mode == DF_CTRL_MASK;
+  da.mx = g->body_mx;
   da.err = g->err_dev;
   da.err_ahead = err_ahead;
   if (heads_tables) {

@@ -96,6 +96,7 @@ struct df_graph {
   int32_t *err_dev = nullptr;    // sticky device error word
   int tile = 0;                  // 0 = default
   int outputs_per_thread = 4;
+  bool body_mx = false;          // M = 16 bodies on the matrix cores (DFHIP_BODY=mx)
   int blocks_per_cu = 0;          // persistent grid; 0 = default
   dfh::Persistent *pers = nullptr;
   bool check_indices = false;    // DFHIP_CHECK_INDICES: every token-moving call syncs and reports device errors

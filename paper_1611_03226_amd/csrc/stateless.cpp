@@ -106,6 +106,7 @@ hipError_t dfh::dpd_forward_enqueue(const FwdScratch &sc, hipStream_t s, const v
   a.B_max = B_max;
   a.M = M;
   a.corr = sc.corr;
+  a.mx = dpd_body_mx_env();
   if (!ctrl) {
     // All branches active in every firing: a row is one convolution.
     a.B_const = B_max;
