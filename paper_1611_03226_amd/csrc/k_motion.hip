@@ -108,6 +108,54 @@ __device__ __forceinline__ void load_rows(const uint8_t *const (&fr)[F + 1], int
   for (int f = 0; f <= F; ++f) load_word(fr[f], y, x0, W, FAST, buf[f]);
 }
 
+// Coalesced form of one row of the F+1 frames (W a multiple of 32): the
+// wavefront's 64 words are the 2 KiB from byte xs of the row; it loads them
+// as two contiguous KiB spans (lane l: 16 bytes at xs + 16 l and at
+// xs + 1024 + 16 l; spans outside the row read as 0) ...
+template <int F>
+__device__ __forceinline__ void load_spans(const uint8_t *const (&fr)[F + 1], int y, int xs, int W,
+                                           uint32_t (&raw)[F + 1][8]) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int f = 0; f <= F; ++f)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int off = xs + 1024 * h + 16 * lane;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (off >= 0 && off < W) v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(fr[f] + (int64_t)y * W + off));
+      raw[f][4 * h + 0] = v.x;
+      raw[f][4 * h + 1] = v.y;
+      raw[f][4 * h + 2] = v.z;
+      raw[f][4 * h + 3] = v.w;
+    }
+}
+
+// ... and passes them through LDS (stg: (F+1) x 512 words of this
+// wavefront), so that each lane ends with its own 32 bytes (bytes 32 l ..
+// 32 l + 31 of the span) in buf.
+template <int F>
+__device__ __forceinline__ void stage_spans(uint32_t *stg, const uint32_t (&raw)[F + 1][8], uint32_t (&buf)[F + 1][8]) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int f = 0; f <= F; ++f)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      *reinterpret_cast<u32x4 *>(stg + 512 * f + 256 * h + 4 * lane) =
+          u32x4{raw[f][4 * h], raw[f][4 * h + 1], raw[f][4 * h + 2], raw[f][4 * h + 3]};
+#pragma unroll
+  for (int f = 0; f <= F; ++f)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const u32x4 v = *reinterpret_cast<const u32x4 *>(stg + 512 * f + 8 * lane + 4 * h);
+      buf[f][4 * h + 0] = v.x;
+      buf[f][4 * h + 1] = v.y;
+      buf[f][4 * h + 2] = v.z;
+      buf[f][4 * h + 3] = v.w;
+    }
+}
+
 // Work items in XCD-contiguous order: workgroups are dispatched to the 8
 // XCDs round robin (workgroup b to XCD b % 8), so item k runs on XCD
 // k / per_xcd, and the items an XCD runs in turn are consecutive: the bands
@@ -197,14 +245,30 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
 #pragma unroll
     for (int k = 0; k < 8; ++k) A[f][k] = Bf[f][k] = 0;
   const int ylast = y1 + 1;
-  auto rowload = [&](int y, uint32_t (&buf)[F + 1][8]) { load_rows<F, FAST>(fr, min(max(y, 0), H - 1), x0, W, buf); };
-  rowload(y0 - 2, A);
-  for (int y = y0 - 2; y <= ylast; y += 2) {
-    if (y + 1 <= ylast) rowload(y + 1, Bf);
-    process(A, y);
-    if (y + 1 > ylast) break;
-    if (y + 2 <= ylast) rowload(y + 2, A);
-    process(Bf, y + 1);
+  if constexpr (FAST) {
+    // coalesced spans: the next row's loads are in flight (raw) while the
+    // current row, already staged through LDS, is processed
+    __shared__ uint32_t stg[F + 1][512];
+    const int xs = (chunk * MW_CHUNK - 1) * 32;
+    auto clampy = [&](int y) { return min(max(y, 0), H - 1); };
+    load_spans<F>(fr, clampy(y0 - 2), xs, W, Bf);
+    stage_spans<F>(&stg[0][0], Bf, A);
+    for (int y = y0 - 2; y <= ylast; ++y) {
+      if (y + 1 <= ylast) load_spans<F>(fr, clampy(y + 1), xs, W, Bf);
+      process(A, y);
+      if (y + 1 > ylast) break;
+      stage_spans<F>(&stg[0][0], Bf, A);
+    }
+  } else {
+    auto rowload = [&](int y, uint32_t (&buf)[F + 1][8]) { load_rows<F, FAST>(fr, min(max(y, 0), H - 1), x0, W, buf); };
+    rowload(y0 - 2, A);
+    for (int y = y0 - 2; y <= ylast; y += 2) {
+      if (y + 1 <= ylast) rowload(y + 1, Bf);
+      process(A, y);
+      if (y + 1 > ylast) break;
+      if (y + 2 <= ylast) rowload(y + 2, A);
+      process(Bf, y + 1);
+    }
   }
 #pragma unroll
   for (int f = 0; f < F; ++f) {
