@@ -9,7 +9,8 @@
 //   o  = OR  of e  over the in-frame 3x3 neighbourhood   (dilation)
 //   count_j = sum o;  emit_j = 1000*count_j >= permille*W*H
 // Emission depends on the whole frame, so a batch runs
-//   bits pass:   opened masks, bit-packed (32 pixels per word), and counts
+//   bits pass:   opened masks, bit-packed (32 pixels per word, transposed
+//                bit order below), and counts
 //   emit scan:   output slots of the emitted frames
 //   expand pass: emitted masks as 0/255 bytes at their output slots
 //   commit:      channel indices.
@@ -19,9 +20,10 @@
 // lanes 0 and 63 are halo words).  It sweeps the rows of the band (plus two
 // above and below) keeping, per frame, the last horizontal-AND rows and
 // horizontal-OR rows in registers:
-//   hm(y)   = m0(y) & m0(y)<<1 & m0(y)>>1        (carries from neighbour lanes)
+//   hm(y)   = m0(y) & left(m0(y)) & right(m0(y))  (neighbour pixels; edge
+//             bits from the neighbour lanes)
 //   e(y-1)  = hm(y-2) & hm(y-1) & hm(y)
-//   he(y-1) = e(y-1) | e(y-1)<<1 | e(y-1)>>1
+//   he(y-1) = e(y-1) | left(e(y-1)) | right(e(y-1))
 //   o(y-2)  = he(y-3) | he(y-2) | he(y-1)
 // Outside the frame m0 counts as set (erosion ignores it) and e as clear
 // (dilation ignores it).  Erosion and dilation over a square are separable,
@@ -71,26 +73,59 @@ __device__ __forceinline__ uint32_t from_upper_lane(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true);   // wave_shl:1
 }
 
-// Bit i of the result: |cur_i - prev_i| > thr for the 32 pixels of a word.
-// Even and odd bytes are spread into 16-bit lanes (byte permutes); with
-// d = cur - prev, the pixel is unchanged iff d - (thr+1) and -(thr+1) - d are
-// both negative, i.e. bit 15 of their AND; those bits are gathered and the
-// word inverted once.
-__device__ __forceinline__ uint32_t thresh_bits(const uint32_t (&c)[8], const uint32_t (&p)[8], i16x2 t1,
-                                                i16x2 nt1) {
+// Mask words use a transposed bit order: pixel 4k + j of a word (dword k
+// of its 32 bytes, byte j) is bit 8j + k.  The threshold's flags then
+// gather with one byte permute and one shift-and-merge per dword, and the
+// expand pass decodes a dword's four bytes with one mask and multiply.
+__host__ __device__ constexpr int tbit(int x) { return 8 * (x & 3) + (x >> 2); }
+
+// Natural-order mask (bit x = pixel x) to the transposed order.
+__device__ __forceinline__ uint32_t to_tbits(uint32_t v) {
+  uint32_t t = 0;
+  for (int x = 0; x < 32; ++x) t |= ((v >> x) & 1u) << tbit(x);
+  return t;
+}
+
+// Neighbour pixels in the transposed order: bit of pixel x receives pixel
+// x+1 (right) or x-1 (left); across the word edge from the neighbouring
+// lane's word (its pixel 0 is bit 0, its pixel 31 is bit 31).
+__device__ __forceinline__ uint32_t tright(uint32_t m, uint32_t rw) {
+  return (m >> 8) | ((m << 23) & 0x7F000000u) | (rw << 31);
+}
+__device__ __forceinline__ uint32_t tleft(uint32_t m, uint32_t lw) {
+  return (m << 8) | ((m >> 23) & 0xFEu) | (lw >> 31);
+}
+
+// Even and odd bytes of a row's dwords spread into 16-bit lanes (byte
+// permutes); in the self-delay form a frame's spread serves as the current
+// frame of one output and the previous frame of the next.
+struct Spread {
+  i16x2 e[8], o[8];
+};
+
+__device__ __forceinline__ void spread(const uint32_t (&v)[8], Spread &s) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    s.e[k] = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(v[k], v[k], 0x0c020c00u));   // bytes 0, 2
+    s.o[k] = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(v[k], v[k], 0x0c030c01u));   // bytes 1, 3
+  }
+}
+
+// |cur - prev| > thr for the 32 pixels of a word (transposed order).  With
+// d = cur - prev, a pixel is unchanged iff d - (thr+1) and -(thr+1) - d are
+// both negative, i.e. bit 15 of their AND: pixels 0 and 2 of a dword in the
+// even product's bits 15 and 31, pixels 1 and 3 in the odd one's.  One
+// byte permute puts pixel j's flag in bit 7 of byte j, a shift by 7 - k and
+// a mask move it to bit 8j + k; the word is inverted once.
+__device__ __forceinline__ uint32_t thresh_tbits(const Spread &c, const Spread &p, i16x2 t1, i16x2 nt1) {
   uint32_t keep = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const i16x2 ce = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(c[k], c[k], 0x0c020c00u));   // bytes 0,2
-    const i16x2 co = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(c[k], c[k], 0x0c030c01u));   // bytes 1,3
-    const i16x2 pe = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(p[k], p[k], 0x0c020c00u));
-    const i16x2 po = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(p[k], p[k], 0x0c030c01u));
-    const i16x2 de = ce - pe, dd = co - po;
+    const i16x2 de = c.e[k] - p.e[k], dd = c.o[k] - p.o[k];
     const uint32_t ye = __builtin_bit_cast(uint32_t, de - t1) & __builtin_bit_cast(uint32_t, nt1 - de);
     const uint32_t yo = __builtin_bit_cast(uint32_t, dd - t1) & __builtin_bit_cast(uint32_t, nt1 - dd);
-    // unchanged flags: pixel 0 bit 15, pixel 2 bit 31 (ye); pixels 1, 3 (yo)
-    const uint32_t t = ((ye >> 15) & 0x00010001u) | ((yo >> 14) & 0x00020002u);
-    keep |= ((t | (t >> 14)) & 0xFu) << (4 * k);
+    const uint32_t g = __builtin_amdgcn_perm(yo, ye, 0x07030501u);   // ye.b1, yo.b1, ye.b3, yo.b3
+    keep |= (g >> (7 - k)) & (0x01010101u << k);
   }
   return ~keep;
 }
@@ -183,7 +218,7 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
   const bool word_in = c >= 0 && c < wpr;
   const bool out_lane = lane >= 1 && lane <= MW_CHUNK && word_in;
   const int x0 = word_in ? c * 32 : 0;
-  const uint32_t valid = (c == wpr - 1 && (W & 31)) ? ((1u << (W & 31)) - 1u) : 0xFFFFFFFFu;
+  const uint32_t valid = (c == wpr - 1 && (W & 31)) ? to_tbits((1u << (W & 31)) - 1u) : 0xFFFFFFFFu;
   const int64_t wh = (int64_t)W * H;
   const short t1s = (short)(a.thr + 1);
   const i16x2 t1 = {t1s, t1s}, nt1 = {(short)-t1s, (short)-t1s};
@@ -213,17 +248,21 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
   auto process = [&](const uint32_t (&buf)[F + 1][8], int y) {
     const bool in = y >= 0 && y < H && word_in;
     const bool e_in = y - 1 >= 0 && y - 1 < H && word_in;
+    Spread sp, sc;
+    spread(buf[0], sp);
 #pragma unroll
     for (int f = 0; f < F; ++f) {
       if (f >= nfr) break;                                  // uniform
-      const uint32_t th = thresh_bits(buf[f + 1], buf[f], t1, nt1);
+      spread(buf[f + 1], sc);
+      const uint32_t th = thresh_tbits(sc, sp, t1, nt1);
+      sp = sc;
       const uint32_t m0 = in ? (th | ~valid) : 0xFFFFFFFFu; // outside the frame: set
       // horizontal AND with the neighbour words' edge bits
       const uint32_t lw = from_lower_lane(m0), rw = from_upper_lane(m0);
-      const uint32_t hm = m0 & ((m0 << 1) | (lw >> 31)) & ((m0 >> 1) | (rw << 31));
+      const uint32_t hm = m0 & tleft(m0, lw) & tright(m0, rw);
       const uint32_t e = e_in ? (hm2[f] & hm1[f] & hm & valid) : 0u;   // e(y-1); outside: clear
       const uint32_t le = from_lower_lane(e), re = from_upper_lane(e);
-      const uint32_t he = e | ((e << 1) | (le >> 31)) | ((e >> 1) | (re << 31));
+      const uint32_t he = e | tleft(e, le) | tright(e, re);
       const uint32_t o = (he3[f] | he2[f] | he) & valid;    // o(y-2)
       const int yo = y - 2;
       if (yo >= y0 && yo < y1 && out_lane) {
@@ -296,15 +335,12 @@ __global__ __launch_bounds__(256) void k_motion_expand(MotionArgs a) {
   const int64_t wi = hw >> 1;
   const int half = (int)(hw & 1);
   const int y = (int)(wi / wpr), c = (int)(wi - (int64_t)y * wpr);
-  const uint32_t o = a.bits[j * (int64_t)H * wpr + wi] >> (16 * half);
+  const uint32_t o = a.bits[j * (int64_t)H * wpr + wi] >> (4 * half);
   const int x = c * 32 + 16 * half;
   uint8_t *dst = a.out + ((a.out_idx[1] + slot) & a.out_mask) * wh + (int64_t)y * W + x;
   uint32_t v[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t nib = (o >> (4 * k)) & 0xFu;
-    v[k] = ((nib * 0x00204081u) & 0x01010101u) * 0xFFu;  // bit i -> byte i
-  }
+  for (int k = 0; k < 4; ++k) v[k] = ((o >> k) & 0x01010101u) * 0xFFu;   // dword k: pixel 4k + j <- bit 8j + k
   if (FAST) {
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     const u32x4 val = {v[0], v[1], v[2], v[3]};
