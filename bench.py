@@ -693,7 +693,7 @@ COUNTER_GROUPS = {
     "dpd_scale": dict(
         file="k_dpd_tiled_dpd_scale_2p24_traffic.md", only="",
         title="k_dpd_tiled<16,4,10>, 2^24-sample workload (4096 firings of 4096, B 1..10, M 16)",
-        kernels=[("body", "k_dpd_tiled<16, 4, 10>",
+        kernels=[("body", "k_dpd_tiled<16, 4, 10, false>",
                   lambda b: (b["roofline"]["algorithmic_bytes_per_launch"],
                              b["roofline"]["algorithmic_flops_per_launch"]))]),
     "motion": dict(
