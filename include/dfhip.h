@@ -177,7 +177,14 @@ int64_t df_paper_channel_bytes(int64_t token_bytes, int64_t rate, int32_t has_de
 
 /* Create an empty network on HIP device `hip_device`.  `hip_stream` is a
  * hipStream_t to order all work on (e.g. torch's current stream), or NULL
- * for a library-owned stream.  *g receives the handle. */
+ * for a library-owned stream.  *g receives the handle.  Environment read
+ * here: DFHIP_CHECK_INDICES (see df_sync), DFHIP_LOG=1|2 (a stderr line per
+ * firing call and graph capture; 2 also per scan run ahead),
+ * DFHIP_TILE=tile,outputs_per_thread,blocks_per_cu (as df_set_tile),
+ * DFHIP_SCAN_AHEAD=0 (df_fire does not scan the next batch's control tokens
+ * ahead; results are the same either way), DFHIP_BODY=mx (16-tap bodies on
+ * the matrix cores: same results within the FP32 tolerance, rounded
+ * differently from the default VALU form). */
 df_status df_graph_create(df_graph **g, int hip_device, void *hip_stream);
 
 /* Synchronise, free all FIFO storage, actor state and the owned stream. */
