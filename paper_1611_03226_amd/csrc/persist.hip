@@ -2,14 +2,19 @@
 //
 // Every instance is an independent actor with its own channels, coefficients
 // and control tokens; a batch fires instance i n_i times.  The chain is
-//   prep:     exclusive scan of n_i (firing bases)
-//   scan:     per-instance control intake and branch offset scan
-//   heads:    head corrections of every firing (one wavefront each)
+//   scan:     per instance: its firing and head-pass bases (sums of n_k over
+//             the instances before it), control intake and branch offset
+//             scan
 //   order:    instances grouped by branch count, work-item bases in that order
-//   items:    one descriptor per (instance, firing, tile) work item, in
+//   heads + items (one launch): head corrections of every firing, and one
+//             descriptor per (instance, firing, tile) work item in
 //             processing order
 //   body:     a persistent grid walking the work items with a grid stride
 //   commit:   per-instance channel indices and carried branch histories
+// (five kernels: every kernel boundary costs a few microseconds.  Folding
+// the order into the scan's last workgroup was measured slower: each
+// workgroup then has to publish its tables with a device-scope release,
+// an L2 write-back here, and 1024 of those cost more than one boundary.)
 // All counts live in device memory, so the chain can be captured once in a
 // HIP graph and replayed.
 #include <hip/hip_ext.h>
@@ -82,40 +87,12 @@ struct PersArgs {
   int32_t masked;         // some instance reads bit-mask control tokens
 };
 
-// One wavefront: exclusive scans of the firing counts (firing bases) and of
-// the head-pass wavefronts (four firings each).
-__global__ __launch_bounds__(64) void k_pers_prep(PersArgs a) {
-  const int lane = threadIdx.x;
-  int64_t cf = 0, ch = 0;
-  for (int c = 0; c < a.n_inst; c += 64) {
-    const int i = c + lane;
-    const int64_t nf = i < a.n_inst ? a.n_fire[i] : 0;
-    const int64_t nh = (nf + 3) / 4;
-    int64_t sf = nf, sh = nh;                      // inclusive wave scans
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int64_t uf = __shfl_up(sf, d), uh = __shfl_up(sh, d);
-      if (lane >= d) sf += uf, sh += uh;
-    }
-    if (i < a.n_inst) {
-      a.fire_base[i] = cf + sf - nf;
-      a.head_base[i] = ch + sh - nh;
-    }
-    cf += __shfl(sf, 63);
-    ch += __shfl(sh, 63);
-  }
-  if (lane == 0) {
-    a.fire_base[a.n_inst] = cf;
-    a.head_base[a.n_inst] = ch;
-  }
-}
-
 // Processing order of the instances, grouped by the Horner length of their
 // first firing's branch set (largest first), and the work-item bases in that
 // order.  The
 // body compiles one unrolled code path per branch count; grouping keeps the
 // workgroups resident on a compute unit on few paths (instruction cache).
-// The order never changes a result.
+// The order never changes a result.  One workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_pers_order(PersArgs a) {
   __shared__ int32_t hist[kMaxBranches + 1], cursor[kMaxBranches + 1];
   __shared__ int64_t wsum[16];
@@ -163,16 +140,10 @@ __global__ __launch_bounds__(1024) void k_pers_order(PersArgs a) {
   if (threadIdx.x == 0) a.tile_base[a.n_inst] = carry;
 }
 
-// One workgroup per instance, one wavefront per branch (as the single-actor
-// scan): validated control tokens, history source firings, last feeders.
-__global__ __launch_bounds__(1024) void k_pers_scan(PersArgs a) {
-  const int i = blockIdx.x;
-  const int b = threadIdx.x >> 6;
+// Branch b's part of instance i's scan (one wavefront).
+__device__ void pers_scan_branch(const PersArgs &a, const InstDesc &d, int i, int b, int64_t n, int64_t base,
+                                 int64_t hbase) {
   const int lane = threadIdx.x & 63;
-  const InstDesc &d = a.inst[i];
-  if (b >= d.B_max) return;
-  const int64_t n = a.n_fire[i];
-  const int64_t base = a.fire_base[i];
   const int64_t R = d.ctrl_idx[0];
   const uint64_t below_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
   int64_t lastw = -1;
@@ -194,14 +165,49 @@ __global__ __launch_bounds__(1024) void k_pers_scan(PersArgs a) {
   }
   if (lane == 0) a.last_all[(int64_t)i * a.Bg + b] = lastw;
   if (b == 0)
-    for (int64_t k = lane; k < (n + 3) / 4; k += 64) a.head_inst[a.head_base[i] + k] = i;
+    for (int64_t k = lane; k < (n + 3) / 4; k += 64) a.head_inst[hbase + k] = i;
+}
+
+// One workgroup per instance, one wavefront per branch (as the single-actor
+// scan): validated control tokens, history source firings, last feeders.
+// The workgroup first sums the firing counts of the instances before it
+// (its firing base, and its first head-pass wavefront: four firings each).
+__global__ __launch_bounds__(1024) void k_pers_scan(PersArgs a) {
+  __shared__ int64_t part[2][16];
+  const int i = blockIdx.x;
+  const int b = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const InstDesc &d = a.inst[i];
+  int64_t sf = 0, sh = 0;
+  for (int k = threadIdx.x; k < i; k += blockDim.x) {
+    const int64_t nf = a.n_fire[k];
+    sf += nf;
+    sh += (nf + 3) / 4;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sf += __shfl_xor(sf, o), sh += __shfl_xor(sh, o);
+  if (lane == 0) part[0][b] = sf, part[1][b] = sh;
+  __syncthreads();
+  int64_t base = 0, hbase = 0;
+  for (int w = 0; w < nw; ++w) base += part[0][w], hbase += part[1][w];
+  const int64_t n = a.n_fire[i];
+  if (threadIdx.x == 0) {
+    a.fire_base[i] = base;
+    a.head_base[i] = hbase;
+    if (i == a.n_inst - 1) {
+      a.fire_base[a.n_inst] = base + n;
+      a.head_base[a.n_inst] = hbase + (n + 3) / 4;
+    }
+  }
+  if (b < d.B_max) pers_scan_branch(a, d, i, b, n, base, hbase);
 }
 
 // Work-item descriptors: item k (processing order) -> the last ordered
-// instance whose tile base is <= k, its firing and tile.
-__global__ __launch_bounds__(256) void k_pers_items(PersArgs a) {
+// instance whose tile base is <= k, its firing and tile.  Workgroup blk of
+// nblk (256 threads each) strides over the items.
+__device__ __forceinline__ void pers_items(const PersArgs &a, int64_t blk, int64_t nblk) {
   const int64_t total = a.tile_base[a.n_inst];
-  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < total; it += (int64_t)gridDim.x * 256) {
+  for (int64_t it = blk * 256 + threadIdx.x; it < total; it += nblk * 256) {
     int lo = 0, hi = a.n_inst - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -260,15 +266,20 @@ struct ItemSrc {
 // Head corrections of all instances' firings: one wavefront per four
 // consecutive firings of one instance (rows), from the head-pass map.  The
 // number of such wavefronts is read from the device (head_base[n_inst],
-// written by k_pers_prep), and a fixed grid walks them with a stride, so
-// the launch does not depend on the batch's firing counts.
+// written by the scan), and a fixed grid walks them with a stride, so the
+// launch does not depend on the batch's firing counts.  The first
+// head_blocks workgroups do that; the others write the work items.
 template <int M>
 __device__ __forceinline__ void pers_head(const PersArgs &a, int64_t w);
 
 template <int M>
-__global__ __launch_bounds__(256) void k_pers_heads(PersArgs a) {
+__global__ __launch_bounds__(256) void k_pers_heads_items(PersArgs a, int head_blocks) {
+  if ((int)blockIdx.x >= head_blocks) {
+    pers_items(a, blockIdx.x - head_blocks, gridDim.x - head_blocks);
+    return;
+  }
   const int64_t n_heads = as_const(a.head_base)[a.n_inst];
-  const int64_t stride = (int64_t)gridDim.x * 4;
+  const int64_t stride = (int64_t)head_blocks * 4;
   for (int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); w < n_heads;
        w += stride)                                   // uniform per wavefront
     pers_head<M>(a, w);
@@ -417,25 +428,23 @@ static hipError_t launch_pers_body_mx(const PersArgs &a, int threads, int blocks
 }
 
 static hipError_t enqueue_chain(Persistent *p, const PersArgs &a, hipStream_t s, df_graph *prof_g) {
-  hipLaunchKernelGGL(k_pers_prep, dim3(1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_pers_scan, dim3(a.n_inst), dim3(64 * a.Bg), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pers_scan, dim3(a.n_inst), dim3(64 * a.Bg), 0, s, a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  {
-    // a grid that covers the head-pass capacity in one sweep, at most a few
-    // workgroups per compute unit (the kernel strides over the device count)
-    const int64_t want = (p->heads_cap + 3) / 4;
-    const dim3 hg((unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 8 * p->ncu)));
-    if (p->M == 16) hipLaunchKernelGGL(k_pers_heads<16>, hg, dim3(256), 0, s, a);
-    else if (p->M == 8) hipLaunchKernelGGL(k_pers_heads<8>, hg, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_pers_heads<4>, hg, dim3(256), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
   hipLaunchKernelGGL(k_pers_order, dim3(1), dim3(1024), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pers_items, dim3(4 * p->ncu), dim3(256), 0, s, a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  {
+    // head pass: a grid that covers the head-pass capacity in one sweep, at
+    // most a few workgroups per compute unit (it strides over the device
+    // count); work items: four workgroups per compute unit
+    const int64_t want = (p->heads_cap + 3) / 4;
+    const int hb = (int)std::max<int64_t>(1, std::min<int64_t>(want, 8 * p->ncu));
+    const dim3 grid((unsigned)(hb + 4 * p->ncu));
+    if (p->M == 16) hipLaunchKernelGGL(k_pers_heads_items<16>, grid, dim3(256), 0, s, a, hb);
+    else if (p->M == 8) hipLaunchKernelGGL(k_pers_heads_items<8>, grid, dim3(256), 0, s, a, hb);
+    else hipLaunchKernelGGL(k_pers_heads_items<4>, grid, dim3(256), 0, s, a, hb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const int threads = p->tile / p->K;
   const int blocks = p->bpc * p->ncu;
   KTiming kt;
