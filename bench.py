@@ -710,7 +710,7 @@ COUNTER_GROUPS = {
     "adaptation": dict(
         file="k_adj_partial_adaptation_64x65536_counters.md", only="adaptation",
         title="coefficient adjoint, 64 streams x 65536 samples, 10 branches x 16 taps",
-        kernels=[("coeff_adjoint", "k_adj_partial<10>",
+        kernels=[("coeff_adjoint", "k_adj_partial<10, 4>",
                   lambda b: (b["adaptation"]["coeff_adjoint_algorithmic_bytes"],
                              b["adaptation"]["coeff_adjoint_algorithmic_flops"]))]),
     "md_paper": dict(

@@ -210,9 +210,10 @@ struct AdjArgs {
   int64_t r;
   int32_t B_max;
   int32_t M;
-  int32_t chunk;          // outputs per workgroup
-  int32_t chunks_per_firing;
-  float2 *partial;        // [n_firings*chunks_per_firing][B_max][M]
+  int32_t chunk;          // outputs staged in LDS at a time (set by launch_adj)
+  int32_t span;           // outputs per workgroup (chunks processed in turn)
+  int32_t blocks_per_firing;
+  float2 *partial;        // [B_max][M][n_firings*blocks_per_firing]
   float2 *grad;           // [B_max][M]
 };
 

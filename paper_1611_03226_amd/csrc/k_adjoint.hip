@@ -26,106 +26,161 @@ __device__ __forceinline__ int64_t adj_prev(const AdjArgs &a, int b, int64_t g) 
   return (g % a.seg_firings) ? g - 1 : -1;
 }
 
-// One workgroup per (firing, chunk of outputs); one wavefront per group of 4
-// taps; lane l of a wavefront takes input samples s = l, l+64, ... of the
-// chunk's window.  For its sample a lane forms p^b once and accumulates
-// G[s+m] conj(x_s) p^b into 4 taps x BM branches of independent registers;
-// the wavefront then reduces over lanes (fixed shuffle order).
-// One reduce-scatter step of the lane butterfly: lanes with bit 2*HALF set
-// keep the upper HALF values, the others the lower HALF, each adding the
-// partner's copy of the kept half.
-template <int HALF>
-__device__ __forceinline__ void butterfly_step(float (&v)[32], int lane) {
-  constexpr int off = 2 * HALF;
-  const bool upper = (lane & off) != 0;
+// Lane reduce-scatter of N values per lane over the 64 lanes of a
+// wavefront, in six steps; step k pairs each lane with a partner that
+// differs in lane bit 32 >> k (and agrees in the bits split before): the
+// lane with that bit set keeps the upper half of its values (padded to an
+// even count with zeros), the other the lower half, each adding the
+// partner's copy.  Steps 0 and 1 pair lanes 32 and 16 apart with the
+// permlane swaps (a swap and an add per kept value); steps 2..5 use the
+// DPP row mirror (lane 15 - l), half-row mirror (7 - l) and quad
+// permutations (l ^ 2, l ^ 1) as partners (two selects and an add).  The
+// partners' lane masks 32, 16, 15, 7, 2, 1 are independent, so after the
+// six steps every kept value is summed over all 64 lanes exactly once, in
+// a fixed order.
+constexpr int rs_half(int n) { return (n + 1) / 2; }
+
+template <int STEP, int N, int CAP>
+__device__ __forceinline__ void rs_steps(float (&v)[CAP], int lane) {
+  constexpr int H = rs_half(N);
 #pragma unroll
-  for (int i = 0; i < HALF; ++i) {
-    const float send = upper ? v[i] : v[i + HALF];
-    const float keep = upper ? v[i + HALF] : v[i];
-    v[i] = keep + __shfl_xor(send, off);
+  for (int i = 0; i < H; ++i) {
+    const float lo = v[i];
+    const float hi = i + H < N ? v[i + H] : 0.f;
+    if constexpr (STEP < 2) {
+      const auto sw = STEP == 0 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false)
+                                : __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+      v[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+    } else {
+      constexpr int ctrl = STEP == 2 ? 0x140 : STEP == 3 ? 0x141 : STEP == 4 ? 0x4E : 0xB1;
+      const bool up = (lane & (32 >> STEP)) != 0;
+      const float send = up ? lo : hi, keep = up ? hi : lo;
+      v[i] = keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), ctrl, 0xF, 0xF, false));
+    }
   }
-  if constexpr (HALF > 1) butterfly_step<HALF / 2>(v, lane);
+  if constexpr (STEP < 5) rs_steps<STEP + 1, H>(v, lane);
 }
 
-template <int BM>
-__global__ __launch_bounds__(512) void k_adj_partial(AdjArgs a) {
+// Values a lane holds after the six steps, and the original index of its
+// j-th one (-1 for padding).
+template <int N>
+struct RsPlan {
+  static constexpr int n0 = N, n1 = rs_half(n0), n2 = rs_half(n1), n3 = rs_half(n2), n4 = rs_half(n3),
+                       n5 = rs_half(n4), kept = rs_half(n5);
+  __device__ static int index(int j, int lane) {
+    const int cnt[6] = {n0, n1, n2, n3, n4, n5};
+    int t = j;
+    bool ok = true;
+    for (int k = 5; k >= 0; --k) {
+      if (lane & (32 >> k)) t += rs_half(cnt[k]);
+      ok = ok && t < cnt[k];
+    }
+    return ok ? t : -1;
+  }
+};
+
+// Taps per wavefront of the coefficient adjoint for BM branches (8 taps,
+// with twice the accumulators and half the wavefronts per SIMD, measured
+// slower at 10 branches).
+constexpr int adj_tpw(int) { return 4; }
+
+// One workgroup per (firing, span of input samples); one wavefront per
+// group of TPW taps.  Every (sample, output) pair with the output in the
+// firing is counted by the workgroup that owns the sample (pairs with a
+// sample before the firing start are added at the end from the branch
+// histories).  The span is processed in chunks of four samples per thread
+// staged in LDS with the G values of the outputs they reach, and lane l of
+// a wavefront takes samples l, l+64, ... of each chunk.  For its sample a
+// lane forms p^b once and accumulates G[s+m] conj(x_s) p^b into TPW taps x
+// BM branches of independent registers; after the span the wavefront
+// reduces over lanes (fixed order).  The next chunk's loads are in flight
+// (in registers) while the current one is processed; a chunk's G window
+// starts with the last M+TPW-2 values of the previous one.
+template <int BM, int TPW>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(BM <= 10 ? 4 : 1))) void k_adj_partial(
+    AdjArgs a) {
   extern __shared__ float2 lds[];
   const int M = a.M;
-  const int64_t g = blockIdx.x / a.chunks_per_firing;
-  const int64_t c = blockIdx.x - g * a.chunks_per_firing;
-  const int64_t n0 = c * a.chunk;
-  const int nout = (int)min((int64_t)a.chunk, a.r - n0);
+  const int64_t g = blockIdx.x / a.blocks_per_firing;
+  const int64_t c = blockIdx.x - g * a.blocks_per_firing;
+  const int64_t s0 = c * a.span;
+  const int64_t s1 = min(s0 + a.span, a.r);
   const uint32_t set = a.B ? (uint32_t)a.B[g] : prefix_set(BM);
   const int B = set_len(set);
   const int64_t xb = g * a.r;
-  // G of the chunk's outputs, staged with M-1 zeros before and M+2 after, so
-  // that every (sample, tap) pair of the loop below reads a defined value
-  // (zero where the output lies outside the chunk, or the tap past M in the
-  // last wavefront's group of 4) and the loop carries no bounds checks
-  const int gpad = M - 1, gpost = M + 2;
-  float2 *sx = lds;                       // window: nout + M - 1 samples
-  float2 *sg = lds + a.chunk + M - 1 + gpad;
-  float2 *red = sg + a.chunk + gpost;     // [BM][M] reduced sums
-  for (int i = threadIdx.x; i < nout + M - 1; i += blockDim.x) {
-    const int64_t pos = n0 - (M - 1) + i;
-    sx[i] = pos >= 0 ? a.x[xb + pos] : make_float2(0.f, 0.f);
-  }
-  for (int i = threadIdx.x - gpad; i < nout + gpost; i += blockDim.x)
-    sg[i] = (i >= 0 && i < nout) ? a.G[xb + n0 + i] : make_float2(0.f, 0.f);
-  __syncthreads();
+  // chunk of C samples at n0: sx[i] = x[n0+i] (zero past the span), sg[o] =
+  // G[n0+o] for o < C+K (zero past the firing); K = M+TPW-2 covers the taps
+  // of the last wavefront's group past M, whose sums are dropped
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const int C = a.chunk;                  // 4 * nt, a multiple of 64
+  const int K = M + TPW - 2;
+  float2 *sx = lds;
+  float2 *sg = lds + C;
+  float2 *red = sg + C + K;               // [BM][M] reduced sums
   const int lane = threadIdx.x & 63;
-  const int m0 = (threadIdx.x >> 6) * 4;  // first tap of this wavefront
-  float accr[4][BM], acci[4][BM];
+  const int m0 = (threadIdx.x >> 6) * TPW;  // first tap of this wavefront
+  constexpr int NV = 2 * TPW * BM;        // TPW taps x BM branches x (re, im)
+  float v[NV];                            // v[q*2BM + 2b + c]
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int i = 0; i < NV; ++i) v[i] = 0.f;
+  float2 carry = make_float2(0.f, 0.f);   // sg[tid] (tid < K) of the next chunk
+  if (tid < K && s0 + tid < a.r) carry = a.G[xb + s0 + tid];
+  float2 rx[4], rg[4];                    // the next chunk's x[n0 + j*nt + tid], G[n0 + K + j*nt + tid]
+  const auto fetch = [&](int64_t n0) {
 #pragma unroll
-    for (int b = 0; b < BM; ++b) accr[q][b] = acci[q][b] = 0.f;
-  // window index i <-> input sample n0-(M-1)+i; output n = sample + m
-  for (int i = lane; i < nout + M - 1; i += 64) {
-    const float2 xv = sx[i];
-    const float p = fmaf(xv.x, xv.x, xv.y * xv.y);
-    float pw[BM];
-    pw[0] = 1.f;
+    for (int j = 0; j < 4; ++j) {
+      const int64_t n = n0 + j * nt + tid;
+      rx[j] = n < s1 ? a.x[xb + n] : make_float2(0.f, 0.f);
+      rg[j] = n + K < a.r ? a.G[xb + n + K] : make_float2(0.f, 0.f);
+    }
+  };
+  fetch(s0);
+  for (int64_t n0 = s0; n0 < s1; n0 += C) {
+    if (tid < K) sg[tid] = carry;
 #pragma unroll
-    for (int b = 1; b < BM; ++b) pw[b] = pw[b - 1] * p;
+    for (int j = 0; j < 4; ++j) {
+      sx[j * nt + tid] = rx[j];
+      sg[K + j * nt + tid] = rg[j];
+    }
+    __syncthreads();
+    if (n0 + C < s1) fetch(n0 + C);
+    // sample n0 + i, output n0 + i + m
+#pragma unroll 2
+    for (int i = lane; i < C; i += 64) {
+      const float2 xv = sx[i];
+      const float p = fmaf(xv.x, xv.x, xv.y * xv.y);
+      float pw[BM];
+      pw[0] = 1.f;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      // output index within the chunk: -(M-1) <= o < nout + M + 2 (zeros outside)
-      const int o = i - (M - 1) + m0 + q;
-      const float2 gv = sg[o];
-      const float zr = fmaf(gv.x, xv.x, gv.y * xv.y);     // G conj(x)
-      const float zi = fmaf(gv.y, xv.x, -(gv.x * xv.y));
+      for (int b = 1; b < BM; ++b) pw[b] = pw[b - 1] * p;
 #pragma unroll
-      for (int b = 0; b < BM; ++b) {
-        accr[q][b] = fmaf(zr, pw[b], accr[q][b]);
-        acci[q][b] = fmaf(zi, pw[b], acci[q][b]);
+      for (int q = 0; q < TPW; ++q) {
+        const float2 gv = sg[i + m0 + q];
+        const float zr = fmaf(gv.x, xv.x, gv.y * xv.y);     // G conj(x)
+        const float zi = fmaf(gv.y, xv.x, -(gv.x * xv.y));
+#pragma unroll
+        for (int b = 0; b < BM; ++b) {
+          v[q * 2 * BM + 2 * b] = fmaf(zr, pw[b], v[q * 2 * BM + 2 * b]);
+          v[q * 2 * BM + 2 * b + 1] = fmaf(zi, pw[b], v[q * 2 * BM + 2 * b + 1]);
+        }
       }
     }
+    if (tid < K) carry = sg[C + tid];    // read before anyone rewrites the window
+    __syncthreads();
   }
-  // Lane sums of the 2*BM values of each tap by a butterfly reduce-scatter
-  // (fixed order): every step halves the values a lane holds, exchanging
-  // the other half with the lane `off` apart; after the steps 32..2 lane l
-  // holds value 16*b5 + 8*b4 + 4*b3 + 2*b2 + b1 (bits of l), summed over the
-  // lanes that share bit 0, and a last exchange adds the pair.
+  rs_steps<0, NV>(v, lane);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    float v[32];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] = i < 2 * BM ? ((i & 1) ? acci[q][i >> 1] : accr[q][i >> 1]) : 0.f;
-    butterfly_step<16>(v, lane);
-    const float tot = v[0] + __shfl_xor(v[0], 1);
-    const int idx = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
-                    ((lane >> 1) & 1);
-    if ((lane & 1) == 0 && idx < 2 * BM && m0 + q < M) {
-      float *dst = reinterpret_cast<float *>(&red[(idx >> 1) * M + m0 + q]);
-      dst[idx & 1] = tot;
-    }
+  for (int j = 0; j < RsPlan<NV>::kept; ++j) {
+    const int idx = RsPlan<NV>::index(j, lane);
+    if (idx < 0) continue;
+    const int q = idx / (2 * BM), rem = idx - q * 2 * BM;
+    if (m0 + q < M) reinterpret_cast<float *>(&red[(rem >> 1) * M + m0 + q])[rem & 1] = v[j];
   }
   // taps before the firing start read branch b's history source: the last
   // M-1 samples of its previous feeding firing (zeros if none), staged in
   // LDS by all threads at once
   float2 *hx = red + BM * M;              // [BM][M-1]
-  if (n0 == 0) {
+  if (s0 == 0) {
     for (int t = threadIdx.x; t < B * (M - 1); t += blockDim.x) {
       const int b = t / (M - 1), i = t - b * (M - 1);
       const int64_t pf = adj_prev(a, b, g);
@@ -139,57 +194,78 @@ __global__ __launch_bounds__(512) void k_adj_partial(AdjArgs a) {
     if (in_set(set, b)) {
       sr = red[t].x;
       si = red[t].y;
-      if (n0 == 0) {
+      if (s0 == 0) {
         // output i, tap mm reads history sample i - mm (< 0)
-        for (int i = 0; i < mm && i < nout; ++i) {
+        for (int i = 0; i < mm && i < a.r; ++i) {
           const float2 xv = hx[b * (M - 1) + (M - 1) + i - mm];
           const float pp = fmaf(xv.x, xv.x, xv.y * xv.y);
           float pb = 1.f;
           for (int e = 0; e < b; ++e) pb *= pp;
-          const float2 gv = sg[i];
+          const float2 gv = a.G[xb + i];
           const float xr = pb * xv.x, xi = pb * xv.y;
           sr += gv.x * xr + gv.y * xi;
           si += gv.y * xr - gv.x * xi;
         }
       }
     }
-    a.partial[(int64_t)blockIdx.x * a.B_max * M + t] = make_float2(sr, si);
+    a.partial[(int64_t)t * gridDim.x + blockIdx.x] = make_float2(sr, si);
   }
 }
 
-// grad_h[b][m] = fp64 sum of the workgroup partials, fixed order.
-__global__ __launch_bounds__(256) void k_adj_reduce(const float2 *partial, int64_t n_blocks, int BM_stride,
-                                                    float2 *grad) {
-  __shared__ double sr[256], si[256];
+// grad_h[b][m] = fp64 sum of the workgroup partials (stored [b][m][block]),
+// fixed order: one workgroup per (b, m); thread t sums blocks t, t+256, ...,
+// then a butterfly over each wavefront's lanes and the four wavefronts in
+// order.
+__global__ __launch_bounds__(256) void k_adj_reduce(const float2 *partial, int64_t n_blocks, float2 *grad) {
+  __shared__ double wr[4], wi[4];
   const int e = blockIdx.x;               // b * M + m
+  const float2 *src = partial + (int64_t)e * n_blocks;
   double ar = 0.0, ai = 0.0;
-  for (int64_t k = threadIdx.x; k < n_blocks; k += 256) {
-    const float2 v = partial[k * BM_stride + e];
+  int64_t k = threadIdx.x;
+  for (; k + 768 < n_blocks; k += 1024) {  // four loads in flight
+    const float2 v0 = src[k], v1 = src[k + 256], v2 = src[k + 512], v3 = src[k + 768];
+    ar += v0.x;
+    ai += v0.y;
+    ar += v1.x;
+    ai += v1.y;
+    ar += v2.x;
+    ai += v2.y;
+    ar += v3.x;
+    ai += v3.y;
+  }
+  for (; k < n_blocks; k += 256) {
+    const float2 v = src[k];
     ar += v.x;
     ai += v.y;
   }
-  sr[threadIdx.x] = ar;
-  si[threadIdx.x] = ai;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sr[threadIdx.x] += sr[threadIdx.x + s];
-      si[threadIdx.x] += si[threadIdx.x + s];
-    }
-    __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    ar += __shfl_xor(ar, o);
+    ai += __shfl_xor(ai, o);
   }
-  if (threadIdx.x == 0) grad[e] = make_float2((float)sr[0], (float)si[0]);
+  if ((threadIdx.x & 63) == 0) wr[threadIdx.x >> 6] = ar, wi[threadIdx.x >> 6] = ai;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    grad[e] = make_float2((float)(((wr[0] + wr[1]) + wr[2]) + wr[3]), (float)(((wi[0] + wi[1]) + wi[2]) + wi[3]));
 }
 
 hipError_t launch_adj(const AdjArgs &a, hipStream_t s) {
-  const int64_t blocks = a.n_firings * a.chunks_per_firing;
+  const int64_t blocks = a.n_firings * a.blocks_per_firing;
   if (blocks > 0) {
-    const int threads = 64 * ((a.M + 3) / 4);          // one wavefront per 4 taps
-    const size_t lds = sizeof(float2) * ((size_t)2 * a.chunk + a.M - 1 + (a.M - 1) + (a.M + 2) +
-                                         (size_t)a.B_max * (2 * a.M - 1));
+    // one wavefront per adj_tpw(B_max) taps; chunks of four samples per
+    // thread; LDS: samples, G window, reduced sums, history samples
+    AdjArgs b = a;
+    const auto lds_of = [&](int threads, int tpw) {
+      b.chunk = 4 * threads;
+      return sizeof(float2) * ((size_t)2 * b.chunk + (a.M + tpw - 2) + (size_t)a.B_max * (2 * a.M - 1));
+    };
     switch (a.B_max) {
-#define DF_CASE(n) \
-  case n: hipLaunchKernelGGL(k_adj_partial<n>, dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
+#define DF_CASE(n)                                                                                  \
+  case n: {                                                                                         \
+    const int threads = 64 * ((a.M + adj_tpw(n) - 1) / adj_tpw(n));                                 \
+    const size_t lds = lds_of(threads, adj_tpw(n));                                                 \
+    hipLaunchKernelGGL((k_adj_partial<n, adj_tpw(n)>), dim3((unsigned)blocks), dim3(threads), lds, s, b); \
+  } break;
       DF_CASE(1) DF_CASE(2) DF_CASE(3) DF_CASE(4) DF_CASE(5) DF_CASE(6) DF_CASE(7) DF_CASE(8)
       DF_CASE(9) DF_CASE(10) DF_CASE(11) DF_CASE(12) DF_CASE(13) DF_CASE(14) DF_CASE(15) DF_CASE(16)
 #undef DF_CASE
@@ -198,8 +274,7 @@ hipError_t launch_adj(const AdjArgs &a, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_adj_reduce, dim3(a.B_max * a.M), dim3(256), 0, s, a.partial, blocks, a.B_max * a.M,
-                     a.grad);
+  hipLaunchKernelGGL(k_adj_reduce, dim3(a.B_max * a.M), dim3(256), 0, s, a.partial, blocks, a.grad);
   return hipGetLastError();
 }
 

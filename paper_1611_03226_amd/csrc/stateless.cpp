@@ -71,7 +71,9 @@ void free_tables(Tables *t, hipStream_t s) {
 }
 
 // outputs per adjoint workgroup (2048 balances the lane reduction against occupancy)
-int adj_chunk(int64_t r) { return (int)std::min<int64_t>(2048, r); }
+// Outputs per workgroup of the coefficient adjoint (processed in staged
+// chunks; the span sets how many samples each lane reduction serves).
+int adj_span(int64_t r) { return (int)std::min<int64_t>(2 * 2048, r); }
 
 }  // namespace
 
@@ -227,9 +229,9 @@ extern "C" int64_t df_dpd_coeff_adjoint_work_bytes(int64_t S, int64_t len, int64
   // Same firing decomposition as df_dpd_coeff_adjoint with explicit control
   // (the all-active case needs no more).
   const int64_t nf = len / r;
-  const int c1 = adj_chunk(r);
+  const int c1 = adj_span(r);
   const int64_t blocks_ctrl = S * nf * ((r + c1 - 1) / c1);
-  const int c2 = adj_chunk(len);
+  const int c2 = adj_span(len);
   const int64_t blocks_all = S * ((len + c2 - 1) / c2);
   return std::max(blocks_ctrl, blocks_all) * B_max * M * (int64_t)sizeof(float2);
 }
@@ -256,14 +258,14 @@ extern "C" df_status df_dpd_coeff_adjoint(void *stream, const void *x, const int
   hipError_t e = hipSuccess;
   if (S == 0 || len == 0) {
     a.n_firings = 0;
-    a.chunks_per_firing = 1;
+    a.blocks_per_firing = 1;
     e = launch_adj(a, s);
   } else if (!ctrl) {
     a.seg_firings = 1;
     a.n_firings = S;
     a.r = len;
-    a.chunk = adj_chunk(len);
-    a.chunks_per_firing = (int32_t)((len + a.chunk - 1) / a.chunk);
+    a.span = adj_span(len);
+    a.blocks_per_firing = (int32_t)((len + a.span - 1) / a.span);
     e = launch_adj(a, s);
   } else {
     const int64_t nf = len / r;
@@ -275,8 +277,8 @@ extern "C" df_status df_dpd_coeff_adjoint(void *stream, const void *x, const int
       a.seg_firings = nf;
       a.n_firings = S * nf;
       a.r = r;
-      a.chunk = adj_chunk(r);
-      a.chunks_per_firing = (int32_t)((r + a.chunk - 1) / a.chunk);
+      a.span = adj_span(r);
+      a.blocks_per_firing = (int32_t)((r + a.span - 1) / a.span);
       e = launch_adj(a, s);
     }
     free_tables(&t, s);

@@ -76,9 +76,10 @@ def test_stateless_null_pointers_and_work_size():
     assert lib.df_dpd_forward(None, None, None, None, None, 2, 64, 8, 4, 4, 0) == D.DF_EINVAL
     assert lib.df_mp_input_adjoint(None, None, None, None, None, 2, 64, 4, 4) == D.DF_EINVAL
     assert lib.df_mp_input_adjoint(None, None, None, None, None, 2, 64, 0, 4) == D.DF_EINVAL
-    # work: one fp32 complex partial per (workgroup, branch, tap); 2048-sample chunks
+    # work: one fp32 complex partial per (workgroup, branch, tap); a workgroup
+    # takes 4096 outputs of a firing
     wb = D.df_dpd_coeff_adjoint_work_bytes(64, 65536, 65536, 10, 16)
-    assert wb == 64 * 32 * 10 * 16 * 8
+    assert wb == 64 * 16 * 10 * 16 * 8
     wb2 = D.df_dpd_coeff_adjoint_work_bytes(2, 4096, 256, 4, 8)
     assert wb2 == 2 * 16 * 1 * 4 * 8 * 8
     assert lib.df_dpd_coeff_adjoint(None, None, None, None, None, 2, 4096, 256, 4, 8, 0, None, 0) == D.DF_EINVAL
