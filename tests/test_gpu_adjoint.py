@@ -120,11 +120,13 @@ def test_coefficient_adjoint_matches_fp64_adjoint(with_ctrl, hist):
 
 
 @pytest.mark.parametrize("B,M,r,with_ctrl", [(1, 4, 256, True), (5, 8, 512, True), (16, 16, 1024, True),
-                                              (3, 5, 300, True), (7, 13, 2100, False), (16, 32, 640, True)])
+                                              (3, 5, 300, True), (7, 13, 2100, False), (16, 32, 640, True),
+                                              (10, 16, 9000, True), (4, 7, 5000, True)])
 def test_coefficient_adjoint_shapes(B, M, r, with_ctrl):
     """Branch and tap counts away from (10, 16): one branch, B_max 16, taps
-    not a multiple of 4 (a partly used wavefront), ragged chunks; per branch
-    against the FP64 adjoint."""
+    not a multiple of 4 (a partly used wavefront), ragged chunks, firings
+    longer than a workgroup's 4096-sample span (pairs across span ends,
+    branch histories); per branch against the FP64 adjoint."""
     import torch
     from paper_1611_03226_amd import dfhip as D
     say(f"coeff adjoint B={B} M={M} r={r} ctrl={with_ctrl}")

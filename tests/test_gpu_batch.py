@@ -105,6 +105,25 @@ def test_wide_branch_counts_match_oracle(M):
             assert np.array_equal(a.view(np.float32), b.view(np.float32)), mode
 
 
+def test_more_instances_than_a_workgroup_with_one_branch():
+    """1300 single-branch instances: the persistent scan runs one wavefront
+    per instance and sums more firing counts than it has threads, the order
+    pass loops over the instances; graph replay == per-actor launches bit
+    for bit, sampled instances against the oracle."""
+    r = 64
+    insts = _instances(71, 1300, r, 2, M=8, B_range=(1, 1))
+    res = {}
+    for mode in ("many", "graph"):
+        say(f"1300 instances {mode}")
+        res[mode] = _run(insts, r, mode, 2)
+    for a, b in zip(res["many"], res["graph"]):
+        assert np.array_equal(a.view(np.float32), b.view(np.float32))
+    for d, y in list(zip(insts, res["graph"]))[::97]:
+        ref = odpd.run_dpd(d["x"][:len(y)], d["ctrl"][:len(y) // r], d["h"], r, hist=d["hist"])
+        worst, _, bad0 = rel_rms_per_firing(y, ref, r)
+        assert worst <= DPD_TOL and bad0 == 0
+
+
 @pytest.mark.parametrize("tile", [(512, 4, 2), (2048, 8, 1), (256, 4, 8), (1024, 8, 4)])
 def test_tile_configurations_are_bit_identical(tile):
     r = 1024
