@@ -835,6 +835,10 @@ STATS_RUNS = {
                "motion (300 x 1920x1080), mask tokens at scale, 1024 lognormal DPD instances (persistent / "
                "graph / per-actor), adaptation step; plus the main line at 3 batches",
                "--no-cpu --no-per-firing --only motion,dpd_mask,instances,adaptation --steps 3 --warmup 1"),
+    "dpd_network": ("dpd_network_scale_kernel_stats.md",
+                    "predistortion at scale (2^24 samples, 4096 firings of 4096, B 1..10, M 16) as the Poly -> "
+                    "FIR_b -> Adder network with materialised branch channels, beside the fused stateless body",
+                    "--no-cpu --no-per-firing --only dpd_network --steps 5 --warmup 2"),
     "md_paper": ("md_paper_pipeline_kernel_stats.md",
                  "paper motion-detection pipeline, 4096 frames of 320x240 per step (three actors and fused), "
                  "5 timed + 2 warm-up steps; plus the main line",

@@ -49,7 +49,8 @@ def test_chain_workload_matches_oracle():
     assert worst <= DPD_TOL and bad_zero == 0
 
 
-@pytest.mark.parametrize("S,nf,r,B,M", [(3, 9, 64, 10, 16), (2, 17, 7, 4, 8), (1, 5, 3, 16, 4), (4, 3, 32, 1, 1)])
+@pytest.mark.parametrize("S,nf,r,B,M", [(3, 9, 64, 10, 16), (2, 17, 7, 4, 8), (1, 5, 3, 16, 4), (4, 3, 32, 1, 1),
+                                       (2, 4, 1500, 5, 32)])
 def test_ragged_rows_match_oracle_and_fused_body(S, nf, r, B, M):
     say(f"dpd network: S={S} nf={nf} r={r} B={B} M={M}")
     rng = np.random.default_rng(S * 1000 + nf * 10 + r)
