@@ -180,7 +180,8 @@ struct MotionArgs {
   const uint8_t *prev;    // ring of frames (two-channel form) or nullptr
   const int64_t *prev_idx;
   int64_t prev_mask;
-  const uint8_t *state;   // previous frame (self-delay form)
+  uint8_t *state;         // previous frame (self-delay form)
+  const uint8_t *state_src;  // the batch's last input frame, copied to state by the emit pass (or nullptr)
   uint8_t *out;           // mask ring
   const int64_t *out_idx;
   int64_t out_mask;

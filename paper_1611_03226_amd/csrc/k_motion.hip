@@ -321,9 +321,23 @@ __global__ __launch_bounds__(64) void k_motion_bits(MotionArgs a, int rows, int 
 // Expand the bit-packed mask of every emitted frame to 0/255 bytes at the
 // frame's output slot.  One thread per 16-pixel half word, so the lanes of a
 // wavefront store one contiguous 1 KiB span per instruction.
+// The same pass leaves the batch's counts at zero for the next batch (the
+// emit scan has read them) and, with state_src set, copies the batch's last
+// frame to the self-delay state (grid row n: 16 bytes per thread; nothing in
+// this pass reads the frames or the state).
 template <bool FAST>
 __global__ __launch_bounds__(256) void k_motion_expand(MotionArgs a) {
   const int64_t j = blockIdx.y;
+  if (j == a.n) {
+    const int64_t off = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+    if (off < (int64_t)a.W * a.H) {
+      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+      const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.state_src + off));
+      *reinterpret_cast<u32x4 *>(a.state + off) = v;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.count[j] = 0;
   const int64_t slot = a.emit_off[j];
   if (slot < 0) return;                                 // uniform: not emitted
   const int W = a.W, H = a.H, wpr = a.words_per_row;
@@ -422,8 +436,12 @@ hipError_t launch_motion_emit_scan(const int32_t *count, int64_t n, int64_t thre
 hipError_t launch_motion_emit(const MotionArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   const int64_t halves = 2 * (int64_t)a.H * a.words_per_row;
-  dim3 grid((unsigned)((halves + 255) / 256), (unsigned)a.n);
-  if ((a.W % 32) == 0 && ((int64_t)a.W * a.H) % 16 == 0)
+  const bool fast = (a.W % 32) == 0 && ((int64_t)a.W * a.H) % 16 == 0;
+  // grid row n copies the state: 16 bytes per thread cover the frame when
+  // the width is a multiple of 32 (halves * 16 = W * H)
+  if (a.state_src && !fast) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((halves + 255) / 256), (unsigned)(a.n + (a.state_src ? 1 : 0)));
+  if (fast)
     hipLaunchKernelGGL(k_motion_expand<true>, grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL(k_motion_expand<false>, grid, dim3(256), 0, s, a);

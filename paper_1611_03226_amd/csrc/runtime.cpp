@@ -840,6 +840,8 @@ static df_status fire_motion(df_graph *g, Actor &a, int64_t n, int flags, int64_
         grow((void **)&a.bits, (size_t)(frame_bits * cap)) != hipSuccess)
       return fail(g, DF_ENOMEM, "scratch allocation failed");
     a.cnt_cap = cap;
+    // counts start at zero; every emit pass leaves the ones it used at zero
+    HIPCHK(g, launch_fill_i32(a.count, 0, cap, g->stream));
   }
   for (int64_t done = 0; done < n; done += chunk_max) {
     const int64_t k = std::min(chunk_max, n - done);
@@ -867,16 +869,18 @@ static df_status fire_motion(df_graph *g, Actor &a, int64_t n, int flags, int64_
     ma.H = p.height;
     ma.thr = p.diff_threshold;
     ma.permille = p.min_changed_permille;
-    HIPCHK(g, launch_fill_i32(a.count, 0, k, g->stream));
+    // the batch's last input frame becomes the self-delay state: copied by
+    // the emit pass when the frame is whole 16-byte words per 32-pixel word
+    const bool fast = (p.width % 32) == 0 && wh % 16 == 0;
+    const uint8_t *last_frame = p.self_delay ? (const uint8_t *)fc.ring + ((fc.read_h + k - 1) & fc.mask) * wh : nullptr;
+    ma.state_src = fast ? last_frame : nullptr;
     HIPCHK(g, prof_begin(g, (int)(&a - g->actors.data())));
     HIPCHK(g, launch_motion_count(ma, g->stream));
     HIPCHK(g, launch_motion_emit_scan(a.count, k, (int64_t)p.min_changed_permille * wh, a.emit_off, g->stream));
     HIPCHK(g, launch_motion_emit(ma, g->stream));
     HIPCHK(g, prof_end(g));
-    if (p.self_delay) {
-      const int64_t last = (fc.read_h + k - 1) & fc.mask;
-      HIPCHK(g, hipMemcpyAsync(a.state, fc.ring + last * wh, (size_t)wh, hipMemcpyDeviceToDevice, g->stream));
-    }
+    if (last_frame && !fast)
+      HIPCHK(g, hipMemcpyAsync(a.state, last_frame, (size_t)wh, hipMemcpyDeviceToDevice, g->stream));
     HIPCHK(g, launch_motion_commit(a.emit_off, k, fc.idx, fp ? fp->idx : nullptr, fm.idx, fi.idx, g->err_dev, g->stream));
     fc.read_h += k;
     if (fp) fp->read_h += k;
