@@ -23,22 +23,52 @@ constexpr int kNetThreads = 256;
 // k_mask_tables for mask tokens).
 __device__ inline bool active(int set, int b) { return in_set((uint32_t)set, b); }
 
+// Poly and Adder: a workgroup per (firing, run of 256 V samples of it):
+// the firing, its branch set and its channel offsets are uniform over the
+// workgroup (scalar loads, no per-thread divisions); V = 2 samples per
+// thread (16-byte accesses) when r is even, else 1.
+template <int V>
+__device__ __forceinline__ bool net_sample(const DpdNetArgs &a, int bpf, int64_t *gg, int64_t *i0) {
+  *gg = blockIdx.x / (uint32_t)bpf;
+  *i0 = (int64_t)(blockIdx.x - *gg * bpf) * (kNetThreads * V) + (int64_t)threadIdx.x * V;
+  return *i0 < a.r;
+}
+
+template <int V>
+__device__ __forceinline__ void net_load(const float2 *p, float2 (&v)[V]) {
+  if constexpr (V == 2) {
+    const float4 q = *reinterpret_cast<const float4 *>(p);
+    v[0] = make_float2(q.x, q.y);
+    v[1] = make_float2(q.z, q.w);
+  } else {
+    v[0] = *p;
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void net_store(float2 *p, const float2 (&v)[V]) {
+  if constexpr (V == 2) *reinterpret_cast<float4 *>(p) = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+  else *p = v[0];
+}
+
 // P: for every sample of every firing, psi_b(x) = |x|^(2b) x into channel b
 // at the firing's offset, for b < B of the firing.
-__global__ __launch_bounds__(kNetThreads) void k_net_poly(DpdNetArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * kNetThreads + threadIdx.x;
-  const int64_t row_len = a.nf * a.r, total = a.S * row_len;
-  if (t >= total) return;
-  const int64_t s = t / row_len, rem = t - s * row_len, g = rem / a.r, i = rem - g * a.r;
-  const int64_t gg = s * a.nf + g;
+template <int V>
+__global__ __launch_bounds__(kNetThreads) void k_net_poly(DpdNetArgs a, int bpf) {
+  int64_t gg, i0;
+  if (!net_sample<V>(a, bpf, &gg, &i0)) return;
+  const int64_t row_len = a.nf * a.r, s = gg / a.nf;
   const int Bg = a.B[gg];
-  const float2 x = a.x[t];
-  const float p = fmaf(x.x, x.x, x.y * x.y);
-  float2 v = x;
+  float2 v[V];
+  net_load<V>(a.x + gg * a.r + i0, v);
+  float p[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) p[k] = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
 #pragma unroll
   for (int b = 0; b < kMaxBranches; ++b) {
-    if (b < a.B_max && active(Bg, b)) a.chan[(b * a.S + s) * row_len + a.off[b * a.stride + gg] + i] = v;
-    v = make_float2(v.x * p, v.y * p);
+    if (b < a.B_max && active(Bg, b)) net_store<V>(a.chan + (b * a.S + s) * row_len + a.off[b * a.stride + gg] + i0, v);
+#pragma unroll
+    for (int k = 0; k < V; ++k) v[k] = make_float2(v[k].x * p[k], v[k].y * p[k]);
   }
 }
 
@@ -90,27 +120,31 @@ __global__ __launch_bounds__(kNetThreads) void k_net_fir(DpdNetArgs a) {
 }
 
 // A: y = sum over b < B of FIR_b's output at the firing's offset.
-__global__ __launch_bounds__(kNetThreads) void k_net_add(DpdNetArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * kNetThreads + threadIdx.x;
-  const int64_t row_len = a.nf * a.r, total = a.S * row_len;
-  if (t >= total) return;
-  const int64_t s = t / row_len, rem = t - s * row_len, g = rem / a.r, i = rem - g * a.r;
-  const int64_t gg = s * a.nf + g;
+template <int V>
+__global__ __launch_bounds__(kNetThreads) void k_net_add(DpdNetArgs a, int bpf) {
+  int64_t gg, i0;
+  if (!net_sample<V>(a, bpf, &gg, &i0)) return;
+  const int64_t row_len = a.nf * a.r, s = gg / a.nf;
   const int Bg = a.B[gg];
   // every branch's load is issued before the sums (unrolled, masked)
-  float2 v[kMaxBranches];
+  float2 v[kMaxBranches][V];
 #pragma unroll
   for (int b = 0; b < kMaxBranches; ++b) {
-    v[b] = make_float2(0.f, 0.f);
-    if (b < a.B_max && active(Bg, b)) v[b] = a.firo[(b * a.S + s) * row_len + a.off[b * a.stride + gg] + i];
-  }
-  float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-  for (int b = 0; b < kMaxBranches; ++b) {
-    acc.x += v[b].x;
-    acc.y += v[b].y;
+    for (int k = 0; k < V; ++k) v[b][k] = make_float2(0.f, 0.f);
+    if (b < a.B_max && active(Bg, b)) net_load<V>(a.firo + (b * a.S + s) * row_len + a.off[b * a.stride + gg] + i0, v[b]);
   }
-  a.y[t] = acc;
+  float2 acc[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    acc[k] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int b = 0; b < kMaxBranches; ++b) {
+      acc[k].x += v[b][k].x;
+      acc[k].y += v[b][k].y;
+    }
+  }
+  net_store<V>(a.y + gg * a.r + i0, acc);
 }
 
 // Mask tables: one thread per (row, branch) walks the row's firings in
@@ -144,11 +178,21 @@ hipError_t launch_mask_tables(const int32_t *ctrl, int32_t *B, int64_t *off, con
 hipError_t launch_dpd_network(const DpdNetArgs &a, hipStream_t s, const KTiming *t) {
   const int64_t row_len = a.nf * a.r, total = a.S * row_len;
   if (total <= 0) return hipSuccess;
-  const dim3 g1((unsigned)((total + kNetThreads - 1) / kNetThreads));
-  if (t)
-    hipExtLaunchKernelGGL(k_net_poly, g1, dim3(kNetThreads), 0, s, t->start, nullptr, 0, a);
-  else
-    hipLaunchKernelGGL(k_net_poly, g1, dim3(kNetThreads), 0, s, a);
+  // pairs: r even, and 16-byte aligned sample and output arrays (the
+  // channels are this library's allocations)
+  const bool pair = (a.r % 2) == 0 && ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.y)) & 15) == 0;
+  const int per_block = kNetThreads * (pair ? 2 : 1);
+  const int bpf = (int)((a.r + per_block - 1) / per_block);
+  const int64_t nb = a.S * a.nf * (int64_t)bpf;
+  if (nb > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 g1((unsigned)nb);
+  if (t) {
+    if (pair) hipExtLaunchKernelGGL(k_net_poly<2>, g1, dim3(kNetThreads), 0, s, t->start, nullptr, 0, a, bpf);
+    else hipExtLaunchKernelGGL(k_net_poly<1>, g1, dim3(kNetThreads), 0, s, t->start, nullptr, 0, a, bpf);
+  } else {
+    if (pair) hipLaunchKernelGGL(k_net_poly<2>, g1, dim3(kNetThreads), 0, s, a, bpf);
+    else hipLaunchKernelGGL(k_net_poly<1>, g1, dim3(kNetThreads), 0, s, a, bpf);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 g2((unsigned)((row_len + kFirSpan - 1) / kFirSpan), (unsigned)(a.B_max * a.S));
@@ -157,10 +201,13 @@ hipError_t launch_dpd_network(const DpdNetArgs &a, hipStream_t s, const KTiming 
   else if (a.M == 4) hipLaunchKernelGGL(k_net_fir<4>, g2, dim3(kNetThreads), 0, s, a);
   else hipLaunchKernelGGL(k_net_fir<0>, g2, dim3(kNetThreads), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (t)
-    hipExtLaunchKernelGGL(k_net_add, g1, dim3(kNetThreads), 0, s, nullptr, t->stop, 0, a);
-  else
-    hipLaunchKernelGGL(k_net_add, g1, dim3(kNetThreads), 0, s, a);
+  if (t) {
+    if (pair) hipExtLaunchKernelGGL(k_net_add<2>, g1, dim3(kNetThreads), 0, s, nullptr, t->stop, 0, a, bpf);
+    else hipExtLaunchKernelGGL(k_net_add<1>, g1, dim3(kNetThreads), 0, s, nullptr, t->stop, 0, a, bpf);
+  } else {
+    if (pair) hipLaunchKernelGGL(k_net_add<2>, g1, dim3(kNetThreads), 0, s, a, bpf);
+    else hipLaunchKernelGGL(k_net_add<1>, g1, dim3(kNetThreads), 0, s, a, bpf);
+  }
   return hipGetLastError();
 }
 
