@@ -74,10 +74,10 @@ __global__ __launch_bounds__(kNetThreads) void k_net_poly(DpdNetArgs a, int bpf)
 
 // FIR_b: outputs over the K_b samples channel b received in row s (K_b = r
 // times the number of firings with b < B), zero history before the row's
-// first sample.  A workgroup takes kFirSpan consecutive outputs (four per
+// first sample.  A workgroup takes kFirSpan consecutive outputs (eight per
 // thread) and stages their inputs and the M-1 before them in LDS once (one
 // global load per sample instead of M).
-constexpr int kFirSpan = 4 * kNetThreads;
+constexpr int kFirSpan = 8 * kNetThreads;
 
 // MT: the tap count as a compile-time constant (4, 8, 16: coefficients in
 // registers, taps unrolled), or 0 for any other count.
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kNetThreads) void k_net_fir(DpdNetArgs a) {
   for (int m = 0; m < MT; ++m) hr[m] = hb[m];
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < kFirSpan / kNetThreads; ++j) {
     const int o = j * kNetThreads + threadIdx.x;
     if (t0 + o >= K) break;
     float2 acc = make_float2(0.f, 0.f);
